@@ -1,0 +1,305 @@
+/*
+ * CPU oracle for affine-gap Smith-Waterman (Gotoh) scoring of short reads
+ * against candidate-alignment-location (CAL) windows.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code
+ * with the GPU library and must never be called by the product path.
+ *
+ * What it computes (McVicar et al., "FPGA Acceleration of Short Read
+ * Alignment"):
+ *   - Each read is scored against the reference around each of its CALs with
+ *     Smith-Waterman under the affine gap model (section 3.5).  The paper
+ *     defers the recurrences to an external reference; the ones used here are
+ *     Gotoh's three-state local-alignment recurrences, written in the plain
+ *     full-matrix form:
+ *         E(i,j) = max(E(i,j-1) - ge, H(i,j-1) - go - ge)   gap consuming window base j
+ *         F(i,j) = max(F(i-1,j) - ge, H(i-1,j) - go - ge)   gap consuming read base i
+ *         H(i,j) = max(0, H(i-1,j-1) + s(q_i, w_j), E(i,j), F(i,j))
+ *     with H = 0 and E = F = -infinity on the boundary, so a gap of k bases
+ *     costs go + k*ge.
+ *   - The read is aligned in the direction given by the strand bit kept with
+ *     each CAL (section 3.1): the reverse strand aligns the reverse complement
+ *     of the read (complement = 3 - code with A,C,G,T = 0,1,2,3, Fig. 3)
+ *     against the forward reference window.
+ *   - The Score Tracker keeps the best-scoring CAL per read (sections 3.6, 4.2).
+ *
+ * Readings of points the paper leaves open (each is also listed in the design
+ * notes of the repository):
+ *   - score = the maximum over every cell of H (a full local maximum), not only
+ *     the final row;
+ *   - window = [p - band, p + L + band) clipped to the reference;
+ *   - ties inside a task: highest score, then smallest reference end, then
+ *     smallest read end; score 0 reports both ends as -1;
+ *   - ties across the CALs of a read: lowest slot index (slot 2c forward,
+ *     2c+1 reverse) and the number of tied slots is reported.
+ *
+ * Arithmetic is int64 throughout; the matrices are allocated in full.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define ORACLE_NEG_INF (INT64_MIN / 4)
+
+typedef struct {
+  int32_t match, mismatch, gap_open, gap_extend, band;
+} oracle_scoring_t;
+
+/* Result of one task. */
+typedef struct {
+  int64_t score, ref_end, read_end;
+} oracle_hit_t;
+
+static inline int64_t max2(int64_t a, int64_t b) { return a > b ? a : b; }
+
+/*
+ * Gotoh local alignment of q[0..L) against w[0..W) with full matrices.
+ * buf must hold 3*(L+1)*(W+1) int64 values.  Ends are 0-based; (-1, -1) when
+ * the best score is 0.
+ */
+static oracle_hit_t gotoh_full(const uint8_t *q, int64_t L, const uint8_t *w, int64_t W,
+                               const oracle_scoring_t *sc, int64_t *buf) {
+  const int64_t cols = W + 1;
+  int64_t *H = buf;
+  int64_t *E = buf + (L + 1) * cols;
+  int64_t *F = buf + 2 * (L + 1) * cols;
+  const int64_t go = sc->gap_open, ge = sc->gap_extend;
+#define AT(M, i, j) M[(i) * cols + (j)]
+  for (int64_t j = 0; j <= W; ++j) {
+    AT(H, 0, j) = 0;
+    AT(E, 0, j) = ORACLE_NEG_INF;
+    AT(F, 0, j) = ORACLE_NEG_INF;
+  }
+  for (int64_t i = 1; i <= L; ++i) {
+    AT(H, i, 0) = 0;
+    AT(E, i, 0) = ORACLE_NEG_INF;
+    AT(F, i, 0) = ORACLE_NEG_INF;
+    for (int64_t j = 1; j <= W; ++j) {
+      int64_t s = (q[i - 1] == w[j - 1]) ? sc->match : sc->mismatch;
+      AT(E, i, j) = max2(AT(E, i, j - 1) - ge, AT(H, i, j - 1) - go - ge);
+      AT(F, i, j) = max2(AT(F, i - 1, j) - ge, AT(H, i - 1, j) - go - ge);
+      int64_t h = AT(H, i - 1, j - 1) + s;
+      h = max2(h, AT(E, i, j));
+      h = max2(h, AT(F, i, j));
+      AT(H, i, j) = max2(h, 0);
+    }
+  }
+  /* best cell: highest score, then smallest window column, then smallest read row */
+  oracle_hit_t best = {0, -1, -1};
+  for (int64_t j = 1; j <= W; ++j) {
+    for (int64_t i = 1; i <= L; ++i) {
+      int64_t v = AT(H, i, j);
+      if (v > best.score) {
+        best.score = v;
+        best.ref_end = j - 1;
+        best.read_end = i - 1;
+      }
+    }
+  }
+#undef AT
+  return best;
+}
+
+/* Single pair, exposed for the brute-force and invariant tests. */
+void oracle_gotoh_many(const uint8_t *q_codes, const int64_t *q_off, const int64_t *q_len,
+                       const uint8_t *w_codes, const int64_t *w_off, const int64_t *w_len,
+                       int64_t n, const oracle_scoring_t *sc, int64_t *score, int64_t *ref_end,
+                       int64_t *read_end) {
+  int64_t cap = 0;
+  int64_t *buf = NULL;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t need = 3 * (q_len[k] + 1) * (w_len[k] + 1);
+    if (need > cap) {
+      free(buf);
+      cap = need;
+      buf = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    }
+    oracle_hit_t h = gotoh_full(q_codes + q_off[k], q_len[k], w_codes + w_off[k], w_len[k], sc, buf);
+    score[k] = h.score;
+    ref_end[k] = h.ref_end;
+    read_end[k] = h.read_end;
+  }
+  free(buf);
+}
+
+/* ---------------------------------------------------------------- batch */
+
+typedef struct {
+  const uint8_t *read_codes;
+  const int64_t *read_off;
+  const int32_t *read_len;
+  int32_t n_reads;
+  const uint8_t *ref_codes;
+  const int64_t *ref_off;
+  const int64_t *ref_len;
+  int32_t n_refs;
+  const int64_t *cal_ptr;
+  const int64_t *cal_read; /* owning read of each CAL */
+  const int64_t *cal_pos;
+  const int16_t *cal_ref;
+  const uint8_t *strand;
+  int64_t n_cals;
+  oracle_scoring_t sc;
+  int32_t max_read_len;
+  int32_t *score;
+  int64_t *ref_end;
+  int16_t *read_end;
+  int64_t begin, end; /* CAL range of this worker */
+  int64_t errors;
+} batch_job_t;
+
+static void *batch_worker(void *arg) {
+  batch_job_t *jb = (batch_job_t *)arg;
+  int64_t cap = 0;
+  int64_t *buf = NULL;
+  uint8_t *qbuf = (uint8_t *)malloc((size_t)jb->max_read_len + 1);
+  for (int64_t c = jb->begin; c < jb->end; ++c) {
+    int64_t r = jb->cal_read[c];
+    int64_t L = jb->read_len[r];
+    int64_t k = jb->cal_ref[c];
+    int64_t p = jb->cal_pos[c];
+    uint8_t mask = jb->strand[c];
+    int valid = (k >= 0 && k < jb->n_refs && L >= 1 && L <= jb->max_read_len);
+    if (valid) valid = (p >= 0 && p < jb->ref_len[k]);
+    for (int h = 0; h < 2; ++h) {
+      int64_t slot = 2 * c + h;
+      jb->score[slot] = -1;
+      jb->ref_end[slot] = -1;
+      jb->read_end[slot] = -1;
+      if (!(mask & (1 << h))) continue;
+      if (!valid) {
+        jb->score[slot] = INT32_MIN;
+        jb->errors++;
+        continue;
+      }
+      const uint8_t *read = jb->read_codes + jb->read_off[r];
+      /* oriented read: forward as given, reverse = reverse complement */
+      for (int64_t i = 0; i < L; ++i) qbuf[i] = h == 0 ? read[i] : (uint8_t)(3 - read[L - 1 - i]);
+      int64_t ws = p - jb->sc.band;
+      if (ws < 0) ws = 0;
+      int64_t we = p + L + jb->sc.band;
+      if (we > jb->ref_len[k]) we = jb->ref_len[k];
+      int64_t W = we - ws;
+      int64_t need = 3 * (L + 1) * (W + 1);
+      if (need > cap) {
+        free(buf);
+        cap = need;
+        buf = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+      }
+      oracle_hit_t hit = gotoh_full(qbuf, L, jb->ref_codes + jb->ref_off[k] + ws, W, &jb->sc, buf);
+      jb->score[slot] = (int32_t)hit.score;
+      if (hit.score > 0) {
+        jb->ref_end[slot] = ws + hit.ref_end;
+        jb->read_end[slot] = (int16_t)hit.read_end;
+      }
+    }
+  }
+  free(buf);
+  free(qbuf);
+  return NULL;
+}
+
+/*
+ * Score every requested (CAL, strand) slot.  Outputs have 2*n_cals entries:
+ * slot 2c forward, 2c+1 reverse.  Unrequested slots: score -1; invalid tasks
+ * (reference id, position or read length out of range): score INT32_MIN.
+ * Returns the number of invalid task slots.
+ */
+int64_t oracle_align_batch(const uint8_t *read_codes, const int64_t *read_off, const int32_t *read_len,
+                           int32_t n_reads, const uint8_t *ref_codes, const int64_t *ref_off,
+                           const int64_t *ref_len, int32_t n_refs, const int64_t *cal_ptr,
+                           const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand,
+                           int64_t n_cals, const oracle_scoring_t *sc, int32_t max_read_len,
+                           int32_t *score, int64_t *ref_end, int16_t *read_end, int32_t n_threads) {
+  int64_t *cal_read = (int64_t *)malloc((size_t)(n_cals > 0 ? n_cals : 1) * sizeof(int64_t));
+  for (int64_t r = 0; r < n_reads; ++r)
+    for (int64_t c = cal_ptr[r]; c < cal_ptr[r + 1]; ++c) cal_read[c] = r;
+  if (n_threads < 1) n_threads = 1;
+  batch_job_t *jobs = (batch_job_t *)calloc((size_t)n_threads, sizeof(batch_job_t));
+  pthread_t *tids = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+  for (int t = 0; t < n_threads; ++t) {
+    batch_job_t *jb = &jobs[t];
+    jb->read_codes = read_codes; jb->read_off = read_off; jb->read_len = read_len;
+    jb->n_reads = n_reads; jb->ref_codes = ref_codes; jb->ref_off = ref_off;
+    jb->ref_len = ref_len; jb->n_refs = n_refs; jb->cal_ptr = cal_ptr; jb->cal_read = cal_read;
+    jb->cal_pos = cal_pos; jb->cal_ref = cal_ref; jb->strand = strand; jb->n_cals = n_cals;
+    jb->sc = *sc; jb->max_read_len = max_read_len; jb->score = score; jb->ref_end = ref_end;
+    jb->read_end = read_end;
+    jb->begin = n_cals * t / n_threads;
+    jb->end = n_cals * (t + 1) / n_threads;
+  }
+  if (n_threads == 1) {
+    batch_worker(&jobs[0]);
+  } else {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&tids[t], NULL, batch_worker, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(tids[t], NULL);
+  }
+  int64_t errors = 0;
+  for (int t = 0; t < n_threads; ++t) errors += jobs[t].errors;
+  free(jobs);
+  free(tids);
+  free(cal_read);
+  return errors;
+}
+
+/*
+ * Best slot per (read, reference): highest score, lowest slot index among ties,
+ * and the number of slots tied at that score.  Unrequested and invalid slots
+ * (negative scores) are skipped.  A pair with no valid slot reports
+ * (-1, -1, 0).  Outputs are [n_reads * n_refs], row-major by read.
+ */
+void oracle_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
+                        const int32_t *score, int32_t *best_score, int64_t *best_slot, int32_t *n_tied) {
+  for (int64_t r = 0; r < n_reads; ++r) {
+    for (int64_t k = 0; k < n_refs; ++k) {
+      best_score[r * n_refs + k] = -1;
+      best_slot[r * n_refs + k] = -1;
+      n_tied[r * n_refs + k] = 0;
+    }
+    for (int64_t c = cal_ptr[r]; c < cal_ptr[r + 1]; ++c) {
+      int64_t k = cal_ref[c];
+      if (k < 0 || k >= n_refs) continue;
+      for (int h = 0; h < 2; ++h) {
+        int64_t slot = 2 * c + h;
+        int32_t s = score[slot];
+        if (s < 0) continue;
+        int64_t o = r * n_refs + k;
+        if (s > best_score[o]) {
+          best_score[o] = s;
+          best_slot[o] = slot;
+          n_tied[o] = 1;
+        } else if (s == best_score[o]) {
+          n_tied[o] += 1;
+        }
+      }
+    }
+  }
+}
+
+/*
+ * Two-or-more-reference classification (section 6.2): a read belongs to the
+ * reference with the strictly highest best score if that score reaches the
+ * threshold; -2 when two or more references share a top score that reaches
+ * it (tie); -1 when no reference reaches it (unaligned).
+ */
+void oracle_classify(const int32_t *best_score, int32_t n_reads, int32_t n_refs, int32_t threshold,
+                     int32_t *cls) {
+  for (int64_t r = 0; r < n_reads; ++r) {
+    int32_t top = -1, arg = -1, count = 0;
+    for (int32_t k = 0; k < n_refs; ++k) {
+      int32_t v = best_score[r * n_refs + k];
+      if (v > top) {
+        top = v;
+        arg = k;
+        count = 1;
+      } else if (v == top) {
+        count++;
+      }
+    }
+    if (top < threshold) cls[r] = -1;
+    else if (count > 1) cls[r] = -2;
+    else cls[r] = arg;
+  }
+}

@@ -1,0 +1,322 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+* brute-force enumeration of every local alignment (exhaustive on tiny inputs,
+  random samples up to 6 x 8), several scoring schemes;
+* closed forms of planted edits at the paper's 76 bp read length (section 3.3);
+* invariants (bounds, symmetry under swapping, reversal, complement, reverse
+  complement, window extension);
+* special cases reducing to textbook problems: linear-gap Smith-Waterman
+  (gap_open = 0) and the longest common substring (prohibitive penalties);
+* the paper's worked examples: the 2-bit code of Fig. 3 and the reverse
+  complement example of section 3.1 (fixtures under tests/golden/).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import oracle as o
+from paper_1805_00106_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+SCORINGS = [
+    dict(match=2, mismatch=-3, gap_open=5, gap_extend=2),   # the workloads' scoring
+    dict(match=1, mismatch=0, gap_open=0, gap_extend=1),    # mismatch 0, linear gaps
+    dict(match=3, mismatch=-1, gap_open=1, gap_extend=1),   # cheap gaps: gap paths win often
+    dict(match=1, mismatch=-2, gap_open=2, gap_extend=1),
+]
+
+
+def _golden_lines(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.strip() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+# ------------------------------------------------------------------ paper examples
+
+def test_fig3_two_bit_code():
+    seed, printed = _golden_lines("fig3_seed2.txt")
+    bits = o.bits_msb_first(o.encode(seed))
+    assert len(bits) == 2 * len(seed) == 44
+    assert len(printed) == 43
+    # the printed string is the encoding with exactly one '1' lost inside the run of ones
+    drops = [i for i in range(len(bits)) if bits[:i] + bits[i + 1:] == printed]
+    assert drops, "printed bits are not the A,C,G,T = 00,01,10,11 encoding minus one bit"
+    run = bits[drops[0]:drops[-1] + 1]
+    assert set(run) == {"1"}
+    # any other code order fails the same check
+    for perm in ("ACTG", "AGCT", "CAGT", "TGCA"):
+        alt = "".join(format(perm.index(ch), "02b") for ch in seed)
+        assert not any(alt[:i] + alt[i + 1:] == printed for i in range(len(alt)))
+
+
+def test_reverse_complement_example():
+    (line,) = _golden_lines("rc_example.txt")
+    fwd, rc = line.split()
+    assert o.decode(o.reverse_complement(o.encode(fwd))) == rc
+
+
+# ------------------------------------------------------------------ brute force
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 4), (2, 2), (2, 4), (3, 3), (3, 4), (4, 4), (3, 5)])
+def test_exhaustive_brute_force(m, n):
+    Q, W, s, r, e = brute.exhaustive(m, n)
+    os_, or_, oe = o.gotoh_pairs(list(Q), list(W))
+    np.testing.assert_array_equal(os_, s)
+    np.testing.assert_array_equal(or_, r)
+    np.testing.assert_array_equal(oe, e)
+
+
+@pytest.mark.parametrize("sc", SCORINGS[1:])
+@pytest.mark.parametrize("m,n", [(2, 3), (3, 4)])
+def test_exhaustive_other_scorings(sc, m, n):
+    Q, W, s, r, e = brute.exhaustive(m, n, **sc)
+    os_, or_, oe = o.gotoh_pairs(list(Q), list(W), **sc)
+    np.testing.assert_array_equal(os_, s)
+    np.testing.assert_array_equal(or_, r)
+    np.testing.assert_array_equal(oe, e)
+
+
+@pytest.mark.parametrize("sc", SCORINGS)
+@pytest.mark.parametrize("m,n,N", [(5, 7, 150), (6, 8, 60), (8, 5, 60)])
+def test_random_brute_force(sc, m, n, N):
+    rng = np.random.default_rng(1000 * m + n)
+    Q = rng.integers(0, 4, (N, m)).astype(np.uint8)
+    W = rng.integers(0, 4, (N, n)).astype(np.uint8)
+    # half of the pairs get a planted near-copy so long gapped alignments occur
+    for k in range(0, N, 2):
+        src = W[k].copy()
+        cut = rng.integers(0, len(src))
+        cand = np.delete(src, cut) if rng.random() < 0.5 else np.insert(src, cut, rng.integers(0, 4))
+        Q[k, :] = np.resize(cand, m)
+    s, r, e = brute.local_batch(Q, W, **sc)
+    os_, or_, oe = o.gotoh_pairs(list(Q), list(W), **sc)
+    np.testing.assert_array_equal(os_, s)
+    np.testing.assert_array_equal(or_, r)
+    np.testing.assert_array_equal(oe, e)
+
+
+# ------------------------------------------------------------------ closed forms, L = 76
+
+def _base_ref(seed=7, n=220):
+    return wl.uniform_genome(np.random.default_rng(seed), n)
+
+
+def test_closed_form_exact_match():
+    ref = _base_ref()
+    read = ref[50:126]
+    assert o.gotoh(read, ref) == (2 * 76, 125, 75)
+
+
+def test_closed_form_one_mismatch():
+    ref = _base_ref()
+    read = ref[50:126].copy()
+    read[38] = (read[38] + 1) % 4
+    assert o.gotoh(read, ref) == (2 * 76 - 5, 125, 75)   # 75 matches + 1 mismatch = 147
+
+
+def test_closed_form_one_base_deletion():
+    ref = _base_ref()
+    read = np.concatenate([ref[50:88], ref[89:127]])       # read lacks reference base 88
+    assert len(read) == 76
+    assert o.gotoh(read, ref) == (2 * 76 - 7, 126, 75)     # 76 matches, one 1-base gap = 145
+
+
+def test_closed_form_one_base_insertion():
+    ref = _base_ref()
+    extra = np.array([(ref[88] + 2) % 4], np.uint8)
+    read = np.concatenate([ref[50:88], extra, ref[88:125]])
+    assert len(read) == 76
+    assert o.gotoh(read, ref) == (2 * 75 - 7, 124, 75)     # 75 matches, one 1-base gap = 143
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 10])
+def test_closed_form_k_base_deletion(k):
+    ref = _base_ref(11, 260)
+    read = np.concatenate([ref[50:88], ref[88 + k:126 + k]])
+    assert len(read) == 76
+    assert o.gotoh(read, ref) == (2 * 76 - (5 + 2 * k), 125 + k, 75)
+
+
+# ------------------------------------------------------------------ invariants
+
+def _pairs(seed, n=120, lq=(1, 40), lw=(1, 60)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        q = rng.integers(0, 4, rng.integers(lq[0], lq[1] + 1)).astype(np.uint8)
+        w = rng.integers(0, 4, rng.integers(lw[0], lw[1] + 1)).astype(np.uint8)
+        if rng.random() < 0.5 and len(w) > 4:
+            a = rng.integers(0, len(w) - 2)
+            b = rng.integers(a + 1, len(w) + 1)
+            q = wl._substitute(rng, w[a:b].copy(), 0.1)
+        out.append((q, w))
+    return out
+
+
+def test_score_bounds_and_swap_symmetry():
+    P = _pairs(1)
+    qs, ws = zip(*P)
+    s, r, e = o.gotoh_pairs(list(qs), list(ws))
+    s2, r2, e2 = o.gotoh_pairs(list(ws), list(qs))
+    for k, (q, w) in enumerate(P):
+        assert 0 <= s[k] <= 2 * min(len(q), len(w))
+        assert (s[k] == 0) == (r[k] == -1) == (e[k] == -1)
+    np.testing.assert_array_equal(s, s2)
+
+
+def test_reverse_and_complement_invariance():
+    P = _pairs(2)
+    qs, ws = zip(*P)
+    s, r, e = o.gotoh_pairs(list(qs), list(ws))
+    sr, _, _ = o.gotoh_pairs([q[::-1].copy() for q in qs], [w[::-1].copy() for w in ws])
+    sc, rc_, ec = o.gotoh_pairs([(3 - q).astype(np.uint8) for q in qs], [(3 - w).astype(np.uint8) for w in ws])
+    np.testing.assert_array_equal(s, sr)
+    np.testing.assert_array_equal(s, sc)
+    np.testing.assert_array_equal(r, rc_)      # complement keeps equality pattern, so ends too
+    np.testing.assert_array_equal(e, ec)
+
+
+def test_reverse_complement_symmetry():
+    P = _pairs(3)
+    qs, ws = zip(*P)
+    a, _, _ = o.gotoh_pairs([o.reverse_complement(q) for q in qs], list(ws))
+    b, _, _ = o.gotoh_pairs(list(qs), [o.reverse_complement(w) for w in ws])
+    np.testing.assert_array_equal(a, b)
+
+
+def test_window_extension_never_lowers_score():
+    rng = np.random.default_rng(4)
+    for q, w in _pairs(4, n=60, lw=(10, 60)):
+        a = int(rng.integers(0, len(w) // 2))
+        b = int(rng.integers(a + 1, len(w) + 1))
+        inner = o.gotoh(q, w[a:b])[0]
+        outer = o.gotoh(q, w)[0]
+        assert inner <= outer
+
+
+# ------------------------------------------------------------------ textbook special cases
+
+def _linear_sw(q, w, match, mismatch, gap):
+    """Textbook single-state Smith-Waterman with linear gaps (cost gap per base)."""
+    L, W = len(q), len(w)
+    H = [[0] * (W + 1) for _ in range(L + 1)]
+    best = (0, -1, -1)
+    for i in range(1, L + 1):
+        for j in range(1, W + 1):
+            d = H[i - 1][j - 1] + (match if q[i - 1] == w[j - 1] else mismatch)
+            H[i][j] = max(0, d, H[i - 1][j] - gap, H[i][j - 1] - gap)
+    for j in range(1, W + 1):
+        for i in range(1, L + 1):
+            if H[i][j] > best[0]:
+                best = (H[i][j], j - 1, i - 1)
+    return best
+
+
+@pytest.mark.parametrize("gap", [1, 2, 4])
+def test_gap_open_zero_is_linear_gap_smith_waterman(gap):
+    for q, w in _pairs(5 + gap, n=50, lq=(1, 25), lw=(1, 35)):
+        got = o.gotoh(q, w, match=2, mismatch=-3, gap_open=0, gap_extend=gap)
+        assert got == _linear_sw(list(q), list(w), 2, -3, gap)
+
+
+def test_prohibitive_penalties_give_longest_common_substring():
+    for q, w in _pairs(6, n=80, lq=(1, 20), lw=(1, 30)):
+        got = o.gotoh(q, w, match=1, mismatch=-1000, gap_open=1000, gap_extend=1000)
+        assert got == brute.longest_common_substring(q, w)
+
+
+# ------------------------------------------------------------------ batch semantics
+
+def _expected_slot(batch, c, h, read_of):
+    """Per-slot expectation built in the test: orientation and clipped window, then the
+    (brute-force pinned) pairwise oracle."""
+    sc = batch.scoring
+    r = read_of[c]
+    k = int(batch.cal_ref[c])
+    p = int(batch.cal_pos[c])
+    if not (int(batch.strand[c]) >> h) & 1:
+        return (-1, -1, -1)
+    if k < 0 or k >= batch.n_refs or p < 0 or p >= batch.ref_len[k]:
+        return (np.iinfo(np.int32).min, -1, -1)
+    read = batch.read(r)
+    L = len(read)
+    q = read if h == 0 else np.array([3 - read[L - 1 - i] for i in range(L)], np.uint8)
+    ws = max(0, p - sc.band)
+    we = min(int(batch.ref_len[k]), p + L + sc.band)
+    s, re, qe = o.gotoh(q, batch.reference(k)[ws:we], match=sc.match, mismatch=sc.mismatch,
+                        gap_open=sc.gap_open, gap_extend=sc.gap_extend)
+    return (s, ws + re if s > 0 else -1, qe if s > 0 else -1)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_batch_orientation_windows_and_slots(seed):
+    b = wl.random_small_batch(seed, n_reads=40, read_len=(1, 50), band=6)
+    read_of = np.repeat(np.arange(b.n_reads), np.diff(b.cal_ptr))
+    score, ref_end, read_end, errs = o.align_batch(b, n_threads=2)
+    assert errs == 0
+    for c in range(b.n_cals):
+        for h in range(2):
+            exp = _expected_slot(b, c, h, read_of)
+            assert (score[2 * c + h], ref_end[2 * c + h], read_end[2 * c + h]) == exp
+
+
+def test_batch_invalid_cals_are_flagged():
+    b = wl.random_small_batch(5, n_reads=10, max_cals=3)
+    b.cal_pos = b.cal_pos.copy()
+    b.cal_ref = b.cal_ref.copy()
+    assert b.n_cals >= 3
+    b.cal_pos[0] = b.ref_len[int(b.cal_ref[0])]     # one past the end
+    b.cal_ref[1] = b.n_refs                           # unknown reference
+    b.cal_pos[2] = -1
+    score, _, _, errs = o.align_batch(b)
+    req = sum(bin(int(b.strand[c])).count("1") for c in range(3))
+    assert errs == req
+    for c in range(3):
+        for h in range(2):
+            expected = np.iinfo(np.int32).min if (int(b.strand[c]) >> h) & 1 else -1
+            assert score[2 * c + h] == expected
+
+
+def test_reduce_best_and_classify_definitions():
+    b = wl.random_small_batch(7, n_reads=60, max_cals=6, n_refs=3)
+    score, _, _, _ = o.align_batch(b)
+    bs, bl, nt = o.reduce_best(b.cal_ptr, b.cal_ref, b.n_reads, b.n_refs, score)
+    for r in range(b.n_reads):
+        for k in range(b.n_refs):
+            slots = [(int(score[s]), s) for c in range(b.cal_ptr[r], b.cal_ptr[r + 1])
+                     if int(b.cal_ref[c]) == k for s in (2 * c, 2 * c + 1) if score[s] >= 0]
+            if not slots:
+                assert (bs[r, k], bl[r, k], nt[r, k]) == (-1, -1, 0)
+                continue
+            slots.sort(key=lambda t: (-t[0], t[1]))
+            top = slots[0][0]
+            assert (bs[r, k], bl[r, k], nt[r, k]) == (top, slots[0][1], sum(1 for t in slots if t[0] == top))
+    for T in (0, 10, 30):
+        cls = o.classify(bs, T)
+        for r in range(b.n_reads):
+            row = list(bs[r])
+            top = max(row)
+            if top < T:
+                assert cls[r] == -1
+            elif row.count(top) > 1:
+                assert cls[r] == -2
+            else:
+                assert cls[r] == row.index(top)
+
+
+def test_planted_error_free_reads_recover_their_locus():
+    rng = np.random.default_rng(9)
+    genome = wl.uniform_genome(rng, 5000)
+    lens = np.full(30, 76, np.int64)
+    reads, pos, rev = wl._sample_reads(rng, rng, genome, lens, 0.0, 0.0)
+    cals = [[(int(p), 0, 2 if v else 1)] for p, v in zip(pos, rev)]
+    b = wl._pack_batch([genome], reads, cals, wl.Scoring(), None, None, None, "planted")
+    score, ref_end, read_end, _ = o.align_batch(b)
+    for r in range(30):
+        slot = 2 * r + (1 if rev[r] else 0)
+        assert score[slot] == 2 * 76
+        assert ref_end[slot] == pos[r] + 75
+        assert read_end[slot] == 75
