@@ -1,0 +1,210 @@
+/*
+ * sw_align.h - C ABI of the MI355X (gfx950) affine-gap Smith-Waterman CAL scorer.
+ *
+ * The library scores short reads against the reference window around each of
+ * their candidate alignment locations (CALs), on one or both strands, and
+ * reports the best local-alignment score and its end cell per (CAL, strand),
+ * then the best per (read, reference).  This is the scoring stage of the
+ * aligner described in McVicar et al., "FPGA Acceleration of Short Read
+ * Alignment": reads with their CALs go to Smith-Waterman units under the affine
+ * gap model (sections 3.5 and 4.2), each CAL carries a strand bit and the
+ * reverse strand is aligned as the reverse complement (section 3.1), and a
+ * Score Tracker keeps the best CAL per read (sections 3.6 and 4.2).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments marked "device" are device pointers owned by the caller;
+ *     arrays marked "host" are host pointers read before the call returns.  The
+ *     library never frees or retains caller memory.
+ *   - GPU work is enqueued on `stream` (0 = the null stream) and is
+ *     asynchronous; outputs are valid once the stream reaches that point.
+ *   - Host-visible arguments are validated before any HIP call; on a
+ *     validation error nothing is enqueued.  Functions return SW_OK (0) or a
+ *     negative SW_ERR_* code; sw_strerror() names it.  No C++ exception crosses
+ *     the ABI.
+ *   - Bases are 2-bit codes A=0, C=1, G=2, T=3 (the code of the paper's index
+ *     figure, section 3.1, Fig. 3).  Packed sequences store base i of a
+ *     sequence at bits [2*(i%16), 2*(i%16)+2) of 32-bit word i/16 (least
+ *     significant first); every sequence starts on a word boundary.
+ *
+ * Scoring (affine gaps, section 3.5): a pair of equal bases scores `match`,
+ * a pair of different bases `mismatch`, and a run of k consecutive read-only or
+ * window-only columns costs gap_open + k*gap_extend.  The score of a task is
+ * the maximum over all local alignments (the empty one scores 0).  Among the
+ * cells reaching it the reported end is the smallest reference position, then
+ * the smallest read position; a score of 0 reports both ends as -1.
+ */
+#ifndef SW_ALIGN_H
+#define SW_ALIGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *sw_stream_t; /* a hipStream_t */
+
+/* ------------------------------------------------------------------ codes */
+#define SW_OK 0
+#define SW_ERR_INVALID_ARG (-1)   /* null pointer, negative count, bad enum */
+#define SW_ERR_SCORING (-2)       /* scoring parameters outside the supported range */
+#define SW_ERR_READ_TOO_LONG (-3) /* max_read_len above SW_MAX_READ_LEN */
+#define SW_ERR_BOUND (-4)         /* int16 requested but the score bound does not hold */
+#define SW_ERR_WORKSPACE (-5)     /* workspace missing or smaller than sw_workspace_bytes() */
+#define SW_ERR_NOMEM (-6)         /* device or host allocation failed */
+#define SW_ERR_HIP (-7)           /* a HIP call failed; sw_last_hip_error() has the code */
+#define SW_ERR_TOO_MANY_REFS (-8) /* more than SW_MAX_REFS references */
+#define SW_ERR_REJECTED (-9)      /* served request larger than the memory budget */
+#define SW_ERR_STATE (-10)        /* object used in the wrong state (e.g. no references set) */
+
+#define SW_MAX_READ_LEN 1024 /* longest read accepted */
+#define SW_MAX_REFS 64       /* references per reference set */
+#define SW_MAX_BAND 1024     /* widest band accepted */
+
+/* precision of the dynamic-programming values inside the kernels */
+#define SW_PREC_AUTO 0  /* int16 pairs when the bound holds, else int32 */
+#define SW_PREC_INT16 1 /* error SW_ERR_BOUND if the bound does not hold */
+#define SW_PREC_INT32 2
+
+/* kernel family */
+#define SW_KERNEL_AUTO 0  /* inter-task unless the window is too wide for it */
+#define SW_KERNEL_INTER 1 /* one CAL per lane (both strands in one lane) */
+#define SW_KERNEL_INTRA 2 /* one wavefront per CAL, lanes hold window columns */
+
+/* strand mask bits of a CAL (section 3.1: a strand bit is kept with each CAL) */
+#define SW_STRAND_FWD 1
+#define SW_STRAND_REV 2
+
+typedef struct {
+  int32_t match;        /* >= 1 */
+  int32_t mismatch;     /* <= 0 */
+  int32_t gap_open;     /* >= 0 */
+  int32_t gap_extend;   /* >= 1 */
+  int32_t band;         /* window = [p - band, p + L + band) clipped to the reference; 0..SW_MAX_BAND */
+  int32_t precision;    /* SW_PREC_* */
+  int32_t kernel;       /* SW_KERNEL_* */
+  int32_t max_read_len; /* upper bound on every read length of the call, 1..SW_MAX_READ_LEN
+                           (0 means SW_MAX_READ_LEN); reads above it are flagged as errors */
+} sw_scoring_t;
+
+/* References resident in device memory (the paper keeps the whole 2-bit
+ * reference in accelerator memory, sections 4.3 and 5.1). */
+typedef struct {
+  const uint32_t *words;       /* device: all references packed back to back */
+  const int64_t *word_offset;  /* host [n_refs]: first word of each reference */
+  const int64_t *length;       /* host [n_refs]: length in bases (>= 1) */
+  int32_t n_refs;              /* 1..SW_MAX_REFS */
+} sw_refset_t;
+
+/* ------------------------------------------------------------------ packing */
+/*
+ * Pack `n` base codes (device uint8, values 0..3; only the low 2 bits are
+ * used) into ceil(n/16) words (device uint32).  Packing each sequence at a
+ * 16-aligned code offset gives word-aligned sequences (section 3.7: 0.25
+ * bytes per base).
+ */
+int sw_pack_2bit(const uint8_t *codes, int64_t n, uint32_t *words, sw_stream_t stream);
+
+/* ------------------------------------------------------------------ scoring */
+/*
+ * Score every requested (CAL, strand) task.
+ *   reads2bit      device: packed reads
+ *   read_word_off  device [n_reads]: first word of each read
+ *   read_len       device [n_reads]: length in bases, 1..max_read_len
+ *   cal_ptr        device [n_reads+1]: CSR row pointer, cal_ptr[0] = 0,
+ *                  cal_ptr[n_reads] = n_cals; CALs of read r are
+ *                  [cal_ptr[r], cal_ptr[r+1])
+ *   cal_pos        device [n_cals]: forward reference position of base 0 of the
+ *                  oriented read (the CAL), 0 <= p < reference length
+ *   cal_ref        device [n_cals]: reference id
+ *   strand         device [n_cals]: mask of SW_STRAND_FWD | SW_STRAND_REV
+ * Outputs, device [2*n_cals], slot 2c = forward, 2c+1 = reverse:
+ *   score          best score; -1 if the strand was not requested; INT32_MIN if
+ *                  the task is invalid (reference id, position or read length
+ *                  out of range, or CAL not covered by cal_ptr)
+ *   ref_end        absolute forward reference position of the end cell, -1 if
+ *                  score <= 0
+ *   read_end       position in the oriented read (reverse strand = reverse
+ *                  complement of the read), -1 if score <= 0
+ * The reverse strand aligns the reverse complement of the read against the same
+ * forward window (section 3.1).  `workspace` (device, >= workspace_bytes) must
+ * hold sw_workspace_bytes(n_reads, n_cals, sc) bytes and must not be used by
+ * another call that overlaps on the device.  The number of invalid tasks is
+ * added to the counter read by sw_error_count().
+ */
+int sw_align_batch(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
+                   int32_t n_reads, const sw_refset_t *refs, const int64_t *cal_ptr,
+                   const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand,
+                   int64_t n_cals, const sw_scoring_t *sc, int32_t *score, int64_t *ref_end,
+                   int16_t *read_end, void *workspace, size_t workspace_bytes, sw_stream_t stream);
+
+/* Workspace size for sw_align_batch (0 is never returned for n_cals > 0). */
+size_t sw_workspace_bytes(int32_t n_reads, int64_t n_cals, const sw_scoring_t *sc);
+
+/* Invalid task slots seen by sw_align_batch on this device since load (or the
+ * last reset).  Synchronises the device. */
+int sw_error_count(int64_t *n_invalid, int reset);
+
+/*
+ * Score Tracker (sections 3.6 and 4.2): best slot per (read, reference).
+ *   best_score  device [n_reads*n_refs] highest score among valid slots (-1 if none)
+ *   best_slot   device [n_reads*n_refs] lowest slot index reaching it (-1 if none)
+ *   n_tied      device [n_reads*n_refs] number of slots reaching it (0 if none)
+ * Slots with negative scores (not requested, invalid) are skipped; CALs whose
+ * reference id is outside [0, n_refs) are skipped.
+ */
+int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
+                   const int32_t *score, int32_t *best_score, int64_t *best_slot, int32_t *n_tied,
+                   sw_stream_t stream);
+
+/*
+ * Classification of reads between references by best score (section 6.2,
+ * xenograft case study): cls[r] = the reference with the strictly highest best
+ * score if it is >= threshold, -2 if two or more references share a top score
+ * >= threshold (tie), -1 if no reference reaches the threshold (unaligned).
+ */
+int sw_classify(const int32_t *best_score, int32_t n_reads, int32_t n_refs, int32_t threshold,
+                int32_t *cls, sw_stream_t stream);
+
+/* ------------------------------------------------------------------ batched */
+/*
+ * A context holds device buffers sized once for a batch capacity, an autotuned
+ * launch plan and captured HIP graphs.  sw_align_batch_ctx has the semantics of
+ * sw_align_batch (bit-identical outputs) but bins tasks by read length and
+ * window width, feeds a persistent kernel from a device work queue ordered
+ * longest-first, and replays a captured graph when the shape repeats.
+ * A context is not thread-safe: use one per host thread.
+ */
+typedef struct sw_ctx sw_ctx_t;
+
+typedef struct {
+  int32_t device;         /* HIP device ordinal */
+  int32_t max_reads;      /* capacity: reads per call */
+  int64_t max_cals;       /* capacity: CALs per call */
+  int32_t use_graph;      /* 1: capture and replay HIP graphs per shape */
+  int32_t autotune;       /* 1: time candidate plans on first use of a shape class */
+  const char *tune_cache; /* optional JSON file for autotune results (may be NULL) */
+} sw_ctx_opts_t;
+
+int sw_ctx_create(const sw_ctx_opts_t *opts, sw_ctx_t **out);
+int sw_ctx_destroy(sw_ctx_t *ctx);
+int sw_align_batch_ctx(sw_ctx_t *ctx, const uint32_t *reads2bit, const int64_t *read_word_off,
+                       const int32_t *read_len, int32_t n_reads, const sw_refset_t *refs,
+                       const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref,
+                       const uint8_t *strand, int64_t n_cals, const sw_scoring_t *sc, int32_t *score,
+                       int64_t *ref_end, int16_t *read_end, sw_stream_t stream);
+/* Invalid task slots seen by this context; synchronises the context's device. */
+int sw_ctx_error_count(sw_ctx_t *ctx, int64_t *n_invalid);
+/* Text description of the last plan used (bins, tiles, kernel variants). */
+const char *sw_ctx_last_plan(sw_ctx_t *ctx);
+
+/* ------------------------------------------------------------------ misc */
+const char *sw_strerror(int code);
+int sw_last_hip_error(void);
+const char *sw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SW_ALIGN_H */

@@ -1,0 +1,228 @@
+"""MI355X (gfx950) affine-gap Smith-Waterman CAL scorer: Python binding.
+
+The binding only marshals arguments: every step of the scoring path runs in the
+HIP kernels of ``libswalign.so`` (C ABI, include/sw_align.h).  PyTorch provides
+device memory and streams.  Importing this module fails loudly when the built
+library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch  # load torch's HIP runtime before the library so both share it
+
+__all__ = [
+    "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
+    "reduce_best", "classify", "error_count", "SwError",
+    "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
+    "MAX_READ_LEN", "MAX_REFS",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswalign.so")
+
+PREC_AUTO, PREC_INT16, PREC_INT32 = 0, 1, 2
+KERNEL_AUTO, KERNEL_INTER, KERNEL_INTRA = 0, 1, 2
+MAX_READ_LEN = 1024
+MAX_REFS = 64
+
+_lib = None
+
+
+class SwError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib().sw_strerror(code).decode()
+        if code == -7:
+            msg += f" (hipError {lib().sw_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{code}]")
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32), ("band", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("max_read_len", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, match=2, mismatch=-3, gap_open=5, gap_extend=2, band=32, precision=PREC_AUTO,
+             kernel=KERNEL_AUTO, max_read_len=0):
+        return cls(match, mismatch, gap_open, gap_extend, band, precision, kernel, max_read_len)
+
+
+class _RefSetC(ctypes.Structure):
+    _fields_ = [("words", ctypes.c_void_p), ("word_offset", ctypes.c_void_p), ("length", ctypes.c_void_p),
+                ("n_refs", ctypes.c_int32)]
+
+
+class _CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_reads", ctypes.c_int32), ("max_cals", ctypes.c_int64),
+                ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.sw_strerror.restype = ctypes.c_char_p
+        L.sw_strerror.argtypes = [ctypes.c_int]
+        L.sw_version.restype = ctypes.c_char_p
+        L.sw_last_hip_error.restype = ctypes.c_int
+        L.sw_pack_2bit.argtypes = [vp, i64, vp, vp]
+        L.sw_workspace_bytes.restype = sz
+        L.sw_workspace_bytes.argtypes = [i32, i64, ctypes.POINTER(Scoring)]
+        L.sw_align_batch.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, vp, i64,
+                                     ctypes.POINTER(Scoring), vp, vp, vp, vp, sz, vp]
+        L.sw_error_count.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.sw_reduce_best.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.sw_classify.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.sw_ctx_create.argtypes = [ctypes.POINTER(_CtxOpts), ctypes.POINTER(vp)]
+        L.sw_ctx_destroy.argtypes = [vp]
+        L.sw_align_batch_ctx.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, vp, i64,
+                                         ctypes.POINTER(Scoring), vp, vp, vp, vp]
+        L.sw_ctx_error_count.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.sw_ctx_last_plan.restype = ctypes.c_char_p
+        L.sw_ctx_last_plan.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise SwError(rc, where)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype) -> torch.Tensor:
+    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+    return t
+
+
+def pack_2bit(codes: torch.Tensor, stream=None) -> torch.Tensor:
+    """Pack a device uint8 code tensor (A,C,G,T = 0..3) into uint32 words."""
+    _dev(codes, torch.uint8)
+    n = codes.numel()
+    words = torch.empty((n + 15) // 16, dtype=torch.int32, device=codes.device)
+    _check(lib().sw_pack_2bit(_ptr(codes), n, _ptr(words), _stream(stream)), "sw_pack_2bit")
+    return words
+
+
+class RefSet:
+    """References resident in device memory (2-bit packed)."""
+
+    def __init__(self, words: torch.Tensor, word_offset, length):
+        self.words = words
+        self.word_offset = (ctypes.c_int64 * len(word_offset))(*[int(x) for x in word_offset])
+        self.length = (ctypes.c_int64 * len(length))(*[int(x) for x in length])
+        self.n_refs = len(length)
+        self._c = _RefSetC(words.data_ptr(), ctypes.cast(self.word_offset, ctypes.c_void_p),
+                           ctypes.cast(self.length, ctypes.c_void_p), self.n_refs)
+
+    @classmethod
+    def from_codes(cls, codes: torch.Tensor, code_offset, length, stream=None):
+        """Pack concatenated reference codes (each reference at a 16-aligned offset) on the device."""
+        words = pack_2bit(codes, stream)
+        return cls(words, [int(o) // 16 for o in code_offset], list(length))
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+class DeviceBatch:
+    """Device tensors of one batch in the library's layout."""
+
+    def __init__(self, reads2bit, read_word_off, read_len, cal_ptr, cal_pos, cal_ref, strand):
+        self.reads2bit = reads2bit
+        self.read_word_off = read_word_off
+        self.read_len = read_len
+        self.cal_ptr = cal_ptr
+        self.cal_pos = cal_pos
+        self.cal_ref = cal_ref
+        self.strand = strand
+
+    @property
+    def n_reads(self):
+        return int(self.read_len.numel())
+
+    @property
+    def n_cals(self):
+        return int(self.cal_pos.numel())
+
+    @classmethod
+    def upload(cls, batch, device="cuda", stream=None):
+        """From a workloads.Batch (host codes, each read at a 16-aligned offset)."""
+        t = lambda a, dt: torch.from_numpy(a).to(device=device, dtype=dt).contiguous()
+        codes = t(batch.read_codes, torch.uint8)
+        words = pack_2bit(codes, stream)
+        return cls(words, t(batch.read_off // 16, torch.int64), t(batch.read_len, torch.int32),
+                   t(batch.cal_ptr, torch.int64), t(batch.cal_pos, torch.int64), t(batch.cal_ref, torch.int16),
+                   t(batch.strand, torch.uint8))
+
+
+def workspace_bytes(n_reads: int, n_cals: int, sc: Scoring) -> int:
+    return int(lib().sw_workspace_bytes(n_reads, n_cals, ctypes.byref(sc)))
+
+
+class Outputs:
+    def __init__(self, n_cals, device="cuda"):
+        self.score = torch.empty(2 * n_cals, dtype=torch.int32, device=device)
+        self.ref_end = torch.empty(2 * n_cals, dtype=torch.int64, device=device)
+        self.read_end = torch.empty(2 * n_cals, dtype=torch.int16, device=device)
+
+
+def align_batch(db: DeviceBatch, refs: RefSet, sc: Scoring, out: Optional[Outputs] = None,
+                workspace: Optional[torch.Tensor] = None, stream=None) -> Outputs:
+    """sw_align_batch on device tensors; returns (score, ref_end, read_end) tensors."""
+    n = db.n_cals
+    if out is None:
+        out = Outputs(n, db.cal_pos.device)
+    need = workspace_bytes(db.n_reads, n, sc)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=db.cal_pos.device)
+    rc = lib().sw_align_batch(_ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len), db.n_reads,
+                              refs.c, _ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref), _ptr(db.strand), n,
+                              ctypes.byref(sc), _ptr(out.score), _ptr(out.ref_end), _ptr(out.read_end),
+                              _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(rc, "sw_align_batch")
+    return out
+
+
+def reduce_best(db: DeviceBatch, n_refs: int, score: torch.Tensor, stream=None):
+    n = db.n_reads
+    dev = score.device
+    bs = torch.empty(n * n_refs, dtype=torch.int32, device=dev)
+    bl = torch.empty(n * n_refs, dtype=torch.int64, device=dev)
+    nt = torch.empty(n * n_refs, dtype=torch.int32, device=dev)
+    _check(lib().sw_reduce_best(_ptr(db.cal_ptr), _ptr(db.cal_ref), n, n_refs, _ptr(score), _ptr(bs), _ptr(bl),
+                                _ptr(nt), _stream(stream)), "sw_reduce_best")
+    return bs.view(n, n_refs), bl.view(n, n_refs), nt.view(n, n_refs)
+
+
+def classify(best_score: torch.Tensor, threshold: int, stream=None) -> torch.Tensor:
+    n, k = best_score.shape
+    cls = torch.empty(n, dtype=torch.int32, device=best_score.device)
+    _check(lib().sw_classify(_ptr(best_score.contiguous()), n, k, threshold, _ptr(cls), _stream(stream)),
+           "sw_classify")
+    return cls
+
+
+def error_count(reset: bool = False) -> int:
+    v = ctypes.c_int64(0)
+    _check(lib().sw_error_count(ctypes.byref(v), int(reset)), "sw_error_count")
+    return int(v.value)

@@ -1,0 +1,342 @@
+// C ABI of the library: argument validation, launch planning and the plain
+// (one launch per batch) scoring path.  Declarations and contracts are in
+// include/sw_align.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/sw_align.h"
+#include "sw_api_internal.h"
+#include "sw_launch.h"
+
+namespace swapi {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return SW_ERR_HIP;
+}
+
+int validate_scoring(const sw_scoring_t *sc, ScoreMode *mode) {
+  if (!sc) return SW_ERR_INVALID_ARG;
+  if (sc->precision < SW_PREC_AUTO || sc->precision > SW_PREC_INT32) return SW_ERR_INVALID_ARG;
+  if (sc->kernel < SW_KERNEL_AUTO || sc->kernel > SW_KERNEL_INTRA) return SW_ERR_INVALID_ARG;
+  if (sc->match < 1 || sc->mismatch > 0 || sc->gap_open < 0 || sc->gap_extend < 1) return SW_ERR_SCORING;
+  if (sc->band < 0 || sc->band > SW_MAX_BAND) return SW_ERR_SCORING;
+  int mrl = sc->max_read_len == 0 ? SW_MAX_READ_LEN : sc->max_read_len;
+  if (mrl < 1) return SW_ERR_INVALID_ARG;
+  if (mrl > SW_MAX_READ_LEN) return SW_ERR_READ_TOO_LONG;
+  const int64_t goe2 = (int64_t)sc->gap_open + 2 * (int64_t)sc->gap_extend;
+  // int32 path: values are V * 4096 + tag with |V| < 2^19
+  const int64_t top = (int64_t)sc->match * mrl;
+  if (top > (1 << 19) - 2 || -(int64_t)sc->mismatch > (1 << 18) || goe2 > (1 << 18)) return SW_ERR_SCORING;
+  // int16 path: values are V * 64 + tag in int16; the bound needs V <= 510 everywhere
+  const bool fits16 = top <= 510 && sc->mismatch >= -511 && goe2 <= 511;
+  bool int16;
+  if (sc->precision == SW_PREC_INT16) {
+    if (!fits16) return SW_ERR_BOUND;
+    int16 = true;
+  } else if (sc->precision == SW_PREC_INT32) {
+    int16 = false;
+  } else {
+    int16 = fits16;
+  }
+  mode->int16 = int16;
+  mode->max_read_len = mrl;
+  mode->wcap = mrl + 2 * sc->band;
+  return SW_OK;
+}
+
+DpConstHost make_consts(const sw_scoring_t *sc) {
+  swk::DpConst k{};
+  const int32_t goe = sc->gap_open + sc->gap_extend, ge = sc->gap_extend;
+  auto pk = [](int32_t v) { return ((uint32_t)(uint16_t)(int16_t)v) * 0x00010001u; };
+  k.goe_e16 = pk(goe * 64 + 1);
+  k.ge_e16 = pk(ge * 64 + 1);
+  k.goe_f16 = pk(goe * 64);
+  k.ge_f16 = pk(ge * 64);
+  const uint16_t sm = (uint16_t)(int16_t)(sc->match * 64 - 1);
+  const uint16_t sx = (uint16_t)(int16_t)(sc->mismatch * 64 - 1);
+  const uint32_t lo_m = sm & 0xFF, hi_m = sm >> 8, lo_x = sx & 0xFF, hi_x = sx >> 8;
+  k.xlo = lo_x * 0x01010101u;
+  k.dlo = lo_x ^ lo_m;
+  k.xhi = hi_x * 0x01010101u;
+  k.dhi = hi_x ^ hi_m;
+  k.e0_16 = 0;
+  k.goe_e32 = goe * 4096 + 1;
+  k.ge_e32 = ge * 4096 + 1;
+  k.goe_f32 = goe * 4096;
+  k.ge_f32 = ge * 4096;
+  k.sm32 = sc->match * 4096 - 1;
+  k.sx32 = sc->mismatch * 4096 - 1;
+  k.e0_32 = 0;
+  return k;
+}
+
+static int strip_candidates16[] = {
+#define SW_LIST(RR) RR,
+    SW_INTER16_STRIPS(SW_LIST)
+#undef SW_LIST
+};
+static int strip_candidates32[] = {
+#define SW_LIST(RR) RR,
+    SW_INTER32_STRIPS(SW_LIST)
+#undef SW_LIST
+};
+
+int choose_strip_rows(bool int16, int rows) {
+  const int *cand = int16 ? strip_candidates16 : strip_candidates32;
+  const int n = int16 ? (int)(sizeof(strip_candidates16) / sizeof(int))
+                      : (int)(sizeof(strip_candidates32) / sizeof(int));
+  int best = cand[0];
+  int64_t best_cost = INT64_MAX;
+  for (int i = 0; i < n; ++i) {
+    const int R = cand[i];
+    const int64_t cost = (int64_t)((rows + R - 1) / R) * R;
+    if (cost < best_cost || (cost == best_cost && R > best)) {
+      best_cost = cost;
+      best = R;
+    }
+  }
+  return best;
+}
+
+int strip_rows_supported(bool int16, int R) {
+  const int *cand = int16 ? strip_candidates16 : strip_candidates32;
+  const int n = int16 ? (int)(sizeof(strip_candidates16) / sizeof(int))
+                      : (int)(sizeof(strip_candidates32) / sizeof(int));
+  for (int i = 0; i < n; ++i)
+    if (cand[i] == R) return 1;
+  return 0;
+}
+
+static std::mutex g_occ_mu;
+static int g_occ[64][2][1100];
+static int g_cus[64];
+
+int device_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  if (!g_cus[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    g_cus[dev] = n;
+  }
+  return g_cus[dev];
+}
+
+int blocks_per_cu(bool int16, int R) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || R <= 0 || R >= 1100) return 8;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  int &v = g_occ[dev][int16 ? 1 : 0][R];
+  if (!v) {
+    int n = swk::inter_blocks_per_cu(int16, R);
+    v = n > 0 ? n : 8;
+  }
+  return v;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainPlan *p) {
+  ScoreMode m;
+  int rc = validate_scoring(sc, &m);
+  if (rc) return rc;
+  p->mode = m;
+  p->strip_rows = strip_override > 0 ? strip_override : choose_strip_rows(m.int16, m.max_read_len);
+  if (!strip_rows_supported(m.int16, p->strip_rows)) return SW_ERR_INVALID_ARG;
+  p->n_tasks = m.int16 ? n_cals : 2 * n_cals;
+  p->wwords = (m.wcap + 15) / 16;
+  p->rwords = (m.max_read_len + 15) / 16;
+  const int64_t n_tiles = (p->n_tasks + 63) / 64;
+  const int64_t resident = (int64_t)device_cus() * blocks_per_cu(m.int16, p->strip_rows);
+  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, resident));
+  p->cal_read_off = 0;
+  p->scratch_off = align_up((size_t)std::max<int64_t>(n_cals, 1) * sizeof(int32_t), 256);
+  p->bytes = p->scratch_off + (size_t)p->grid * (size_t)m.wcap * 64 * sizeof(uint2);
+  return SW_OK;
+}
+
+int validate_refs(const sw_refset_t *refs, int64_t n_cals, swk::RefTable *T) {
+  if (!refs) return SW_ERR_INVALID_ARG;
+  if (refs->n_refs < 1) return SW_ERR_INVALID_ARG;
+  if (refs->n_refs > SW_MAX_REFS) return SW_ERR_TOO_MANY_REFS;
+  if (!refs->word_offset || !refs->length) return SW_ERR_INVALID_ARG;
+  if (n_cals > 0 && !refs->words) return SW_ERR_INVALID_ARG;
+  std::memset(T, 0, sizeof(*T));
+  for (int i = 0; i < refs->n_refs; ++i) {
+    if (refs->length[i] < 1 || refs->word_offset[i] < 0) return SW_ERR_INVALID_ARG;
+    T->word_off[i] = refs->word_offset[i];
+    T->len[i] = refs->length[i];
+  }
+  return SW_OK;
+}
+
+int validate_batch(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
+                   int32_t n_reads, const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref,
+                   const uint8_t *strand, int64_t n_cals, int32_t *score, int64_t *ref_end,
+                   int16_t *read_end) {
+  if (n_reads < 0 || n_cals < 0) return SW_ERR_INVALID_ARG;
+  if (!cal_ptr) return SW_ERR_INVALID_ARG;
+  if (n_reads > 0 && (!reads2bit || !read_word_off || !read_len)) return SW_ERR_INVALID_ARG;
+  if (n_cals > 0 && (!cal_pos || !cal_ref || !strand || !score || !ref_end || !read_end))
+    return SW_ERR_INVALID_ARG;
+  return SW_OK;
+}
+
+int run_plain(const PlainPlan &plan, const swk::RefTable &T, const uint32_t *reads2bit,
+              const int64_t *read_word_off, const int32_t *read_len, int32_t n_reads, const sw_refset_t *refs,
+              const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand,
+              int64_t n_cals, const sw_scoring_t *sc, int32_t *score, int64_t *ref_end, int16_t *read_end,
+              void *workspace, unsigned long long *err, hipStream_t st) {
+  char *ws = (char *)workspace;
+  int32_t *cal_read = (int32_t *)(ws + plan.cal_read_off);
+  hipError_t e = swk::launch_expand(cal_ptr, n_reads, n_cals, cal_read, st);
+  if (e != hipSuccess) return hip_fail(e);
+  swk::AlignArgs A{};
+  A.reads = reads2bit;
+  A.read_word_off = read_word_off;
+  A.read_len = read_len;
+  A.n_reads = n_reads;
+  A.n_refs = refs->n_refs;
+  A.ref_words = refs->words;
+  A.cal_pos = cal_pos;
+  A.cal_ref = cal_ref;
+  A.strand = strand;
+  A.cal_read = cal_read;
+  A.order = nullptr;
+  A.n_cals = n_cals;
+  A.n_tasks = plan.n_tasks;
+  A.score = score;
+  A.ref_end = ref_end;
+  A.read_end = read_end;
+  A.scratch = (uint2 *)(ws + plan.scratch_off);
+  A.err = err;
+  A.wcap = plan.mode.wcap;
+  A.wwords = plan.wwords;
+  A.rwords = plan.rwords;
+  A.max_read_len = plan.mode.max_read_len;
+  A.band = sc->band;
+  A.strip_rows = plan.strip_rows;
+  A.k = make_consts(sc);
+  e = swk::launch_inter(plan.mode.int16, A, T, plan.grid, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return SW_OK;
+}
+
+}  // namespace swapi
+
+using namespace swapi;
+
+extern "C" {
+
+const char *sw_strerror(int code) {
+  switch (code) {
+    case SW_OK: return "ok";
+    case SW_ERR_INVALID_ARG: return "invalid argument";
+    case SW_ERR_SCORING: return "scoring parameters out of the supported range";
+    case SW_ERR_READ_TOO_LONG: return "maximum read length above SW_MAX_READ_LEN";
+    case SW_ERR_BOUND: return "int16 precision requested but the score bound does not hold";
+    case SW_ERR_WORKSPACE: return "workspace missing or too small";
+    case SW_ERR_NOMEM: return "out of memory";
+    case SW_ERR_HIP: return "HIP runtime error";
+    case SW_ERR_TOO_MANY_REFS: return "more than SW_MAX_REFS references";
+    case SW_ERR_REJECTED: return "request larger than the memory budget";
+    case SW_ERR_STATE: return "object in the wrong state";
+    default: return "unknown error";
+  }
+}
+
+int sw_last_hip_error(void) { return g_last_hip; }
+
+const char *sw_version(void) { return "swalign-gfx950 0.1"; }
+
+int sw_pack_2bit(const uint8_t *codes, int64_t n, uint32_t *words, sw_stream_t stream) {
+  if (n < 0) return SW_ERR_INVALID_ARG;
+  if (n == 0) return SW_OK;
+  if (!codes || !words) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_pack(codes, n, words, (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+size_t sw_workspace_bytes(int32_t n_reads, int64_t n_cals, const sw_scoring_t *sc) {
+  (void)n_reads;
+  if (n_cals < 0) return 0;
+  PlainPlan p;
+  if (make_plan(n_cals, sc, 0, &p) != SW_OK) return 0;
+  return p.bytes;
+}
+
+int sw_align_batch(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
+                   int32_t n_reads, const sw_refset_t *refs, const int64_t *cal_ptr, const int64_t *cal_pos,
+                   const int16_t *cal_ref, const uint8_t *strand, int64_t n_cals, const sw_scoring_t *sc,
+                   int32_t *score, int64_t *ref_end, int16_t *read_end, void *workspace,
+                   size_t workspace_bytes, sw_stream_t stream) {
+  ScoreMode m;
+  int rc = validate_scoring(sc, &m);
+  if (rc) return rc;
+  rc = validate_batch(reads2bit, read_word_off, read_len, n_reads, cal_ptr, cal_pos, cal_ref, strand, n_cals,
+                      score, ref_end, read_end);
+  if (rc) return rc;
+  swk::RefTable T;
+  rc = validate_refs(refs, n_cals, &T);
+  if (rc) return rc;
+  if (n_cals == 0) return SW_OK;
+  if (!workspace) return SW_ERR_WORKSPACE;
+  PlainPlan plan;
+  rc = make_plan(n_cals, sc, 0, &plan);
+  if (rc) return rc;
+  if (workspace_bytes < plan.bytes) return SW_ERR_WORKSPACE;
+  unsigned long long *err = swk::error_counter();
+  if (!err) return hip_fail(hipErrorInvalidDevice);
+  return run_plain(plan, T, reads2bit, read_word_off, read_len, n_reads, refs, cal_ptr, cal_pos, cal_ref, strand,
+                   n_cals, sc, score, ref_end, read_end, workspace, err, (hipStream_t)stream);
+}
+
+int sw_error_count(int64_t *n_invalid, int reset) {
+  if (!n_invalid) return SW_ERR_INVALID_ARG;
+  unsigned long long *err = swk::error_counter();
+  if (!err) return hip_fail(hipErrorInvalidDevice);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e);
+  unsigned long long v = 0;
+  e = hipMemcpy(&v, err, sizeof(v), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  *n_invalid = (int64_t)v;
+  if (reset) {
+    v = 0;
+    e = hipMemcpy(err, &v, sizeof(v), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return SW_OK;
+}
+
+int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
+                   const int32_t *score, int32_t *best_score, int64_t *best_slot, int32_t *n_tied,
+                   sw_stream_t stream) {
+  if (n_reads < 0 || n_refs < 1) return SW_ERR_INVALID_ARG;
+  if (n_refs > SW_MAX_REFS) return SW_ERR_TOO_MANY_REFS;
+  if (n_reads == 0) return SW_OK;
+  if (!cal_ptr || !cal_ref || !score || !best_score || !best_slot || !n_tied) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_reduce(cal_ptr, cal_ref, n_reads, n_refs, score, best_score, best_slot, n_tied,
+                                    (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+int sw_classify(const int32_t *best_score, int32_t n_reads, int32_t n_refs, int32_t threshold, int32_t *cls,
+                sw_stream_t stream) {
+  if (n_reads < 0 || n_refs < 1) return SW_ERR_INVALID_ARG;
+  if (n_refs > SW_MAX_REFS) return SW_ERR_TOO_MANY_REFS;
+  if (n_reads == 0) return SW_OK;
+  if (!best_score || !cls) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_classify(best_score, n_reads, n_refs, threshold, cls, (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Device-side declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sw_align.h"
+
+namespace swk {
+
+// Reference table, copied into LDS by each wave at kernel start.
+struct RefTable {
+  int64_t word_off[SW_MAX_REFS];
+  int64_t len[SW_MAX_REFS];
+};
+
+// Constants of the tagged dynamic program.
+//
+// Every DP value of column c is kept as N = V * 2^K + tag(c) with
+// tag(c) = 2^K - 1 - (c mod 2^K): the low K bits name the column inside a tile
+// of 2^K columns, so a max over values of one column orders by V exactly and a
+// running max over a row orders by (V, then smallest column).  Moving one
+// column right lowers the tag by one, so every penalty of a move that consumes
+// a window base (diagonal, horizontal gap) carries an extra -1; vertical gap
+// moves carry none.  With these constants every term reaching a cell carries
+// that cell's tag, and the maximum needs no separate position bookkeeping.
+struct DpConst {
+  // int16 pairs (K = 6), both halves hold the same constant
+  uint32_t goe_e16, ge_e16, goe_f16, ge_f16, e0_16;
+  uint32_t xlo, dlo, xhi, dhi;  // substitution table bytes (see the kernel)
+  // int32 (K = 12)
+  int32_t goe_e32, ge_e32, goe_f32, ge_f32, sm32, sx32, e0_32;
+};
+
+struct AlignArgs {
+  const uint32_t *reads;
+  const int64_t *read_word_off;
+  const int32_t *read_len;
+  int32_t n_reads;
+  int32_t n_refs;
+  const uint32_t *ref_words;
+  const int64_t *cal_pos;
+  const int16_t *cal_ref;
+  const uint8_t *strand;
+  const int32_t *cal_read;  // owning read of each CAL (from the expansion kernel)
+  const int32_t *order;     // task position -> CAL index; null means identity
+  int64_t n_cals;
+  int64_t n_tasks;          // lanes to run (CALs for int16 pairs, 2*CALs for int32)
+  int32_t *score;
+  int64_t *ref_end;
+  int16_t *read_end;
+  uint2 *scratch;           // strip-boundary rows, [grid][wcap][64]
+  unsigned long long *err;  // invalid-task counter
+  const int32_t *tiles;     // batched: [n_tiles] first task position of each tile (64 tasks max)
+  const int32_t *tile_len;  // batched: tasks in each tile
+  const int32_t *tile_strips; // batched: strip rows R of each tile
+  int32_t *queue;           // batched: tile counter (work queue), null for static striding
+  const int32_t *n_tiles_dev; // batched: number of tiles (device), null -> ceil(n_tasks/64)
+  int32_t wcap;             // widest window (columns) of the call
+  int32_t wwords;           // LDS words per lane for the window
+  int32_t rwords;           // LDS words per lane for the read
+  int32_t max_read_len;
+  int32_t band;
+  int32_t strip_rows;       // R of the launch (plain path)
+  DpConst k;
+};
+
+}  // namespace swk

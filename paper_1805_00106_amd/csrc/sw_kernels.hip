@@ -1,0 +1,710 @@
+// HIP kernels for gfx950: 2-bit packing, task expansion, the inter-task Gotoh
+// kernels (one CAL per lane), the per-read Score Tracker reduction and the
+// two-reference classification.
+//
+// The recurrence is Gotoh's affine-gap local alignment (section 3.5 of the
+// paper defers it to an external reference):
+//   E(i,j) = max(E(i,j-1) - ge, H(i,j-1) - go - ge)
+//   F(i,j) = max(F(i-1,j) - ge, H(i-1,j) - go - ge)
+//   H(i,j) = max(0, H(i-1,j-1) + s(q_i, w_j), E(i,j), F(i,j))
+// Rows i are read bases, columns j window bases (section 3.5: the read on the
+// vertical axis, the reference on the horizontal one).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_device.h"
+#include "sw_launch.h"
+
+namespace swk {
+
+typedef short v2s __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bits(v2s a) { return __builtin_bit_cast(uint32_t, a); }
+__device__ __forceinline__ v2s pair(uint32_t a) { return __builtin_bit_cast(v2s, a); }
+__device__ __forceinline__ v2s vmax(v2s a, v2s b) { return __builtin_elementwise_max(a, b); }
+
+__device__ __forceinline__ int wave_max(int v) {
+  for (int m = 32; m; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+  for (int m = 32; m; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// --------------------------------------------------------------------------- packing
+
+// One thread per output word: 16 codes -> 2 bits each, least significant first.
+__global__ void k_pack_2bit(const uint8_t *__restrict__ codes, int64_t n, uint32_t *__restrict__ words,
+                            int64_t n_words) {
+  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n_words) return;
+  int64_t base = w * 16;
+  uint32_t acc = 0;
+  if (base + 16 <= n && (((uintptr_t)(codes + base)) & 15) == 0) {
+    uint4 v = *reinterpret_cast<const uint4 *>(codes + base);
+    uint32_t part[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc |= ((part[q] >> (8 * b)) & 3u) << (2 * (4 * q + b));
+  } else {
+    for (int k = 0; k < 16 && base + k < n; ++k) acc |= (uint32_t)(codes[base + k] & 3u) << (2 * k);
+  }
+  words[w] = acc;
+}
+
+// --------------------------------------------------------------------------- expansion
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Owner read of each CAL from the CSR row pointer (one thread per read).  CALs
+// outside every read's range keep -1 and are reported as invalid tasks.
+__global__ void k_cal_owner(const int64_t *__restrict__ cal_ptr, int32_t n_reads, int64_t n_cals,
+                            int32_t *__restrict__ cal_read) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  int64_t a = cal_ptr[r], b = cal_ptr[r + 1];
+  if (a < 0) a = 0;
+  if (b > n_cals) b = n_cals;
+  for (int64_t c = a; c < b; ++c) cal_read[c] = (int32_t)r;
+}
+
+// --------------------------------------------------------------------------- common lane setup
+
+struct LaneTask {
+  int64_t c;    // CAL index
+  int64_t ws;   // window start (absolute, forward)
+  int32_t L;    // read length (0: lane idle)
+  int32_t W;    // window width
+  int32_t mask; // strand mask handled by this lane
+  int32_t k;    // reference id
+  int32_t r;    // read id
+};
+
+__device__ __forceinline__ void write_slot(const AlignArgs &A, int64_t slot, int32_t s, int64_t re,
+                                           int16_t qe) {
+  A.score[slot] = s;
+  A.ref_end[slot] = re;
+  A.read_end[slot] = qe;
+}
+
+// Loads the task of one lane.  `strand_sel` restricts the strands handled by
+// the lane (3 for a lane holding both strands).  Invalid tasks are written out
+// here and leave the lane idle.
+__device__ __forceinline__ LaneTask load_task(const AlignArgs &A, const int64_t *rt_len, int64_t c,
+                                              int strand_sel) {
+  LaneTask t;
+  t.c = c;
+  t.ws = 0;
+  t.L = 0;
+  t.W = 0;
+  t.k = 0;
+  t.r = 0;
+  int mask = A.strand[c] & strand_sel;
+  t.mask = mask;
+  int32_t r = A.cal_read[c];
+  int32_t k = A.cal_ref[c];
+  int64_t p = A.cal_pos[c];
+  bool ok = r >= 0 && r < A.n_reads && k >= 0 && k < A.n_refs;
+  int32_t L = 0;
+  if (ok) {
+    L = A.read_len[r];
+    ok = L >= 1 && L <= A.max_read_len && p >= 0 && p < rt_len[k];
+  }
+  if (!ok) {
+    for (int h = 0; h < 2; ++h) {
+      if ((mask >> h) & 1) write_slot(A, 2 * c + h, INT32_MIN, -1, -1);
+      else if ((strand_sel >> h) & 1) write_slot(A, 2 * c + h, -1, -1, -1);
+    }
+    if (mask) atomicAdd(A.err, (unsigned long long)__builtin_popcount(mask));
+    t.mask = 0;
+    return t;
+  }
+  for (int h = 0; h < 2; ++h)
+    if (((strand_sel >> h) & 1) && !((mask >> h) & 1)) write_slot(A, 2 * c + h, -1, -1, -1);
+  if (!mask) return t;
+  int64_t ws = p - A.band;
+  if (ws < 0) ws = 0;
+  int64_t we = p + L + A.band;
+  if (we > rt_len[k]) we = rt_len[k];
+  t.ws = ws;
+  t.W = (int32_t)(we - ws);
+  t.L = L;
+  t.k = k;
+  t.r = r;
+  return t;
+}
+
+// Stage the lane's read words and its window words (re-aligned so that window
+// column 0 sits at bit 0 of word 0) into LDS, [word][lane] layout.
+__device__ __forceinline__ void stage(const AlignArgs &A, const int64_t *rt_off, const int64_t *rt_len,
+                                      const LaneTask &t, int rwmax, int wwmax, uint32_t *rdw,
+                                      uint32_t *win, int lane) {
+  if (t.L > 0) {
+    const uint32_t *rp = A.reads + A.read_word_off[t.r];
+    int nrw = (t.L + 15) >> 4;
+    for (int q = 0; q < rwmax; ++q) rdw[q * 64 + lane] = q < nrw ? rp[q] : 0u;
+    int64_t first = rt_off[t.k] + (t.ws >> 4);
+    int64_t last = rt_off[t.k] + ((rt_len[t.k] - 1) >> 4);
+    uint32_t sh = 2u * (uint32_t)(t.ws & 15);
+    uint32_t lo = A.ref_words[first];
+    for (int q = 0; q < wwmax; ++q) {
+      uint32_t hi = (first + q + 1 <= last) ? A.ref_words[first + q + 1] : 0u;
+      win[q * 64 + lane] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+      lo = hi;
+    }
+  } else {
+    for (int q = 0; q < rwmax; ++q) rdw[q * 64 + lane] = 0u;
+    for (int q = 0; q < wwmax; ++q) win[q * 64 + lane] = 0u;
+  }
+}
+
+__device__ __forceinline__ uint32_t base_at(const uint32_t *rdw, int lane, int i) {
+  return (rdw[(i >> 4) * 64 + lane] >> (2 * (i & 15))) & 3u;
+}
+
+// Lexicographic best-cell key: score, then smallest column, then smallest row.
+__device__ __forceinline__ uint64_t cell_key(int32_t v, int32_t col, int32_t row) {
+  return ((uint64_t)(uint32_t)v << 32) | ((uint64_t)(0xFFFFu - (uint32_t)col) << 16) |
+         (uint64_t)(0xFFFFu - (uint32_t)row);
+}
+
+__device__ __forceinline__ void write_result(const AlignArgs &A, int64_t slot, uint64_t key, int64_t ws) {
+  int32_t v = (int32_t)(key >> 32);
+  if (v > 0) {
+    int32_t col = 0xFFFF - (int32_t)((key >> 16) & 0xFFFF);
+    int32_t row = 0xFFFF - (int32_t)(key & 0xFFFF);
+    write_slot(A, slot, v, ws + col, (int16_t)row);
+  } else {
+    write_slot(A, slot, 0, -1, -1);
+  }
+}
+
+// Tile of task positions for this iteration (plain: fixed 64-wide tiles with
+// static striding; batched: descriptors popped from a device work queue).
+struct TileIter {
+  int64_t next;
+  int64_t n_tiles;
+};
+
+__device__ __forceinline__ bool next_tile(const AlignArgs &A, TileIter &it, int64_t &first, int &count) {
+  int64_t t;
+  if (A.queue) {
+    int v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(A.queue, 1);
+    t = __shfl(v, 0, 64);
+  } else {
+    t = it.next;
+    it.next += gridDim.x;
+  }
+  if (t >= it.n_tiles) return false;
+  if (A.tiles) {
+    first = A.tiles[t];
+    count = A.tile_len[t];
+  } else {
+    first = t * 64;
+    int64_t rem = A.n_tasks - first;
+    count = rem < 64 ? (int)rem : 64;
+  }
+  return true;
+}
+
+__device__ __forceinline__ void load_ref_table(const RefTable &T, int n_refs, int64_t *rt_off,
+                                               int64_t *rt_len, int lane) {
+  for (int i = 0; i < n_refs; ++i) {
+    int64_t o = T.word_off[i], l = T.len[i];
+    if (lane == i) {
+      rt_off[i] = o;
+      rt_len[i] = l;
+    }
+  }
+  __syncthreads();
+}
+
+// --------------------------------------------------------------------------- int16-pair kernel
+//
+// One lane holds one CAL; the low int16 half of every register is the forward
+// strand task and the high half the reverse strand task (reverse complement of
+// the read against the same window), so both halves always share the window.
+// A lane keeps a strip of R read rows in registers and sweeps the window
+// columns; between strips the strip's bottom row (H and the F entering the next
+// row) goes through a per-wave scratch buffer.
+//
+// Substitution: for column j the lane builds an 8-byte table (lo bytes and hi
+// bytes of s~(b, w_j) for b = 0..3) and each row holds a byte selector
+// (q, q|4) per half, so v_perm_b32 yields both halves' scores in one
+// instruction.  Rows past the read end use selector bytes 12/13 (0x00, 0xFF):
+// every substitution is -256, so those rows only decrease and are never
+// reported.  Columns past the lane's window use a table of 0x8000 (a wall).
+
+template <int R>
+__global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTable T) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const int lane = threadIdx.x;
+  load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
+  uint32_t *win = smem;
+  uint32_t *rdw = smem + A.wwords * 64;
+  uint2 *scr = A.scratch + (size_t)blockIdx.x * (size_t)A.wcap * 64;
+
+  const DpConst K = A.k;
+  const v2s GOE_E = pair(K.goe_e16), GE_E = pair(K.ge_e16);
+  const v2s GOE_F = pair(K.goe_f16), GE_F = pair(K.ge_f16);
+  const v2s TAG64 = pair(0x00400040u);
+
+  TileIter it{(int64_t)blockIdx.x, A.n_tiles_dev ? (int64_t)*A.n_tiles_dev : (A.n_tasks + 63) / 64};
+  int64_t first;
+  int count;
+  while (next_tile(A, it, first, count)) {
+    LaneTask t{};
+    if (lane < count) {
+      int64_t pos = first + lane;
+      int64_t c = A.order ? (int64_t)A.order[pos] : pos;
+      t = load_task(A, rt_len, c, 3);
+    }
+    const int L = t.L, W = t.W;
+    const int Lmax = wave_max(L);
+    if (Lmax == 0) continue;
+    const int Wmax = wave_max(W);
+    const int Wmin = wave_min(L > 0 ? W : 0x7fffffff);
+    stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
+
+    uint64_t best_f = 0, best_r = 0;
+    const int nstrips = (Lmax + R - 1) / R;
+    for (int s = 0; s < nstrips; ++s) {
+      const int r0 = s * R;
+      uint32_t sel[R];
+      v2s Hl[R], E[R], M[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = r0 + r;
+        if (i < L) {
+          uint32_t qf = base_at(rdw, lane, i);
+          uint32_t qr = 3u - base_at(rdw, lane, L - 1 - i);
+          sel[r] = qf | ((qf | 4u) << 8) | (qr << 16) | ((qr | 4u) << 24);
+        } else {
+          sel[r] = 0x0D0C0D0Cu;
+        }
+        Hl[r] = TAG64;
+        E[r] = TAG64 - GOE_E;
+        M[r] = pair(0u);
+      }
+      v2s hup_prev = TAG64;
+      uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
+      if (s > 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        pf0 = scr[lane];
+        if (Wmax > 1) pf1 = scr[64 + lane];
+      }
+      uint32_t wd = 0;
+      for (int c = 0; c < Wmax; ++c) {
+        const int cc = c & 63;
+        if (cc == 0 && c) {
+          // leave a 64-column tile: fold the row maxima, restart them, re-base tags
+          const int tb = c - 64;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int i = r0 + r;
+            uint32_t m = bits(M[r]);
+            int32_t vf = (int32_t)(int16_t)(m & 0xFFFFu), vr = (int32_t)(int16_t)(m >> 16);
+            if (i < L) {
+              if ((vf >> 6) > 0) {
+                uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), i);
+                best_f = kf > best_f ? kf : best_f;
+              }
+              if ((vr >> 6) > 0) {
+                uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), i);
+                best_r = kr > best_r ? kr : best_r;
+              }
+            }
+            M[r] = pair(0u);
+            Hl[r] = Hl[r] + TAG64;
+            E[r] = E[r] + TAG64;
+          }
+          hup_prev = hup_prev + TAG64;
+        }
+        const uint32_t zt = (uint32_t)(63 - cc) * 0x00010001u;
+        if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
+        const uint32_t sh8 = ((wd >> (2 * (c & 15))) & 3u) << 3;
+        uint32_t tlo = K.xlo ^ (K.dlo << sh8);
+        uint32_t thi = K.xhi ^ (K.dhi << sh8);
+        if (c >= Wmin && c >= W) {
+          tlo = 0u;
+          thi = 0x80808080u;
+        }
+        v2s hup, F;
+        if (s == 0) {
+          hup = pair(zt);
+          F = pair(zt) - GOE_F;
+        } else {
+          const uint2 cur = pf0;
+          pf0 = pf1;
+          if (c + 2 < Wmax) pf1 = scr[(c + 2) * 64 + lane];
+          hup = pair(cur.x);
+          F = pair(cur.y);
+        }
+        v2s Hd = hup_prev;
+        hup_prev = hup;
+        const v2s ZT = pair(zt);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const v2s sub = pair(__builtin_amdgcn_perm(thi, tlo, sel[r]));
+          v2s H = Hd + sub;
+          H = vmax(H, E[r]);
+          H = vmax(H, ZT);
+          H = vmax(H, F);
+          M[r] = vmax(M[r], H);
+          E[r] = vmax(E[r] - GE_E, H - GOE_E);
+          F = vmax(F - GE_F, H - GOE_F);
+          Hd = Hl[r];
+          Hl[r] = H;
+        }
+        if (s + 1 < nstrips) scr[c * 64 + lane] = make_uint2(bits(Hl[R - 1]), bits(F));
+      }
+      // fold the last (partial) tile
+      const int tb = ((Wmax - 1) >> 6) << 6;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = r0 + r;
+        uint32_t m = bits(M[r]);
+        int32_t vf = (int32_t)(int16_t)(m & 0xFFFFu), vr = (int32_t)(int16_t)(m >> 16);
+        if (i < L) {
+          if ((vf >> 6) > 0) {
+            uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), i);
+            best_f = kf > best_f ? kf : best_f;
+          }
+          if ((vr >> 6) > 0) {
+            uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), i);
+            best_r = kr > best_r ? kr : best_r;
+          }
+        }
+      }
+      if (s + 1 < nstrips) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    if (L > 0) {
+      if (t.mask & 1) write_result(A, 2 * t.c, best_f, t.ws);
+      if (t.mask & 2) write_result(A, 2 * t.c + 1, best_r, t.ws);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------- int32 kernel
+//
+// Same sweep with one task (one strand of one CAL) per lane and 32-bit values
+// tagged with K = 12 bits (tiles of 4096 columns, wider than any window the
+// library accepts, so no tile change happens inside a sweep).
+
+template <int R>
+__global__ __launch_bounds__(64) void k_inter32(const AlignArgs A, const RefTable T) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const int lane = threadIdx.x;
+  load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
+  uint32_t *win = smem;
+  uint32_t *rdw = smem + A.wwords * 64;
+  uint2 *scr = A.scratch + (size_t)blockIdx.x * (size_t)A.wcap * 64;
+  const DpConst K = A.k;
+
+  TileIter it{(int64_t)blockIdx.x, A.n_tiles_dev ? (int64_t)*A.n_tiles_dev : (A.n_tasks + 63) / 64};
+  int64_t first;
+  int count;
+  while (next_tile(A, it, first, count)) {
+    LaneTask t{};
+    int h = 0;
+    if (lane < count) {
+      int64_t pos = first + lane;
+      int64_t tk = A.order ? (int64_t)A.order[pos] : pos;
+      h = (int)(tk & 1);
+      t = load_task(A, rt_len, tk >> 1, 1 << h);
+    }
+    const int L = t.L, W = t.W;
+    const int Lmax = wave_max(L);
+    if (Lmax == 0) continue;
+    const int Wmax = wave_max(W);
+    stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
+
+    uint64_t best = 0;
+    const int nstrips = (Lmax + R - 1) / R;
+    for (int s = 0; s < nstrips; ++s) {
+      const int r0 = s * R;
+      int32_t q[R], Hl[R], E[R], M[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = r0 + r;
+        if (i < L) {
+          q[r] = h == 0 ? (int32_t)base_at(rdw, lane, i) : (int32_t)(3u - base_at(rdw, lane, L - 1 - i));
+        } else {
+          q[r] = 4;  // never equal to a window code: a mismatch-only row
+        }
+        Hl[r] = 4096;
+        E[r] = 4096 - K.goe_e32;
+        M[r] = 0;
+      }
+      int32_t hup_prev = 4096;
+      uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
+      if (s > 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        pf0 = scr[lane];
+        if (Wmax > 1) pf1 = scr[64 + lane];
+      }
+      uint32_t wd = 0;
+      for (int c = 0; c < Wmax; ++c) {
+        const int32_t zt = 4095 - c;
+        if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
+        int32_t w = (int32_t)((wd >> (2 * (c & 15))) & 3u);
+        if (c >= W) w = 5;  // past the window: never matches
+        int32_t hup, F;
+        if (s == 0) {
+          hup = zt;
+          F = zt - K.goe_f32;
+        } else {
+          const uint2 cur = pf0;
+          pf0 = pf1;
+          if (c + 2 < Wmax) pf1 = scr[(c + 2) * 64 + lane];
+          hup = (int32_t)cur.x;
+          F = (int32_t)cur.y;
+        }
+        int32_t Hd = hup_prev;
+        hup_prev = hup;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int32_t sub = q[r] == w ? K.sm32 : K.sx32;
+          int32_t H = max(max(Hd + sub, E[r]), F);
+          H = max(H, zt);
+          M[r] = max(M[r], H);
+          E[r] = max(E[r] - K.ge_e32, H - K.goe_e32);
+          F = max(F - K.ge_f32, H - K.goe_f32);
+          Hd = Hl[r];
+          Hl[r] = H;
+        }
+        if (s + 1 < nstrips) scr[c * 64 + lane] = make_uint2((uint32_t)Hl[R - 1], (uint32_t)F);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = r0 + r;
+        int32_t v = M[r] >> 12;
+        if (i < L && v > 0) {
+          uint64_t kk = cell_key(v, 4095 - (M[r] & 4095), i);
+          best = kk > best ? kk : best;
+        }
+      }
+      if (s + 1 < nstrips) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    if (L > 0) write_result(A, 2 * t.c + h, best, t.ws);
+  }
+}
+
+// --------------------------------------------------------------------------- Score Tracker
+
+// One thread per read: best slot per reference, lowest slot among ties, tie count.
+__global__ void k_reduce_best(const int64_t *__restrict__ cal_ptr, const int16_t *__restrict__ cal_ref,
+                              int32_t n_reads, int32_t n_refs, const int32_t *__restrict__ score,
+                              int32_t *__restrict__ best_score, int64_t *__restrict__ best_slot,
+                              int32_t *__restrict__ n_tied) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  int64_t o = r * n_refs;
+  if (n_refs <= 8) {
+    int32_t bs[8];
+    int64_t bl[8];
+    int32_t nt[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      bs[k] = -1;
+      bl[k] = -1;
+      nt[k] = 0;
+    }
+    for (int64_t c = cal_ptr[r]; c < cal_ptr[r + 1]; ++c) {
+      int k = cal_ref[c];
+      if (k < 0 || k >= n_refs) continue;
+      int2 s2 = *reinterpret_cast<const int2 *>(score + 2 * c);
+      int32_t sv[2] = {s2.x, s2.y};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        int32_t s = sv[h];
+        if (s < 0) continue;
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          if (kk == k) {
+            if (s > bs[kk]) {
+              bs[kk] = s;
+              bl[kk] = 2 * c + h;
+              nt[kk] = 1;
+            } else if (s == bs[kk]) {
+              nt[kk] += 1;
+            }
+          }
+        }
+      }
+    }
+    for (int k = 0; k < n_refs; ++k) {
+      best_score[o + k] = bs[k];
+      best_slot[o + k] = bl[k];
+      n_tied[o + k] = nt[k];
+    }
+  } else {
+    for (int k = 0; k < n_refs; ++k) {
+      best_score[o + k] = -1;
+      best_slot[o + k] = -1;
+      n_tied[o + k] = 0;
+    }
+    for (int64_t c = cal_ptr[r]; c < cal_ptr[r + 1]; ++c) {
+      int k = cal_ref[c];
+      if (k < 0 || k >= n_refs) continue;
+      for (int h = 0; h < 2; ++h) {
+        int32_t s = score[2 * c + h];
+        if (s < 0) continue;
+        if (s > best_score[o + k]) {
+          best_score[o + k] = s;
+          best_slot[o + k] = 2 * c + h;
+          n_tied[o + k] = 1;
+        } else if (s == best_score[o + k]) {
+          n_tied[o + k] += 1;
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_classify(const int32_t *__restrict__ best_score, int32_t n_reads, int32_t n_refs,
+                           int32_t threshold, int32_t *__restrict__ cls) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  int32_t top = -1, arg = -1, cnt = 0;
+  for (int k = 0; k < n_refs; ++k) {
+    int32_t v = best_score[r * n_refs + k];
+    if (v > top) {
+      top = v;
+      arg = k;
+      cnt = 1;
+    } else if (v == top) {
+      cnt++;
+    }
+  }
+  cls[r] = top < threshold ? -1 : (cnt > 1 ? -2 : arg);
+}
+
+// --------------------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_pack(const uint8_t *codes, int64_t n, uint32_t *words, hipStream_t st) {
+  int64_t nw = (n + 15) / 16;
+  if (nw == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_2bit, dim3(blocks_for(nw, 256)), dim3(256), 0, st, codes, n, words, nw);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, int32_t *cal_read,
+                         hipStream_t st) {
+  if (n_cals > 0)
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n_cals, 256)), dim3(256), 0, st, cal_read, n_cals, -1);
+  if (n_reads > 0)
+    hipLaunchKernelGGL(k_cal_owner, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, n_reads,
+                       n_cals, cal_read);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_inter16_r(const AlignArgs &A, const RefTable &T, int grid, size_t lds,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16<R>), dim3(grid), dim3(64), lds, st, A, T);
+  return hipGetLastError();
+}
+template <int R>
+static hipError_t launch_inter32_r(const AlignArgs &A, const RefTable &T, int grid, size_t lds,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter32<R>), dim3(grid), dim3(64), lds, st, A, T);
+  return hipGetLastError();
+}
+
+#define SW_INTER16_CASE(RR) \
+  case RR:                  \
+    return launch_inter16_r<RR>(A, T, grid, lds, st);
+#define SW_INTER32_CASE(RR) \
+  case RR:                  \
+    return launch_inter32_r<RR>(A, T, grid, lds, st);
+
+hipError_t launch_inter(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st) {
+  size_t lds = (size_t)(A.wwords + A.rwords) * 64 * sizeof(uint32_t);
+  if (int16) {
+    switch (A.strip_rows) { SW_INTER16_STRIPS(SW_INTER16_CASE) default: return hipErrorInvalidValue; }
+  } else {
+    switch (A.strip_rows) { SW_INTER32_STRIPS(SW_INTER32_CASE) default: return hipErrorInvalidValue; }
+  }
+}
+
+hipError_t launch_reduce(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
+                         const int32_t *score, int32_t *bs, int64_t *bl, int32_t *nt, hipStream_t st) {
+  if (n_reads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_best, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, cal_ref,
+                     n_reads, n_refs, score, bs, bl, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify(const int32_t *bs, int32_t n_reads, int32_t n_refs, int32_t thr, int32_t *cls,
+                           hipStream_t st) {
+  if (n_reads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_classify, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, bs, n_reads, n_refs,
+                     thr, cls);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------- queries
+
+__device__ unsigned long long g_invalid_tasks;
+
+unsigned long long *error_counter() {
+  static void *addr[64] = {nullptr};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!addr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_invalid_tasks)) != hipSuccess) return nullptr;
+    addr[dev] = p;
+  }
+  return (unsigned long long *)addr[dev];
+}
+
+template <int R>
+static int occ16(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_inter16<R>), 64,
+                                                  lds) != hipSuccess)
+    return 0;
+  return n;
+}
+template <int R>
+static int occ32(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_inter32<R>), 64,
+                                                  lds) != hipSuccess)
+    return 0;
+  return n;
+}
+
+#define SW_OCC16_CASE(RR) \
+  case RR:                \
+    return occ16<RR>(8192);
+#define SW_OCC32_CASE(RR) \
+  case RR:                \
+    return occ32<RR>(8192);
+
+int inter_blocks_per_cu(bool int16, int strip_rows) {
+  if (int16) {
+    switch (strip_rows) { SW_INTER16_STRIPS(SW_OCC16_CASE) default: return 0; }
+  } else {
+    switch (strip_rows) { SW_INTER32_STRIPS(SW_OCC32_CASE) default: return 0; }
+  }
+}
+
+}  // namespace swk

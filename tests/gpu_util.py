@@ -1,0 +1,44 @@
+"""Helpers for the GPU tests: run the HIP path and the oracle on the same batch."""
+import numpy as np
+import torch
+
+import paper_1805_00106_amd as sw
+from oracle import oracle as orc
+
+
+def scoring_for(batch, precision, kernel=0, max_read_len=None):
+    sc = batch.scoring
+    mrl = int(batch.read_len.max()) if max_read_len is None and batch.n_reads else (max_read_len or 0)
+    return sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, precision, kernel,
+                           max(mrl, 1) if mrl else 0)
+
+
+def gpu_align(batch, precision=sw.PREC_AUTO, kernel=0, max_read_len=None, reduce=True):
+    refs = sw.RefSet.from_codes(torch.from_numpy(batch.ref_codes).cuda(), batch.ref_off, batch.ref_len)
+    db = sw.DeviceBatch.upload(batch)
+    scoring = scoring_for(batch, precision, kernel, max_read_len)
+    out = sw.align_batch(db, refs, scoring)
+    res = dict(score=out.score, ref_end=out.ref_end, read_end=out.read_end)
+    if reduce:
+        bs, bl, nt = sw.reduce_best(db, batch.n_refs, out.score)
+        res.update(best_score=bs, best_slot=bl, n_tied=nt)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+def oracle_align(batch, threads=8):
+    s, r, e, errs = orc.align_batch(batch, n_threads=threads)
+    bs, bl, nt = orc.reduce_best(batch.cal_ptr, batch.cal_ref, batch.n_reads, batch.n_refs, s)
+    return dict(score=s, ref_end=r, read_end=e, best_score=bs, best_slot=bl, n_tied=nt), errs
+
+
+def assert_same(got, exp, what=""):
+    for k in exp:
+        if k not in got:
+            continue
+        g, e = got[k], exp[k]
+        if not np.array_equal(g, e):
+            bad = np.nonzero(g.reshape(-1) != e.reshape(-1))[0]
+            i = int(bad[0])
+            raise AssertionError(f"{what}: {k} differs in {len(bad)} of {e.size} entries; first at {i}: "
+                                 f"gpu={g.reshape(-1)[i]} oracle={e.reshape(-1)[i]}")

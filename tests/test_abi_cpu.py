@@ -1,0 +1,107 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad host-visible arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sw_align.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(sw_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def sw():
+    import paper_1805_00106_amd as sw
+    sw.lib()
+    return sw
+
+
+def test_header_declares_entry_points():
+    names = _declared_functions()
+    for n in ("sw_align_batch", "sw_workspace_bytes", "sw_reduce_best", "sw_classify", "sw_pack_2bit",
+              "sw_ctx_create", "sw_align_batch_ctx", "sw_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(sw):
+    L = sw.lib()
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_strerror_covers_codes(sw):
+    L = sw.lib()
+    for code in range(0, -11, -1):
+        assert L.sw_strerror(code).decode() != "unknown error"
+
+
+def _refset(sw, n_refs=1, length=1000):
+    offs = (ctypes.c_int64 * n_refs)(*[0] * n_refs)
+    lens = (ctypes.c_int64 * n_refs)(*[length] * n_refs)
+    return sw._RefSetC(ctypes.c_void_p(16), ctypes.cast(offs, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p),
+                       n_refs), (offs, lens)
+
+
+def _call(sw, sc, refs=None, n_cals=4, workspace=None, n_reads=2):
+    L = sw.lib()
+    p = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    if refs is None:
+        refs, keep = _refset(sw)
+    return L.sw_align_batch(p, p, p, n_reads, ctypes.byref(refs), p, p, p, p, n_cals,
+                            ctypes.byref(sc) if sc is not None else None, p, p, p, workspace, 0, None)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("match", 0, -2), ("mismatch", 1, -2), ("gap_open", -1, -2), ("gap_extend", 0, -2), ("band", -1, -2),
+    ("band", 5000, -2), ("precision", 7, -1), ("kernel", 9, -1), ("max_read_len", 5000, -3),
+    ("max_read_len", -3, -1),
+])
+def test_scoring_validation(sw, field, value, code):
+    sc = sw.Scoring.make(max_read_len=100)
+    setattr(sc, field, value)
+    assert _call(sw, sc) == code
+
+
+def test_null_scoring_is_invalid(sw):
+    assert _call(sw, None) == -1
+
+
+def test_int16_bound_rejected_when_requested(sw):
+    sc = sw.Scoring.make(precision=sw.PREC_INT16, max_read_len=300)   # 2 * 300 > 510
+    assert _call(sw, sc) == -4
+    sc = sw.Scoring.make(precision=sw.PREC_INT16, max_read_len=255)
+    assert _call(sw, sc) == -5                                         # passes bound, then no workspace
+
+
+def test_reference_set_validation(sw):
+    sc = sw.Scoring.make(max_read_len=100)
+    refs, keep = _refset(sw, n_refs=65)
+    assert _call(sw, sc, refs=refs) == -8
+    refs, keep = _refset(sw, n_refs=1, length=0)
+    assert _call(sw, sc, refs=refs) == -1
+
+
+def test_counts_and_workspace_validation(sw):
+    sc = sw.Scoring.make(max_read_len=100)
+    assert _call(sw, sc, n_cals=-1) == -1
+    assert _call(sw, sc, n_reads=-1) == -1
+    assert _call(sw, sc, n_cals=10) == -5        # no workspace
+    assert _call(sw, sc, n_cals=0) == 0          # nothing to do
+
+
+def test_reduce_and_classify_validation(sw):
+    L = sw.lib()
+    p = ctypes.c_void_p(16)
+    assert L.sw_reduce_best(p, p, -1, 1, p, p, p, p, None) == -1
+    assert L.sw_reduce_best(p, p, 1, 0, p, p, p, p, None) == -1
+    assert L.sw_reduce_best(p, p, 1, 65, p, p, p, p, None) == -8
+    assert L.sw_classify(p, 1, 0, 0, p, None) == -1
+    assert L.sw_pack_2bit(p, -1, p, None) == -1

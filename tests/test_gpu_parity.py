@@ -1,0 +1,114 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Scores and end positions are integers, so the bar is bit-exact equality of
+every output (score, ref_end, read_end, best_score, best_slot, n_tied).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1805_00106_amd as sw
+from paper_1805_00106_amd import workloads as wl
+from tests.gpu_util import assert_same, gpu_align, oracle_align
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = [sw.PREC_INT16, sw.PREC_INT32]
+
+
+def _case(batch, precision, **kw):
+    exp, _ = oracle_align(batch)
+    got = gpu_align(batch, precision, **kw)
+    assert_same(got, exp, f"{batch.name} prec={precision} {kw}")
+
+
+def test_config1_int32_full():
+    """Config 1 exactly as stated: 1000 x 76 bp reads, 2 CALs, both strands, int32."""
+    _case(wl.config1(), sw.PREC_INT32)
+
+
+def test_config1_int16():
+    _case(wl.config1(), sw.PREC_INT16)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("seed", range(6))
+def test_random_ragged_small(seed, precision):
+    """Ragged reads (1..60 bp), CALs near both reference ends (clipped windows),
+    mixed strand masks, zero-CAL reads, two references."""
+    _case(wl.random_small_batch(seed, n_reads=80, read_len=(1, 60), band=8), precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_long_reads_wide_band(precision):
+    """L up to 250 with band 64: windows up to 378 columns (several 64-column tiles and strips)."""
+    b = wl.random_small_batch(11, n_reads=40, read_len=(180, 250), ref_len=(300, 3000), band=64)
+    _case(b, precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_homopolymers_maximal_ties(precision):
+    b = wl.random_small_batch(12, n_reads=40, read_len=(1, 90), band=20, homopolymer=True)
+    _case(b, precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_single_base_reads(precision):
+    _case(wl.random_small_batch(13, n_reads=60, read_len=(1, 1), band=3), precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("sc", [wl.Scoring(1, 0, 0, 1, 10), wl.Scoring(3, -1, 1, 1, 10),
+                                wl.Scoring(2, -3, 0, 2, 10), wl.Scoring(1, -4, 6, 1, 10)])
+def test_other_scorings(sc, precision):
+    b = wl.random_small_batch(14, n_reads=60, read_len=(1, 80), band=10)
+    b = dataclasses.replace(b, scoring=sc)
+    _case(b, precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("mrl", [76, 100, 150, 250])
+def test_strip_heights(mrl, precision):
+    """Different read-length bounds pick different strip heights (rows per lane)."""
+    b = wl.random_small_batch(15, n_reads=50, read_len=(1, min(mrl, 250)), band=16, ref_len=(300, 2000))
+    _case(b, precision, max_read_len=mrl)
+
+
+def test_invalid_cals_flagged():
+    b = wl.random_small_batch(16, n_reads=30, max_cals=3)
+    b.cal_pos = b.cal_pos.copy()
+    b.cal_ref = b.cal_ref.copy()
+    b.cal_pos[0] = b.ref_len[int(b.cal_ref[0])]
+    b.cal_ref[1] = b.n_refs
+    b.cal_pos[2] = -5
+    sw.error_count(reset=True)
+    exp, errs = oracle_align(b)
+    got = gpu_align(b, sw.PREC_INT16)
+    assert_same(got, exp, "invalid cals")
+    assert sw.error_count() == errs > 0
+
+
+def test_three_references_reduce_and_classify():
+    b = wl.random_small_batch(17, n_refs=3, n_reads=100, max_cals=6, band=12)
+    exp, _ = oracle_align(b)
+    got = gpu_align(b, sw.PREC_INT16)
+    assert_same(got, exp, "3 refs")
+    from oracle import oracle as orc
+    bs = torch.from_numpy(got["best_score"]).cuda()
+    for thr in (0, 10, 40):
+        cls = sw.classify(bs, thr).cpu().numpy()
+        np.testing.assert_array_equal(cls, orc.classify(exp["best_score"], thr))
+
+
+def test_config2_shape_moderate():
+    """Config 2 generator (100 Mbp reference with repeats, 100 bp reads, Poisson(6)+1
+    CALs, band 32, int16) at 5000 reads: full oracle parity."""
+    _case(wl.config2(n_reads=5000), sw.PREC_INT16)
+
+
+def test_config3_shape_moderate():
+    """Config 3 generator (L uniform 75..250, geometric CAL counts) at 1500 reads."""
+    b = wl.config3(n_reads=1500, band=64)
+    _case(b, sw.PREC_INT16, max_read_len=250)
