@@ -18,6 +18,7 @@
 namespace swk {
 
 typedef short v2s __attribute__((ext_vector_type(2)));
+typedef unsigned short v2u __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t bits(v2s a) { return __builtin_bit_cast(uint32_t, a); }
 __device__ __forceinline__ v2s pair(uint32_t a) { return __builtin_bit_cast(v2s, a); }
@@ -241,6 +242,158 @@ __device__ __forceinline__ void load_ref_table(const RefTable &T, int n_refs, in
 // every substitution is -256, so those rows only decrease and are never
 // reported.  Columns past the lane's window use a table of 0x8000 (a wall).
 
+// Fold the per-row maxima of one 64-column tile (tile base tb) into the
+// lexicographic best keys of both halves.  The packed maximum over the rows
+// gives, per half, the best value and (through its tag) the smallest column;
+// the smallest row holding exactly that value is then found with a packed
+// equality scan.  Rows past the read end need no check: every value there
+// derives from the rows above minus a positive penalty (their substitutions
+// are -4), so it stays strictly below the best real cell and never wins.
+template <int R>
+__device__ __forceinline__ void fold16(const v2s (&M)[R], int r0, int tb, uint64_t &best_f, uint64_t &best_r) {
+  v2s mx = M[0];
+#pragma unroll
+  for (int r = 1; r < R; ++r) mx = vmax(mx, M[r]);
+  const uint32_t mxb = bits(mx);
+  if ((mxb & 0xFFC0FFC0u) == 0) return;  // both halves at value 0 (V <= 0)
+  uint32_t rows = 0xFFFFFFFFu;
+  const v2u ONE = __builtin_bit_cast(v2u, 0x00010001u);
+#pragma unroll
+  for (int r = R - 1; r >= 0; --r) {
+    // eq: 0xFFFF in the halves where M[r] equals the maximum
+    const v2u d = __builtin_elementwise_min(__builtin_bit_cast(v2u, bits(M[r]) ^ mxb), ONE);
+    const uint32_t eq = __builtin_bit_cast(uint32_t, (v2u)(d - ONE));
+    rows = (rows & ~eq) | ((uint32_t)r * 0x00010001u & eq);
+  }
+  const int32_t vf = (int32_t)(int16_t)(mxb & 0xFFFFu), vr = (int32_t)(int16_t)(mxb >> 16);
+  if ((vf >> 6) > 0) {
+    const uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), r0 + (int32_t)(rows & 0xFFFFu));
+    best_f = kf > best_f ? kf : best_f;
+  }
+  if ((vr >> 6) > 0) {
+    const uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), r0 + (int32_t)(rows >> 16));
+    best_r = kr > best_r ? kr : best_r;
+  }
+}
+
+// One strip of R read rows swept over every window column.  FIRST: the strip
+// starts at read row 0 (top boundary H = 0); LAST: no strip follows (nothing
+// is written to the scratch rows).
+template <int R, bool FIRST, bool LAST>
+__device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
+                                        int lane, int r0, int L, int W, int Wmin, int Wmax, uint64_t &best_f,
+                                        uint64_t &best_r) {
+  const v2s GOE_E = pair(K.goe_e16), GE_E = pair(K.ge_e16);
+  const v2s GOE_F = pair(K.goe_f16), GE_F = pair(K.ge_f16);
+  const v2s TAG64 = pair(0x00400040u);
+  uint32_t sel[R];
+  v2s Hl[R], E[R], M[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = r0 + r;
+    if (i < L) {
+      const uint32_t qf = base_at(rdw, lane, i);
+      const uint32_t qr = 3u - base_at(rdw, lane, L - 1 - i);
+      sel[r] = qf | ((qf | 4u) << 8) | (qr << 16) | ((qr | 4u) << 24);
+    } else {
+      sel[r] = 0x0D0C0D0Cu;
+    }
+    Hl[r] = TAG64;
+    E[r] = TAG64 - GOE_E;
+    M[r] = pair(0u);
+  }
+  v2s hup_prev = TAG64;
+  uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
+  if (!FIRST) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    pf0 = scr[lane];
+    if (Wmax > 1) pf1 = scr[64 + lane];
+  }
+  for (int tb = 0; tb < Wmax; tb += 64) {
+    const int tend = min(tb + 64, Wmax);
+    uint32_t wd = 0;
+    for (int c = tb; c < tend; ++c) {
+      const int cc = c - tb;
+      const uint32_t zt = (uint32_t)(63 - cc) * 0x00010001u;
+      if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
+      const uint32_t sh8 = ((wd >> (2 * (c & 15))) & 3u) << 3;
+      uint32_t tlo = K.xlo ^ (K.dlo << sh8);
+      uint32_t thi = K.xhi ^ (K.dhi << sh8);
+      if (c >= Wmin) {
+        if (c >= W) {
+          tlo = 0u;
+          thi = 0x80808080u;
+        }
+      }
+      v2s hup, F;
+      if (FIRST) {
+        hup = pair(zt);
+        F = pair(zt) - GOE_F;
+      } else {
+        const uint2 cur = pf0;
+        pf0 = pf1;
+        if (c + 2 < Wmax) pf1 = scr[(c + 2) * 64 + lane];
+        hup = pair(cur.x);
+        F = pair(cur.y);
+      }
+      const v2s ZT = pair(zt);
+      // Row r needs p_r = max(H(i-1,j-1) + s, E(i,j), 0) (independent of F) and
+      // then the serial F chain.  The partial of row r+1 is computed while row
+      // r's chain resolves so that no packed op waits on its predecessor.
+      v2s Hd = hup_prev;
+      hup_prev = hup;
+      v2s p = vmax(vmax(Hd + pair(__builtin_amdgcn_perm(thi, tlo, sel[0])), E[0]), ZT);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // the diagonal of row r+1 is row r's previous H: consume it before row r's
+        // new H takes its register
+        v2s t;
+        if (r + 1 < R) t = Hl[r] + pair(__builtin_amdgcn_perm(thi, tlo, sel[r + 1]));
+        const v2s H = vmax(p, F);
+        const v2s f2 = F - GE_F;
+        const v2s e2 = E[r] - GE_E;
+        const v2s v = H - GOE_F;
+        const v2s u = H - GOE_E;
+        if (r + 1 < R) t = vmax(t, E[r + 1]);
+        F = vmax(f2, v);
+        E[r] = vmax(e2, u);
+        if (r + 1 < R) p = vmax(t, ZT);
+        M[r] = vmax(M[r], H);
+        Hl[r] = H;
+      }
+      if (!LAST) scr[c * 64 + lane] = make_uint2(bits(Hl[R - 1]), bits(F));
+    }
+    fold16<R>(M, r0, tb, best_f, best_r);
+    if (tend < Wmax) {
+      // next tile: restart the row maxima and re-base the carried tags by +64
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        M[r] = pair(0u);
+        Hl[r] = Hl[r] + TAG64;
+        E[r] = E[r] + TAG64;
+      }
+      hup_prev = hup_prev + TAG64;
+    }
+  }
+  if (!LAST) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+// --------------------------------------------------------------------------- int16-pair kernel
+//
+// One lane holds one CAL; the low int16 half of every register is the forward
+// strand task and the high half the reverse strand task (reverse complement of
+// the read against the same window), so both halves always share the window.
+// A lane keeps a strip of R read rows in registers and sweeps the window
+// columns; between strips the strip's bottom row (H and the F entering the next
+// row) goes through a per-wave scratch buffer.
+//
+// Substitution: for column j the lane builds an 8-byte table (lo bytes and hi
+// bytes of s~(b, w_j) for b = 0..3) and each row holds a byte selector
+// (q, q|4) per half, so v_perm_b32 yields both halves' scores in one
+// instruction.  Rows past the read end use selector bytes 12/13 (0x00, 0xFF):
+// every substitution is -256, so those rows only decrease and are never
+// reported.  Columns past the lane's window use a table of 0x8000 (a wall).
+
 template <int R>
 __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
@@ -250,11 +403,7 @@ __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTabl
   uint32_t *win = smem;
   uint32_t *rdw = smem + A.wwords * 64;
   uint2 *scr = A.scratch + (size_t)blockIdx.x * (size_t)A.wcap * 64;
-
   const DpConst K = A.k;
-  const v2s GOE_E = pair(K.goe_e16), GE_E = pair(K.ge_e16);
-  const v2s GOE_F = pair(K.goe_f16), GE_F = pair(K.ge_f16);
-  const v2s TAG64 = pair(0x00400040u);
 
   TileIter it{(int64_t)blockIdx.x, A.n_tiles_dev ? (int64_t)*A.n_tiles_dev : (A.n_tasks + 63) / 64};
   int64_t first;
@@ -275,115 +424,13 @@ __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTabl
 
     uint64_t best_f = 0, best_r = 0;
     const int nstrips = (Lmax + R - 1) / R;
-    for (int s = 0; s < nstrips; ++s) {
-      const int r0 = s * R;
-      uint32_t sel[R];
-      v2s Hl[R], E[R], M[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = r0 + r;
-        if (i < L) {
-          uint32_t qf = base_at(rdw, lane, i);
-          uint32_t qr = 3u - base_at(rdw, lane, L - 1 - i);
-          sel[r] = qf | ((qf | 4u) << 8) | (qr << 16) | ((qr | 4u) << 24);
-        } else {
-          sel[r] = 0x0D0C0D0Cu;
-        }
-        Hl[r] = TAG64;
-        E[r] = TAG64 - GOE_E;
-        M[r] = pair(0u);
-      }
-      v2s hup_prev = TAG64;
-      uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
-      if (s > 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        pf0 = scr[lane];
-        if (Wmax > 1) pf1 = scr[64 + lane];
-      }
-      uint32_t wd = 0;
-      for (int c = 0; c < Wmax; ++c) {
-        const int cc = c & 63;
-        if (cc == 0 && c) {
-          // leave a 64-column tile: fold the row maxima, restart them, re-base tags
-          const int tb = c - 64;
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int i = r0 + r;
-            uint32_t m = bits(M[r]);
-            int32_t vf = (int32_t)(int16_t)(m & 0xFFFFu), vr = (int32_t)(int16_t)(m >> 16);
-            if (i < L) {
-              if ((vf >> 6) > 0) {
-                uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), i);
-                best_f = kf > best_f ? kf : best_f;
-              }
-              if ((vr >> 6) > 0) {
-                uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), i);
-                best_r = kr > best_r ? kr : best_r;
-              }
-            }
-            M[r] = pair(0u);
-            Hl[r] = Hl[r] + TAG64;
-            E[r] = E[r] + TAG64;
-          }
-          hup_prev = hup_prev + TAG64;
-        }
-        const uint32_t zt = (uint32_t)(63 - cc) * 0x00010001u;
-        if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
-        const uint32_t sh8 = ((wd >> (2 * (c & 15))) & 3u) << 3;
-        uint32_t tlo = K.xlo ^ (K.dlo << sh8);
-        uint32_t thi = K.xhi ^ (K.dhi << sh8);
-        if (c >= Wmin && c >= W) {
-          tlo = 0u;
-          thi = 0x80808080u;
-        }
-        v2s hup, F;
-        if (s == 0) {
-          hup = pair(zt);
-          F = pair(zt) - GOE_F;
-        } else {
-          const uint2 cur = pf0;
-          pf0 = pf1;
-          if (c + 2 < Wmax) pf1 = scr[(c + 2) * 64 + lane];
-          hup = pair(cur.x);
-          F = pair(cur.y);
-        }
-        v2s Hd = hup_prev;
-        hup_prev = hup;
-        const v2s ZT = pair(zt);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const v2s sub = pair(__builtin_amdgcn_perm(thi, tlo, sel[r]));
-          v2s H = Hd + sub;
-          H = vmax(H, E[r]);
-          H = vmax(H, ZT);
-          H = vmax(H, F);
-          M[r] = vmax(M[r], H);
-          E[r] = vmax(E[r] - GE_E, H - GOE_E);
-          F = vmax(F - GE_F, H - GOE_F);
-          Hd = Hl[r];
-          Hl[r] = H;
-        }
-        if (s + 1 < nstrips) scr[c * 64 + lane] = make_uint2(bits(Hl[R - 1]), bits(F));
-      }
-      // fold the last (partial) tile
-      const int tb = ((Wmax - 1) >> 6) << 6;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = r0 + r;
-        uint32_t m = bits(M[r]);
-        int32_t vf = (int32_t)(int16_t)(m & 0xFFFFu), vr = (int32_t)(int16_t)(m >> 16);
-        if (i < L) {
-          if ((vf >> 6) > 0) {
-            uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), i);
-            best_f = kf > best_f ? kf : best_f;
-          }
-          if ((vr >> 6) > 0) {
-            uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), i);
-            best_r = kr > best_r ? kr : best_r;
-          }
-        }
-      }
-      if (s + 1 < nstrips) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (nstrips == 1) {
+      strip16<R, true, true>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    } else {
+      strip16<R, true, false>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+      for (int s = 1; s + 1 < nstrips; ++s)
+        strip16<R, false, false>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
+      strip16<R, false, true>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
     }
     if (L > 0) {
       if (t.mask & 1) write_result(A, 2 * t.c, best_f, t.ws);
