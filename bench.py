@@ -1,8 +1,8 @@
 """Benchmark of the Smith-Waterman CAL scorer on one MI355X.
 
-Workload: the chromosome-scale plain configuration — a 100 Mbp synthetic
-reference (uniform ACGT with 5% planted repeats), 1,000,000 reads of 100 bp
-(1% substitutions, 0.1% indels), Poisson(6)+1 CALs per read drawn from the true
+Workload: the chromosome-scale configuration — a 100 Mbp synthetic reference
+(uniform ACGT with 5% planted repeats), 1,000,000 reads of 100 bp (1%
+substitutions, 0.1% indels), Poisson(6)+1 CALs per read drawn from the true
 locus, repeat homologs and uniform decoys, window = read +/- 32 bp, both
 strands, int16 dynamic programming.
 
@@ -10,7 +10,11 @@ One step is one pass of the whole scoring path over the batch with the
 references already resident in HBM: 2-bit packing of the reads, CAL expansion,
 the Gotoh sweep of every (CAL, strand) task, and the per-read, per-reference
 best-score reduction.  GCUPS = sum over computed tasks of read length x
-(clipped) window width, divided by the step time.
+(clipped) window width, divided by the step time.  The batched path (length
+bins, persistent work queue, HIP graph) is the reported value; the plain path
+(one launch per batch, static tiles) is timed on the same inputs beside it and
+must give bit-identical outputs.  A second leg runs the uneven-length workload
+(L uniform 75..250, geometric CAL counts) where binning matters.
 
 Prints one JSON line.
 """
@@ -39,7 +43,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("sw_kernels.hip", "sw_device.h"):
+    for name in ("sw_kernels.hip", "sw_device.h", "sw_launch.h"):
         with open(os.path.join(ROOT, "paper_1805_00106_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -90,12 +94,113 @@ def cpu_baseline(batch, target_s: float = 15.0):
             "reads_per_s": round(n / dt, 1)}
 
 
+def parity_sample(batch, out, n=300, seed=7):
+    """Compare a random sample of reads against the oracle (not timed)."""
+    from oracle import oracle as orc
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(batch.n_reads, min(n, batch.n_reads), replace=False))
+    sub = batch.subset_reads(idx)
+    s, r, e, _ = orc.align_batch(sub, n_threads=min(16, os.cpu_count() or 1))
+    sel = np.concatenate([np.arange(batch.cal_ptr[i], batch.cal_ptr[i + 1]) for i in idx])
+    slots = np.stack([2 * sel, 2 * sel + 1], 1).reshape(-1)
+    gs, gr, ge = (out.score.cpu().numpy()[slots], out.ref_end.cpu().numpy()[slots],
+                  out.read_end.cpu().numpy()[slots])
+    return bool(np.array_equal(gs, s) and np.array_equal(gr, r) and np.array_equal(ge, e))
+
+
+class Leg:
+    """One workload resident on the GPU, timed on the plain and the batched path."""
+
+    def __init__(self, batch, max_read_len, steps, warmup):
+        import torch
+        import paper_1805_00106_amd as sw
+        self.torch, self.sw = torch, sw
+        self.batch, self.steps, self.warmup = batch, steps, warmup
+        dev = torch.device("cuda:0")
+        sc = batch.scoring
+        self.scoring = sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, sw.PREC_INT16,
+                                       sw.KERNEL_INTER, max_read_len)
+        self.stream = torch.cuda.current_stream()
+        # references resident in HBM (outside the timed region)
+        self.refs = sw.RefSet.from_codes(torch.from_numpy(batch.ref_codes).to(dev), batch.ref_off, batch.ref_len)
+        # inputs resident in HBM: read codes and CAL arrays
+        self.read_codes = torch.from_numpy(batch.read_codes).to(dev)
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
+        self.db = sw.DeviceBatch(torch.empty((self.read_codes.numel() + 15) // 16, dtype=torch.int32, device=dev),
+                                 t(batch.read_off // 16, torch.int64), t(batch.read_len, torch.int32),
+                                 t(batch.cal_ptr, torch.int64), t(batch.cal_pos, torch.int64),
+                                 t(batch.cal_ref, torch.int16), t(batch.strand, torch.uint8))
+        db = self.db
+        self.out = sw.Outputs(db.n_cals, dev)
+        self.ws = torch.empty(sw.workspace_bytes(db.n_reads, db.n_cals, self.scoring), dtype=torch.uint8, device=dev)
+        self.bs = torch.empty(db.n_reads * batch.n_refs, dtype=torch.int32, device=dev)
+        self.bl = torch.empty(db.n_reads * batch.n_refs, dtype=torch.int64, device=dev)
+        self.nt = torch.empty(db.n_reads * batch.n_refs, dtype=torch.int32, device=dev)
+        self.ctx = sw.Context(db.n_reads, db.n_cals)
+        self.cells = cells_of(batch)
+
+    def step(self, batched, k_events=None):
+        sw, db, L, st = self.sw, self.db, self.sw.lib(), self.stream
+        assert L.sw_pack_2bit(sw._ptr(self.read_codes), self.read_codes.numel(), sw._ptr(db.reads2bit),
+                              sw._stream(st)) == 0
+        if k_events is not None:
+            k_events[0].record(st)
+        if batched:
+            self.ctx.align(db, self.refs, self.scoring, self.out, st)
+        else:
+            sw.align_batch(db, self.refs, self.scoring, self.out, self.ws, st)
+        if k_events is not None:
+            k_events[1].record(st)
+        assert L.sw_reduce_best(sw._ptr(db.cal_ptr), sw._ptr(db.cal_ref), db.n_reads, self.batch.n_refs,
+                                sw._ptr(self.out.score), sw._ptr(self.bs), sw._ptr(self.bl), sw._ptr(self.nt),
+                                sw._stream(st)) == 0
+
+    def timed(self, batched):
+        torch = self.torch
+        for _ in range(self.warmup):
+            self.step(batched)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(self.steps)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(self.stream)
+        for k in range(self.steps):
+            self.step(batched, ev[k])
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / self.steps, float(np.mean([a.elapsed_time(b) for a, b in ev])), wall
+
+    def run(self):
+        torch = self.torch
+        plain_ms, plain_kern, _ = self.timed(False)
+        plain = (self.out.score.clone(), self.out.ref_end.clone(), self.out.read_end.clone())
+        batched_ms, batched_kern, wall = self.timed(True)
+        same = bool(torch.equal(plain[0], self.out.score) and torch.equal(plain[1], self.out.ref_end)
+                    and torch.equal(plain[2], self.out.read_end))
+        best = self.bs.view(self.db.n_reads, self.batch.n_refs).max(dim=1).values
+        aligned = float((best >= ALIGNED_THRESHOLD).float().mean().item())
+        g = lambda ms: round(self.cells / (ms * 1e-3) / 1e9, 1)
+        return {"plain_ms": plain_ms, "plain_kern_ms": plain_kern, "batched_ms": batched_ms,
+                "batched_kern_ms": batched_kern, "wall": wall, "plain_gcups": g(plain_ms),
+                "batched_gcups": g(batched_ms), "plain_equals_batched": same, "aligned_fraction": aligned,
+                "plan": self.ctx.last_plan()}
+
+    def free(self):
+        self.ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--reads", type=int, default=1_000_000)
+    ap.add_argument("--config3-reads", type=int, default=2_000_000,
+                    help="reads of the uneven-length leg (0 skips it)")
+    ap.add_argument("--config3-band", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -108,95 +213,51 @@ def main():
 
     import torch
 
-    import paper_1805_00106_amd as sw
     from paper_1805_00106_amd import workloads as wl
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     t_gen = time.perf_counter()
     batch = wl.config2(n_reads=args.reads)
     t_gen = time.perf_counter() - t_gen
-    sc = batch.scoring
-    scoring = sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, sw.PREC_INT16,
-                              sw.KERNEL_INTER, int(batch.read_len.max()))
-    stream = torch.cuda.current_stream()
-
-    # references resident in HBM (outside the timed region)
-    refs = sw.RefSet.from_codes(torch.from_numpy(batch.ref_codes).to(dev), batch.ref_off, batch.ref_len)
-    # inputs resident in HBM: read codes and CAL arrays
-    read_codes = torch.from_numpy(batch.read_codes).to(dev)
-    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
-    db = sw.DeviceBatch(torch.empty((read_codes.numel() + 15) // 16, dtype=torch.int32, device=dev),
-                        t(batch.read_off // 16, torch.int64), t(batch.read_len, torch.int32),
-                        t(batch.cal_ptr, torch.int64), t(batch.cal_pos, torch.int64), t(batch.cal_ref, torch.int16),
-                        t(batch.strand, torch.uint8))
-    out = sw.Outputs(db.n_cals, dev)
-    ws = torch.empty(sw.workspace_bytes(db.n_reads, db.n_cals, scoring), dtype=torch.uint8, device=dev)
-    bs = torch.empty(db.n_reads * batch.n_refs, dtype=torch.int32, device=dev)
-    bl = torch.empty(db.n_reads * batch.n_refs, dtype=torch.int64, device=dev)
-    nt = torch.empty(db.n_reads * batch.n_refs, dtype=torch.int32, device=dev)
-    L = sw.lib()
-    import ctypes
-
-    def step(k_events=None):
-        rc = L.sw_pack_2bit(sw._ptr(read_codes), read_codes.numel(), sw._ptr(db.reads2bit), sw._stream(stream))
-        assert rc == 0
-        if k_events is not None:
-            k_events[0].record(stream)
-        sw.align_batch(db, refs, scoring, out, ws, stream)
-        if k_events is not None:
-            k_events[1].record(stream)
-        rc = L.sw_reduce_best(sw._ptr(db.cal_ptr), sw._ptr(db.cal_ref), db.n_reads, batch.n_refs,
-                              sw._ptr(out.score), sw._ptr(bs), sw._ptr(bl), sw._ptr(nt), sw._stream(stream))
-        assert rc == 0
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for k in range(args.steps):
-        step(ev[k])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = e0.elapsed_time(e1) / args.steps
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    leg = Leg(batch, int(batch.read_len.max()), args.steps, args.warmup)
+    r2 = leg.run()
+    parity = None if args.no_parity else parity_sample(batch, leg.out)
+    n_reads, n_cals, cells = leg.db.n_reads, leg.db.n_cals, leg.cells
+    leg.free()
+    del leg
 
     if args.calib_copy_mib:
-        src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.int32, device=dev)
+        src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             torch.add(src, 0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
-    cells = cells_of(batch)
+    c3 = None
+    if args.config3_reads:
+        b3 = wl.config3(n_reads=args.config3_reads, band=args.config3_band)
+        leg3 = Leg(b3, 250, max(3, args.steps // 4), 1)
+        r3 = leg3.run()
+        p3 = None if args.no_parity else parity_sample(b3, leg3.out, n=100)
+        c3 = {"workload": f"config3: same reference, {b3.n_reads} reads with L uniform 75..250, geometric CALs "
+                          f"(mean 8, cap 64), band {args.config3_band}, both strands, int16",
+              "cals": b3.n_cals, "cells": leg3.cells,
+              "plain_gcups": r3["plain_gcups"], "batched_gcups": r3["batched_gcups"],
+              "plain_ms_per_step": round(r3["plain_ms"], 3), "batched_ms_per_step": round(r3["batched_ms"], 3),
+              "batched_reads_per_s": round(b3.n_reads / (r3["batched_ms"] * 1e-3), 1),
+              "speedup_batched_vs_plain": round(r3["plain_ms"] / r3["batched_ms"], 3),
+              "plain_equals_batched": r3["plain_equals_batched"], "parity_sample_ok": p3, "plan": r3["plan"]}
+        leg3.free()
+        del leg3
+
+    step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
     gcups = cells / (step_ms * 1e-3) / 1e9
-    best = bs.view(db.n_reads, batch.n_refs).max(dim=1).values
-    aligned = float((best >= ALIGNED_THRESHOLD).float().mean().item())
-
-    parity = None
-    if not args.no_parity:
-        from oracle import oracle as orc
-        rng = np.random.default_rng(7)
-        idx = np.sort(rng.choice(batch.n_reads, min(300, batch.n_reads), replace=False))
-        sub = batch.subset_reads(idx)
-        s, r, e, _ = orc.align_batch(sub, n_threads=min(16, os.cpu_count() or 1))
-        sel = np.concatenate([np.arange(batch.cal_ptr[i], batch.cal_ptr[i + 1]) for i in idx])
-        slots = np.stack([2 * sel, 2 * sel + 1], 1).reshape(-1)
-        gs, gr, ge = (out.score.cpu().numpy()[slots], out.ref_end.cpu().numpy()[slots],
-                      out.read_end.cpu().numpy()[slots])
-        parity = bool(np.array_equal(gs, s) and np.array_equal(gr, r) and np.array_equal(ge, e))
-
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
     traffic = load_traffic("inter16", "config2")
     roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_INT16_TOPS, 2),
             "unit": "Tops/s (int16 lane-ops)", "frac": round(achieved / PEAK_INT16_TOPS, 4), "traffic": traffic,
-            "kernel": "k_inter16", "kernel_ms": round(kern_ms, 3),
+            "kernel": "k_inter16_queue", "kernel_ms": round(kern_ms, 3),
             "kernel_gcups": round(cells / (kern_ms * 1e-3) / 1e9, 1),
             "gcups_peak": round(PEAK_INT16_TOPS * 1e12 / OPS_PER_CELL / 1e9, 1)}
     res = {
@@ -205,13 +266,19 @@ def main():
         "vs_baseline": None, "dtype": "int16", "data": "synthetic",
         "config": {"workload": "config2: 100 Mbp reference (5% planted repeats), 1M x 100 bp reads, "
                                "Poisson(6)+1 CALs/read, band 32, both strands, int16",
-                   "reads": db.n_reads, "cals": db.n_cals, "tasks": 2 * db.n_cals, "cells": cells,
-                   "path": "plain (one launch per batch)"},
-        "reads_per_s": round(db.n_reads / (step_ms * 1e-3), 1),
-        "aligned_fraction": round(aligned, 4), "aligned_threshold": ALIGNED_THRESHOLD,
-        "wall_s_timed": round(wall, 3), "gen_s": round(t_gen, 1), "parity_sample_ok": parity,
+                   "reads": n_reads, "cals": n_cals, "tasks": 2 * n_cals, "cells": cells,
+                   "path": "batched (length bins, persistent queue, HIP graph)", "plan": r2["plan"]},
+        "reads_per_s": round(n_reads / (step_ms * 1e-3), 1),
+        "plain": {"gcups": r2["plain_gcups"], "ms_per_step": round(r2["plain_ms"], 3),
+                  "reads_per_s": round(n_reads / (r2["plain_ms"] * 1e-3), 1),
+                  "kernel_ms": round(r2["plain_kern_ms"], 3)},
+        "plain_equals_batched": r2["plain_equals_batched"],
+        "aligned_fraction": round(r2["aligned_fraction"], 4), "aligned_threshold": ALIGNED_THRESHOLD,
+        "wall_s_timed": round(r2["wall"], 3), "gen_s": round(t_gen, 1), "parity_sample_ok": parity,
         "roofline": roof,
     }
+    if c3:
+        res["config3"] = c3
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(batch)
     print(json.dumps(res))

@@ -194,7 +194,8 @@ int sw_align_batch_ctx(sw_ctx_t *ctx, const uint32_t *reads2bit, const int64_t *
                        const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref,
                        const uint8_t *strand, int64_t n_cals, const sw_scoring_t *sc, int32_t *score,
                        int64_t *ref_end, int16_t *read_end, sw_stream_t stream);
-/* Invalid task slots seen by this context; synchronises the context's device. */
+/* Invalid task slots of the last sw_align_batch_ctx call on this context;
+ * synchronises the context's device. */
 int sw_ctx_error_count(sw_ctx_t *ctx, int64_t *n_invalid);
 /* Text description of the last plan used (bins, tiles, kernel variants). */
 const char *sw_ctx_last_plan(sw_ctx_t *ctx);

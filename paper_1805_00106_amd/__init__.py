@@ -15,7 +15,7 @@ import torch  # load torch's HIP runtime before the library so both share it
 
 __all__ = [
     "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
-    "reduce_best", "classify", "error_count", "SwError",
+    "reduce_best", "classify", "error_count", "SwError", "Context", "Outputs",
     "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
     "MAX_READ_LEN", "MAX_REFS",
 ]
@@ -220,6 +220,48 @@ def classify(best_score: torch.Tensor, threshold: int, stream=None) -> torch.Ten
     _check(lib().sw_classify(_ptr(best_score.contiguous()), n, k, threshold, _ptr(cls), _stream(stream)),
            "sw_classify")
     return cls
+
+
+class Context:
+    """Batched execution context (sw_ctx_*): length-binned persistent work queue,
+    HIP graphs per call shape and an autotuned binning plan.  Same outputs as
+    align_batch, bit for bit."""
+
+    def __init__(self, max_reads: int, max_cals: int, device: int = 0, use_graph: bool = True,
+                 autotune: bool = True, tune_cache: Optional[str] = None):
+        self._h = ctypes.c_void_p()
+        self._cache = tune_cache.encode() if tune_cache else None
+        opts = _CtxOpts(device, max_reads, max_cals, int(use_graph), int(autotune), self._cache)
+        _check(lib().sw_ctx_create(ctypes.byref(opts), ctypes.byref(self._h)), "sw_ctx_create")
+
+    def close(self):
+        if self._h:
+            lib().sw_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def align(self, db: DeviceBatch, refs: RefSet, sc: Scoring, out: Optional[Outputs] = None, stream=None):
+        if out is None:
+            out = Outputs(db.n_cals, db.cal_pos.device)
+        rc = lib().sw_align_batch_ctx(self._h, _ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len),
+                                      db.n_reads, refs.c, _ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref),
+                                      _ptr(db.strand), db.n_cals, ctypes.byref(sc), _ptr(out.score),
+                                      _ptr(out.ref_end), _ptr(out.read_end), _stream(stream))
+        _check(rc, "sw_align_batch_ctx")
+        return out
+
+    def error_count(self) -> int:
+        v = ctypes.c_int64(0)
+        _check(lib().sw_ctx_error_count(self._h, ctypes.byref(v)), "sw_ctx_error_count")
+        return int(v.value)
+
+    def last_plan(self) -> str:
+        return lib().sw_ctx_last_plan(self._h).decode()
 
 
 def error_count(reset: bool = False) -> int:

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sw_device.h"
 #include "sw_launch.h"
 
@@ -192,8 +194,8 @@ struct TileIter {
   int64_t n_tiles;
 };
 
-__device__ __forceinline__ bool next_tile(const AlignArgs &A, TileIter &it, int64_t &first, int &count) {
-  int64_t t;
+__device__ __forceinline__ bool next_tile(const AlignArgs &A, TileIter &it, int64_t &first, int &count,
+                                          int64_t &t) {
   if (A.queue) {
     int v = 0;
     if (threadIdx.x == 0) v = atomicAdd(A.queue, 1);
@@ -394,6 +396,42 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
 // every substitution is -256, so those rows only decrease and are never
 // reported.  Columns past the lane's window use a table of 0x8000 (a wall).
 
+// One tile of up to 64 CALs (task positions [first, first + count)).
+template <int R>
+__device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off, const int64_t *rt_len,
+                                       uint32_t *win, uint32_t *rdw, uint2 *scr, int lane, int64_t first,
+                                       int count) {
+  LaneTask t{};
+  if (lane < count) {
+    const int64_t pos = first + lane;
+    const int64_t c = A.order ? (int64_t)A.order[pos] : pos;
+    t = load_task(A, rt_len, c, 3);
+  }
+  const int L = t.L, W = t.W;
+  const int Lmax = wave_max(L);
+  if (Lmax == 0) return;
+  const int Wmax = wave_max(W);
+  const int Wmin = wave_min(L > 0 ? W : 0x7fffffff);
+  stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
+
+  const DpConst &K = A.k;
+  uint64_t best_f = 0, best_r = 0;
+  const int nstrips = (Lmax + R - 1) / R;
+  if (nstrips == 1) {
+    strip16<R, true, true>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+  } else {
+    strip16<R, true, false>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    for (int s = 1; s + 1 < nstrips; ++s)
+      strip16<R, false, false>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
+    strip16<R, false, true>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
+  }
+  if (L > 0) {
+    if (t.mask & 1) write_result(A, 2 * t.c, best_f, t.ws);
+    if (t.mask & 2) write_result(A, 2 * t.c + 1, best_r, t.ws);
+  }
+}
+
+// Plain launch: fixed 64-CAL tiles, static striding over a persistent grid.
 template <int R>
 __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
@@ -403,38 +441,35 @@ __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTabl
   uint32_t *win = smem;
   uint32_t *rdw = smem + A.wwords * 64;
   uint2 *scr = A.scratch + (size_t)blockIdx.x * (size_t)A.wcap * 64;
-  const DpConst K = A.k;
-
-  TileIter it{(int64_t)blockIdx.x, A.n_tiles_dev ? (int64_t)*A.n_tiles_dev : (A.n_tasks + 63) / 64};
-  int64_t first;
+  TileIter it{(int64_t)blockIdx.x, (A.n_tasks + 63) / 64};
+  int64_t first, ti;
   int count;
-  while (next_tile(A, it, first, count)) {
-    LaneTask t{};
-    if (lane < count) {
-      int64_t pos = first + lane;
-      int64_t c = A.order ? (int64_t)A.order[pos] : pos;
-      t = load_task(A, rt_len, c, 3);
-    }
-    const int L = t.L, W = t.W;
-    const int Lmax = wave_max(L);
-    if (Lmax == 0) continue;
-    const int Wmax = wave_max(W);
-    const int Wmin = wave_min(L > 0 ? W : 0x7fffffff);
-    stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
+  while (next_tile(A, it, first, count, ti)) tile16<R>(A, rt_off, rt_len, win, rdw, scr, lane, first, count);
+}
 
-    uint64_t best_f = 0, best_r = 0;
-    const int nstrips = (Lmax + R - 1) / R;
-    if (nstrips == 1) {
-      strip16<R, true, true>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
-    } else {
-      strip16<R, true, false>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
-      for (int s = 1; s + 1 < nstrips; ++s)
-        strip16<R, false, false>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
-      strip16<R, false, true>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
-    }
-    if (L > 0) {
-      if (t.mask & 1) write_result(A, 2 * t.c, best_f, t.ws);
-      if (t.mask & 2) write_result(A, 2 * t.c + 1, best_r, t.ws);
+// Batched launch: tiles (each with its own strip height) popped from a device
+// work queue, longest reads first.
+__global__ __launch_bounds__(64) void k_inter16_queue(const AlignArgs A, const RefTable T) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const int lane = threadIdx.x;
+  load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
+  uint32_t *win = smem;
+  uint32_t *rdw = smem + A.wwords * 64;
+  uint2 *scr = A.scratch + (size_t)blockIdx.x * (size_t)A.wcap * 64;
+  TileIter it{(int64_t)blockIdx.x, (int64_t)*A.n_tiles_dev};
+  int64_t first, ti;
+  int count;
+  while (next_tile(A, it, first, count, ti)) {
+    switch (A.tile_strips[ti]) {
+#define SW_Q16_CASE(RR)                                                 \
+  case RR:                                                              \
+    tile16<RR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
+    break;
+      SW_QUEUE16_STRIPS(SW_Q16_CASE)
+#undef SW_Q16_CASE
+      default:
+        break;
     }
   }
 }
@@ -446,6 +481,95 @@ __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTabl
 // library accepts, so no tile change happens inside a sweep).
 
 template <int R>
+__device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off, const int64_t *rt_len,
+                                       uint32_t *win, uint32_t *rdw, uint2 *scr, int lane, int64_t first,
+                                       int count) {
+  const DpConst &K = A.k;
+  LaneTask t{};
+  int h = 0;
+  if (lane < count) {
+    const int64_t pos = first + lane;
+    const int64_t tk = A.order ? (int64_t)A.order[pos] : pos;
+    h = (int)(tk & 1);
+    t = load_task(A, rt_len, tk >> 1, 1 << h);
+  }
+  const int L = t.L, W = t.W;
+  const int Lmax = wave_max(L);
+  if (Lmax == 0) return;
+  const int Wmax = wave_max(W);
+  stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
+
+  uint64_t best = 0;
+  const int nstrips = (Lmax + R - 1) / R;
+  for (int s = 0; s < nstrips; ++s) {
+    const int r0 = s * R;
+    int32_t q[R], Hl[R], E[R], M[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = r0 + r;
+      if (i < L) {
+        q[r] = h == 0 ? (int32_t)base_at(rdw, lane, i) : (int32_t)(3u - base_at(rdw, lane, L - 1 - i));
+      } else {
+        q[r] = 4;  // never equal to a window code: a mismatch-only row
+      }
+      Hl[r] = 4096;
+      E[r] = 4096 - K.goe_e32;
+      M[r] = 0;
+    }
+    int32_t hup_prev = 4096;
+    uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
+    if (s > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      pf0 = scr[lane];
+      if (Wmax > 1) pf1 = scr[64 + lane];
+    }
+    uint32_t wd = 0;
+    for (int c = 0; c < Wmax; ++c) {
+      const int32_t zt = 4095 - c;
+      if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
+      int32_t w = (int32_t)((wd >> (2 * (c & 15))) & 3u);
+      if (c >= W) w = 5;  // past the window: never matches
+      int32_t hup, F;
+      if (s == 0) {
+        hup = zt;
+        F = zt - K.goe_f32;
+      } else {
+        const uint2 cur = pf0;
+        pf0 = pf1;
+        if (c + 2 < Wmax) pf1 = scr[(c + 2) * 64 + lane];
+        hup = (int32_t)cur.x;
+        F = (int32_t)cur.y;
+      }
+      int32_t Hd = hup_prev;
+      hup_prev = hup;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int32_t sub = q[r] == w ? K.sm32 : K.sx32;
+        int32_t H = max(max(Hd + sub, E[r]), F);
+        H = max(H, zt);
+        M[r] = max(M[r], H);
+        E[r] = max(E[r] - K.ge_e32, H - K.goe_e32);
+        F = max(F - K.ge_f32, H - K.goe_f32);
+        Hd = Hl[r];
+        Hl[r] = H;
+      }
+      if (s + 1 < nstrips) scr[c * 64 + lane] = make_uint2((uint32_t)Hl[R - 1], (uint32_t)F);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = r0 + r;
+      int32_t v = M[r] >> 12;
+      if (i < L && v > 0) {
+        uint64_t kk = cell_key(v, 4095 - (M[r] & 4095), i);
+        best = kk > best ? kk : best;
+      }
+    }
+    if (s + 1 < nstrips) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  }
+  if (L > 0) write_result(A, 2 * t.c + h, best, t.ws);
+}
+
+template <int R>
 __global__ __launch_bounds__(64) void k_inter32(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
@@ -454,94 +578,34 @@ __global__ __launch_bounds__(64) void k_inter32(const AlignArgs A, const RefTabl
   uint32_t *win = smem;
   uint32_t *rdw = smem + A.wwords * 64;
   uint2 *scr = A.scratch + (size_t)blockIdx.x * (size_t)A.wcap * 64;
-  const DpConst K = A.k;
-
-  TileIter it{(int64_t)blockIdx.x, A.n_tiles_dev ? (int64_t)*A.n_tiles_dev : (A.n_tasks + 63) / 64};
-  int64_t first;
+  TileIter it{(int64_t)blockIdx.x, (A.n_tasks + 63) / 64};
+  int64_t first, ti;
   int count;
-  while (next_tile(A, it, first, count)) {
-    LaneTask t{};
-    int h = 0;
-    if (lane < count) {
-      int64_t pos = first + lane;
-      int64_t tk = A.order ? (int64_t)A.order[pos] : pos;
-      h = (int)(tk & 1);
-      t = load_task(A, rt_len, tk >> 1, 1 << h);
-    }
-    const int L = t.L, W = t.W;
-    const int Lmax = wave_max(L);
-    if (Lmax == 0) continue;
-    const int Wmax = wave_max(W);
-    stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
+  while (next_tile(A, it, first, count, ti)) tile32<R>(A, rt_off, rt_len, win, rdw, scr, lane, first, count);
+}
 
-    uint64_t best = 0;
-    const int nstrips = (Lmax + R - 1) / R;
-    for (int s = 0; s < nstrips; ++s) {
-      const int r0 = s * R;
-      int32_t q[R], Hl[R], E[R], M[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = r0 + r;
-        if (i < L) {
-          q[r] = h == 0 ? (int32_t)base_at(rdw, lane, i) : (int32_t)(3u - base_at(rdw, lane, L - 1 - i));
-        } else {
-          q[r] = 4;  // never equal to a window code: a mismatch-only row
-        }
-        Hl[r] = 4096;
-        E[r] = 4096 - K.goe_e32;
-        M[r] = 0;
-      }
-      int32_t hup_prev = 4096;
-      uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
-      if (s > 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        pf0 = scr[lane];
-        if (Wmax > 1) pf1 = scr[64 + lane];
-      }
-      uint32_t wd = 0;
-      for (int c = 0; c < Wmax; ++c) {
-        const int32_t zt = 4095 - c;
-        if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
-        int32_t w = (int32_t)((wd >> (2 * (c & 15))) & 3u);
-        if (c >= W) w = 5;  // past the window: never matches
-        int32_t hup, F;
-        if (s == 0) {
-          hup = zt;
-          F = zt - K.goe_f32;
-        } else {
-          const uint2 cur = pf0;
-          pf0 = pf1;
-          if (c + 2 < Wmax) pf1 = scr[(c + 2) * 64 + lane];
-          hup = (int32_t)cur.x;
-          F = (int32_t)cur.y;
-        }
-        int32_t Hd = hup_prev;
-        hup_prev = hup;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int32_t sub = q[r] == w ? K.sm32 : K.sx32;
-          int32_t H = max(max(Hd + sub, E[r]), F);
-          H = max(H, zt);
-          M[r] = max(M[r], H);
-          E[r] = max(E[r] - K.ge_e32, H - K.goe_e32);
-          F = max(F - K.ge_f32, H - K.goe_f32);
-          Hd = Hl[r];
-          Hl[r] = H;
-        }
-        if (s + 1 < nstrips) scr[c * 64 + lane] = make_uint2((uint32_t)Hl[R - 1], (uint32_t)F);
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = r0 + r;
-        int32_t v = M[r] >> 12;
-        if (i < L && v > 0) {
-          uint64_t kk = cell_key(v, 4095 - (M[r] & 4095), i);
-          best = kk > best ? kk : best;
-        }
-      }
-      if (s + 1 < nstrips) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+__global__ __launch_bounds__(64) void k_inter32_queue(const AlignArgs A, const RefTable T) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const int lane = threadIdx.x;
+  load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
+  uint32_t *win = smem;
+  uint32_t *rdw = smem + A.wwords * 64;
+  uint2 *scr = A.scratch + (size_t)blockIdx.x * (size_t)A.wcap * 64;
+  TileIter it{(int64_t)blockIdx.x, (int64_t)*A.n_tiles_dev};
+  int64_t first, ti;
+  int count;
+  while (next_tile(A, it, first, count, ti)) {
+    switch (A.tile_strips[ti]) {
+#define SW_Q32_CASE(RR)                                                 \
+  case RR:                                                              \
+    tile32<RR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
+    break;
+      SW_QUEUE32_STRIPS(SW_Q32_CASE)
+#undef SW_Q32_CASE
+      default:
+        break;
     }
-    if (L > 0) write_result(A, 2 * t.c + h, best, t.ws);
   }
 }
 
@@ -635,6 +699,124 @@ __global__ void k_classify(const int32_t *__restrict__ best_score, int32_t n_rea
   cls[r] = top < threshold ? -1 : (cnt > 1 ? -2 : arg);
 }
 
+// --------------------------------------------------------------------------- batched planning
+//
+// Tasks are binned by read length so that the lanes of a tile share their
+// strip count; bins are laid out longest first (largest work first onto the
+// queue) and cut into tiles of at most 64 tasks.  Every step runs on the
+// device, so the whole batched call needs no host synchronisation and can be
+// captured into a HIP graph.
+
+__device__ __forceinline__ int task_bin(const int32_t *cal_read, const int32_t *read_len, int32_t n_reads,
+                                        int64_t c, const BinParams &P) {
+  const int32_t r = cal_read[c];
+  if (r < 0 || r >= n_reads) return P.nb;
+  const int32_t L = read_len[r];
+  if (L < 1 || L > P.max_read_len) return P.nb;
+  return (L - 1) / P.bin_width;
+}
+
+__global__ void k_bin_count(const int32_t *__restrict__ cal_read, const int32_t *__restrict__ read_len,
+                            int32_t n_reads, int64_t n_tasks, int32_t *__restrict__ bin_count, const BinParams P) {
+  extern __shared__ int32_t hist[];
+  for (int i = threadIdx.x; i <= P.nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_tasks;
+       k += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[task_bin(cal_read, read_len, n_reads, k / P.per_cal, P)], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i <= P.nb; i += blockDim.x)
+    if (hist[i]) atomicAdd(&bin_count[i], hist[i]);
+}
+
+// One thread: bin order, bin offsets, tile offsets, strip height per bin, and
+// the queue reset.
+__global__ void k_bin_plan(const int32_t *__restrict__ bin_count, int32_t *__restrict__ bin_off,
+                           int32_t *__restrict__ bin_cursor, int32_t *__restrict__ tile_off,
+                           int32_t *__restrict__ tile_bin, int32_t *__restrict__ strip_of_bin,
+                           int32_t *__restrict__ n_tiles, int32_t *__restrict__ queue, const BinParams P) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t pos = 0, tiles = 0;
+  for (int k = 0; k <= P.nb; ++k) {
+    const int b = k == P.nb ? P.nb : (P.descending ? P.nb - 1 - k : k);
+    bin_off[b] = pos;
+    bin_cursor[b] = pos;
+    tile_off[k] = tiles;
+    tile_bin[k] = b;
+    const int32_t cnt = bin_count[b];
+    pos += cnt;
+    tiles += (cnt + 63) / 64;
+    int best = P.strips[0];
+    if (b < P.nb) {
+      const int Lb = min((b + 1) * P.bin_width, P.max_read_len);
+      int best_cost = 0x7fffffff;
+      for (int j = 0; j < P.n_strips; ++j) {
+        const int R = P.strips[j];
+        const int cost = (Lb + R - 1) / R * R;
+        if (cost < best_cost || (cost == best_cost && R > best)) {
+          best_cost = cost;
+          best = R;
+        }
+      }
+    }
+    strip_of_bin[b] = best;
+  }
+  tile_off[P.nb + 1] = tiles;
+  *n_tiles = tiles;
+  *queue = 0;
+}
+
+__global__ void k_bin_scatter(const int32_t *__restrict__ cal_read, const int32_t *__restrict__ read_len,
+                              int32_t n_reads, int64_t n_tasks, int32_t *__restrict__ bin_cursor,
+                              int32_t *__restrict__ order, const BinParams P) {
+  extern __shared__ int32_t sh[];
+  int32_t *cnt = sh;                // [nb+1]
+  int32_t *base = sh + (P.nb + 1);  // [nb+1]
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // the block handles the tasks k = k0 + j*stride, one pass per j
+  for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x; k0 < n_tasks; k0 += stride) {
+    for (int i = threadIdx.x; i <= P.nb; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const int64_t k = k0 + threadIdx.x;
+    int b = -1;
+    if (k < n_tasks) {
+      b = task_bin(cal_read, read_len, n_reads, k / P.per_cal, P);
+      atomicAdd(&cnt[b], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= P.nb; i += blockDim.x) {
+      base[i] = cnt[i] ? atomicAdd(&bin_cursor[i], cnt[i]) : 0;
+      cnt[i] = 0;
+    }
+    __syncthreads();
+    if (b >= 0) {
+      const int local = atomicAdd(&cnt[b], 1);
+      order[base[b] + local] = (int32_t)k;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_tile_fill(const int32_t *__restrict__ bin_count, const int32_t *__restrict__ bin_off,
+                            const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_bin,
+                            const int32_t *__restrict__ strip_of_bin, const int32_t *__restrict__ n_tiles,
+                            int32_t *__restrict__ tiles, int32_t *__restrict__ tile_len,
+                            int32_t *__restrict__ tile_strips, int32_t max_tiles, const BinParams P) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= *n_tiles || t >= max_tiles) return;
+  int lo = 0, hi = P.nb;  // find k with tile_off[k] <= t < tile_off[k+1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_off[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int b = tile_bin[lo];
+  const int32_t j = t - tile_off[lo];
+  tiles[t] = bin_off[b] + 64 * j;
+  tile_len[t] = min(64, bin_count[b] - 64 * j);
+  tile_strips[t] = strip_of_bin[b];
+}
+
 // --------------------------------------------------------------------------- launchers
 
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -688,6 +870,42 @@ hipError_t launch_inter(bool int16, const AlignArgs &A, const RefTable &T, int g
   } else {
     switch (A.strip_rows) { SW_INTER32_STRIPS(SW_INTER32_CASE) default: return hipErrorInvalidValue; }
   }
+}
+
+hipError_t launch_batch_plan(const BatchBufs &B, const int32_t *read_len, int32_t n_reads, int64_t n_tasks,
+                             const BinParams &P, hipStream_t st) {
+  if (n_tasks == 0) return hipSuccess;
+  const int nbins = P.nb + 1;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nbins, 256)), dim3(256), 0, st, B.bin_count, (int64_t)nbins, 0);
+  const int grid = (int)std::min<int64_t>(1024, blocks_for(n_tasks, 256));
+  hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), nbins * sizeof(int32_t), st, B.cal_read, read_len,
+                     n_reads, n_tasks, B.bin_count, P);
+  hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, st, B.bin_count, B.bin_off, B.bin_cursor, B.tile_off,
+                     B.tile_bin, B.strip_of_bin, B.n_tiles, B.queue, P);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 2 * nbins * sizeof(int32_t), st, B.cal_read, read_len,
+                     n_reads, n_tasks, B.bin_cursor, B.order, P);
+  const int64_t max_tiles = (n_tasks + 63) / 64 + nbins;
+  hipLaunchKernelGGL(k_tile_fill, dim3(blocks_for(max_tiles, 256)), dim3(256), 0, st, B.bin_count, B.bin_off,
+                     B.tile_off, B.tile_bin, B.strip_of_bin, B.n_tiles, B.tiles, B.tile_len, B.tile_strips,
+                     (int32_t)max_tiles, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st) {
+  size_t lds = (size_t)(A.wwords + A.rwords) * 64 * sizeof(uint32_t);
+  if (int16)
+    hipLaunchKernelGGL(k_inter16_queue, dim3(grid), dim3(64), lds, st, A, T);
+  else
+    hipLaunchKernelGGL(k_inter32_queue, dim3(grid), dim3(64), lds, st, A, T);
+  return hipGetLastError();
+}
+
+int queue_blocks_per_cu(bool int16) {
+  int n = 0;
+  const void *f = int16 ? reinterpret_cast<const void *>(&k_inter16_queue)
+                        : reinterpret_cast<const void *>(&k_inter32_queue);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, 8192) != hipSuccess) return 0;
+  return n;
 }
 
 hipError_t launch_reduce(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,

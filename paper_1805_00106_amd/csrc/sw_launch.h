@@ -7,10 +7,32 @@
 #include "sw_device.h"
 
 // Strip heights (read rows held in registers per lane) compiled for each kernel.
-#define SW_INTER16_STRIPS(X) X(24) X(32) X(40) X(48) X(50) X(56)
+#define SW_INTER16_STRIPS(X) X(24) X(32) X(40) X(44) X(48) X(50)
 #define SW_INTER32_STRIPS(X) X(24) X(32) X(38) X(48)
+// Strip heights available to the batched (work-queue) kernels, ascending.
+#define SW_QUEUE16_STRIPS(X) X(24) X(32) X(40) X(44) X(48) X(50)
+#define SW_QUEUE32_STRIPS(X) X(24) X(32) X(40) X(48)
 
 namespace swk {
+
+// Parameters of the length binning of the batched path.
+struct BinParams {
+  int32_t nb;            // number of length bins; bin nb collects invalid tasks
+  int32_t bin_width;     // read lengths per bin
+  int32_t max_read_len;
+  int32_t per_cal;       // tasks per CAL: 1 (int16 pairs) or 2 (int32)
+  int32_t descending;    // 1: longest bin first
+  int32_t n_strips;      // compiled strip heights available
+  int32_t strips[16];    // ascending
+};
+
+// Device buffers of the batched path (owned by a context).
+struct BatchBufs {
+  int32_t *cal_read, *order;
+  int32_t *bin_count, *bin_off, *bin_cursor, *tile_off, *tile_bin, *strip_of_bin;
+  int32_t *tiles, *tile_len, *tile_strips;
+  int32_t *n_tiles, *queue;
+};
 
 hipError_t launch_pack(const uint8_t *codes, int64_t n, uint32_t *words, hipStream_t st);
 hipError_t launch_expand(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, int32_t *cal_read,
@@ -23,6 +45,10 @@ hipError_t launch_classify(const int32_t *bs, int32_t n_reads, int32_t n_refs, i
                            hipStream_t st);
 // Resident waves of the inter kernel with R strip rows on this device (occupancy query).
 int inter_blocks_per_cu(bool int16, int strip_rows);
+hipError_t launch_batch_plan(const BatchBufs &B, const int32_t *read_len, int32_t n_reads, int64_t n_tasks,
+                             const BinParams &P, hipStream_t st);
+hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
+int queue_blocks_per_cu(bool int16);
 // Address of the library's device-resident invalid-task counter on the current device.
 unsigned long long *error_counter();
 

@@ -1,0 +1,126 @@
+"""GPU parity of the batched context (length bins, persistent work queue, HIP
+graphs, autotuned plan): bit-exact against the oracle and against the plain
+one-launch path, including graph replays with eager work between them."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1805_00106_amd as sw
+from paper_1805_00106_amd import workloads as wl
+from tests.gpu_util import assert_same, gpu_align, oracle_align, scoring_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx_run(batch, precision, ctx=None, max_read_len=None, repeats=1):
+    refs = sw.RefSet.from_codes(torch.from_numpy(batch.ref_codes).cuda(), batch.ref_off, batch.ref_len)
+    db = sw.DeviceBatch.upload(batch)
+    sc = scoring_for(batch, precision, max_read_len=max_read_len)
+    own = ctx is None
+    if own:
+        ctx = sw.Context(max(batch.n_reads, 1), max(batch.n_cals, 1))
+    out = sw.Outputs(db.n_cals)
+    results = []
+    for _ in range(repeats):
+        out.score.fill_(-7)
+        out.ref_end.fill_(-7)
+        out.read_end.fill_(-7)
+        torch.cuda.synchronize()
+        ctx.align(db, refs, sc, out)
+        torch.cuda.synchronize()
+        results.append(dict(score=out.score.cpu().numpy(), ref_end=out.ref_end.cpu().numpy(),
+                            read_end=out.read_end.cpu().numpy()))
+    plan = ctx.last_plan()
+    if own:
+        ctx.close()
+    return results, plan
+
+
+@pytest.mark.parametrize("precision", [sw.PREC_INT16, sw.PREC_INT32])
+@pytest.mark.parametrize("seed", range(4))
+def test_ctx_random_ragged(seed, precision):
+    b = wl.random_small_batch(20 + seed, n_reads=120, read_len=(1, 120), band=12)
+    exp, _ = oracle_align(b)
+    res, plan = _ctx_run(b, precision, repeats=3)
+    for k, r in enumerate(res):
+        assert_same(r, exp, f"ctx seed {seed} replay {k} ({plan})")
+
+
+@pytest.mark.parametrize("band", [16, 32, 64])
+def test_ctx_config3_shape(band):
+    """Config 3 generator (L uniform 75..250, geometric CAL counts capped at 64)."""
+    b = wl.config3(n_reads=1200, band=band)
+    exp, _ = oracle_align(b)
+    res, plan = _ctx_run(b, sw.PREC_INT16, max_read_len=250, repeats=2)
+    for r in res:
+        assert_same(r, exp, f"config3 band {band} ({plan})")
+    assert "longest first" in plan or "shortest first" in plan
+
+
+def test_ctx_equals_plain_on_config2_shape():
+    b = wl.config2(n_reads=20000)
+    plain = gpu_align(b, sw.PREC_INT16, reduce=False)
+    res, plan = _ctx_run(b, sw.PREC_INT16, repeats=2)
+    for r in res:
+        assert_same(r, plain, f"ctx vs plain ({plan})")
+
+
+def test_ctx_invalid_cals_and_capacity():
+    b = wl.random_small_batch(30, n_reads=40, max_cals=3)
+    b.cal_pos = b.cal_pos.copy()
+    b.cal_ref = b.cal_ref.copy()
+    b.cal_pos[0] = b.ref_len[int(b.cal_ref[0])] + 3
+    b.cal_ref[1] = -1
+    exp, errs = oracle_align(b)
+    ctx = sw.Context(b.n_reads, b.n_cals)
+    res, _ = _ctx_run(b, sw.PREC_INT16, ctx=ctx)
+    assert_same(res[0], exp, "ctx invalid")
+    assert ctx.error_count() == errs > 0
+    small = sw.Context(1, 1)
+    with pytest.raises(sw.SwError) as ei:
+        _ctx_run(b, sw.PREC_INT16, ctx=small)
+    assert ei.value.code == -5
+    small.close()
+    ctx.close()
+
+
+def _prepare(batch):
+    refs = sw.RefSet.from_codes(torch.from_numpy(batch.ref_codes).cuda(), batch.ref_off, batch.ref_len)
+    db = sw.DeviceBatch.upload(batch)
+    return refs, db, sw.Outputs(db.n_cals)
+
+
+def _host(out):
+    torch.cuda.synchronize()
+    return dict(score=out.score.cpu().numpy(), ref_end=out.ref_end.cpu().numpy(), read_end=out.read_end.cpu().numpy())
+
+
+def test_ctx_shapes_change_and_graph_cache(tmp_path):
+    """One context, alternating shapes: graphs are captured per shape and replayed."""
+    cache = str(tmp_path / "tune.json")
+    ctx = sw.Context(5000, 60000, tune_cache=cache)
+    batches = [wl.random_small_batch(40 + k, n_reads=100 + 50 * k, read_len=(20, 200), band=16) for k in range(3)]
+    exps = [oracle_align(b)[0] for b in batches]
+    prepared = [_prepare(b) for b in batches]
+    plans = []
+    for rnd in range(2):
+        for b, exp, (refs, db, out) in zip(batches, exps, prepared):
+            out.score.fill_(-7)
+            ctx.align(db, refs, scoring_for(b, sw.PREC_INT16, max_read_len=200), out)
+            assert_same(_host(out), exp, f"round {rnd} {ctx.last_plan()}")
+            plans.append(ctx.last_plan())
+    ctx.close()
+    assert all("replay" in p for p in plans[3:]), plans
+    with open(cache) as f:
+        tuned = json.load(f)
+    assert tuned and all("bin_width" in v for v in tuned.values())
+    # a new context reads the cache and does not tune again
+    ctx2 = sw.Context(5000, 60000, tune_cache=cache)
+    refs, db, out = prepared[0]
+    ctx2.align(db, refs, scoring_for(batches[0], sw.PREC_INT16, max_read_len=200), out)
+    assert "tuned=cached" in ctx2.last_plan()
+    assert_same(_host(out), exps[0], "cached plan")
+    ctx2.close()
