@@ -200,6 +200,73 @@ int sw_ctx_error_count(sw_ctx_t *ctx, int64_t *n_invalid);
 /* Text description of the last plan used (bins, tiles, kernel variants). */
 const char *sw_ctx_last_plan(sw_ctx_t *ctx);
 
+/* ------------------------------------------------------------------ served */
+/*
+ * A server keeps a reference set resident, admits requests by their device
+ * memory footprint and packs chunks of every admitted request into each device
+ * step (continuous batching): a request that arrives while a step runs joins
+ * the next step as soon as arena memory frees up.  Each step runs the batched
+ * pipeline (sw_align_batch_ctx) and the Score Tracker reduction, and a request's
+ * results are bit-identical to sw_align_batch + sw_reduce_best on the request
+ * alone.  The paper's V2 streams reads and their CALs from host threads to the
+ * accelerator that holds the whole reference (sections 4.2, 4.3).
+ * One scheduler thread per server; submit, wait and info may be called from
+ * any thread.
+ */
+typedef struct sw_server sw_server_t;
+
+typedef struct {
+  int32_t device;
+  sw_scoring_t scoring;     /* scoring of every request (max_read_len bounds the reads) */
+  size_t memory_budget;     /* device bytes for admitted requests (>= 1 MiB); a pinned host
+                               mirror of the same size is allocated */
+  int32_t max_step_reads;   /* reads per device step; also the largest request in reads */
+  int64_t max_step_cals;    /* CALs per device step; also the most CALs of one read */
+  int32_t max_step_chunks;  /* request chunks per step, 1..4096 */
+  int32_t autotune;         /* 1: autotune the binning plan of each step shape class */
+} sw_server_opts_t;
+
+typedef struct {
+  int64_t steps, step_reads, step_cals; /* device steps run and their totals */
+  int64_t pending;                      /* submitted, not yet admitted */
+  int64_t in_flight_requests;           /* admitted, not yet done */
+  int64_t arena_used, arena_size;       /* bytes */
+} sw_server_stats_t;
+
+int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out);
+/* Set the resident references (device words stay owned by the caller and must
+ * outlive the server) and start serving.  Once only. */
+int sw_server_set_refs(sw_server_t *srv, const sw_refset_t *refs);
+/*
+ * Submit one request (host arrays, copied before the call returns):
+ *   read_codes     host uint8 [n_codes], base codes; read r starts at
+ *                  read_code_off[r], a multiple of 16
+ *   read_len       host [n_reads], 0..scoring.max_read_len
+ *   cal_ptr        host [n_reads+1] CSR (cal_ptr[0] = 0, cal_ptr[n_reads] = n_cals)
+ *   cal_pos, cal_ref, strand: host [n_cals], as for sw_align_batch
+ * Outputs (host, written when the request completes; keep them alive until then):
+ *   score, ref_end, read_end [2*n_cals] as for sw_align_batch;
+ *   best_score, best_slot, n_tied [n_reads*n_refs] as for sw_reduce_best (may be NULL).
+ * Returns SW_ERR_REJECTED if the request's footprint exceeds the memory budget,
+ * SW_ERR_INVALID_ARG for malformed inputs or a request with more reads than a
+ * step.  *req_id identifies the request.
+ */
+int sw_server_submit(sw_server_t *srv, const uint8_t *read_codes, int64_t n_codes, const int64_t *read_code_off,
+                     const int32_t *read_len, int32_t n_reads, const int64_t *cal_ptr, const int64_t *cal_pos,
+                     const int16_t *cal_ref, const uint8_t *strand, int64_t n_cals, int32_t *score,
+                     int64_t *ref_end, int16_t *read_end, int32_t *best_score, int64_t *best_slot,
+                     int32_t *n_tied, int64_t *req_id);
+/* Wait up to timeout_ms (-1: forever) for a request; *done = 1 when complete. */
+int sw_server_wait(sw_server_t *srv, int64_t req_id, int32_t timeout_ms, int32_t *done);
+/* State (0 pending, 1 admitted, 2 draining, 3 done) and steady-clock times in seconds. */
+int sw_server_request_info(sw_server_t *srv, int64_t req_id, int32_t *state, double *t_submit, double *t_admit,
+                           double *t_done);
+/* Forget a completed request. */
+int sw_server_release(sw_server_t *srv, int64_t req_id);
+int sw_server_stats(sw_server_t *srv, sw_server_stats_t *out);
+/* Drain every submitted request, then free the server. */
+int sw_server_destroy(sw_server_t *srv);
+
 /* ------------------------------------------------------------------ misc */
 const char *sw_strerror(int code);
 int sw_last_hip_error(void);

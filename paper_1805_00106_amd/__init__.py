@@ -15,7 +15,7 @@ import torch  # load torch's HIP runtime before the library so both share it
 
 __all__ = [
     "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
-    "reduce_best", "classify", "error_count", "SwError", "Context", "Outputs",
+    "reduce_best", "classify", "error_count", "SwError", "Context", "Outputs", "Server", "Request",
     "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
     "MAX_READ_LEN", "MAX_REFS",
 ]
@@ -56,6 +56,18 @@ class _RefSetC(ctypes.Structure):
                 ("n_refs", ctypes.c_int32)]
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("scoring", Scoring), ("memory_budget", ctypes.c_size_t),
+                ("max_step_reads", ctypes.c_int32), ("max_step_cals", ctypes.c_int64),
+                ("max_step_chunks", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("step_reads", ctypes.c_int64), ("step_cals", ctypes.c_int64),
+                ("pending", ctypes.c_int64), ("in_flight_requests", ctypes.c_int64),
+                ("arena_used", ctypes.c_int64), ("arena_size", ctypes.c_int64)]
+
+
 class _CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_reads", ctypes.c_int32), ("max_cals", ctypes.c_int64),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
@@ -89,6 +101,16 @@ def lib():
         L.sw_ctx_error_count.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.sw_ctx_last_plan.restype = ctypes.c_char_p
         L.sw_ctx_last_plan.argtypes = [vp]
+        L.sw_server_create.argtypes = [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]
+        L.sw_server_set_refs.argtypes = [vp, ctypes.POINTER(_RefSetC)]
+        L.sw_server_submit.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp,
+                                       ctypes.POINTER(i64)]
+        L.sw_server_wait.argtypes = [vp, i64, i32, ctypes.POINTER(i32)]
+        L.sw_server_request_info.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.sw_server_release.argtypes = [vp, i64]
+        L.sw_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+        L.sw_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -262,6 +284,95 @@ class Context:
 
     def last_plan(self) -> str:
         return lib().sw_ctx_last_plan(self._h).decode()
+
+
+class Request:
+    """Host outputs of one served request (filled when it completes)."""
+
+    def __init__(self, rid, n_reads, n_cals, n_refs, keep):
+        import numpy as np
+        self.id = rid
+        self.score = np.full(2 * n_cals, -7, np.int32)
+        self.ref_end = np.full(2 * n_cals, -7, np.int64)
+        self.read_end = np.full(2 * n_cals, -7, np.int16)
+        self.best_score = np.full(n_reads * n_refs, -7, np.int32)
+        self.best_slot = np.full(n_reads * n_refs, -7, np.int64)
+        self.n_tied = np.full(n_reads * n_refs, -7, np.int32)
+        self.keep = keep
+        self.n_reads, self.n_refs = n_reads, n_refs
+
+
+class Server:
+    """Served scoring (sw_server_*): resident references, admission by device
+    memory, continuous batching of admitted requests, per-request timestamps."""
+
+    def __init__(self, scoring: Scoring, memory_budget: int = 1 << 30, max_step_reads: int = 65536,
+                 max_step_cals: int = 1 << 20, max_step_chunks: int = 512, device: int = 0, autotune: bool = False):
+        self._h = ctypes.c_void_p()
+        opts = _ServerOpts(device, scoring, memory_budget, max_step_reads, max_step_cals, max_step_chunks,
+                           int(autotune))
+        _check(lib().sw_server_create(ctypes.byref(opts), ctypes.byref(self._h)), "sw_server_create")
+        self.n_refs = 0
+        self.requests = {}
+
+    def set_refs(self, refs: "RefSet"):
+        self._refs = refs
+        self.n_refs = refs.n_refs
+        _check(lib().sw_server_set_refs(self._h, refs.c), "sw_server_set_refs")
+
+    def submit(self, read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref, strand) -> Request:
+        import numpy as np
+        a = [np.ascontiguousarray(read_codes, np.uint8), np.ascontiguousarray(read_code_off, np.int64),
+             np.ascontiguousarray(read_len, np.int32), np.ascontiguousarray(cal_ptr, np.int64),
+             np.ascontiguousarray(cal_pos, np.int64), np.ascontiguousarray(cal_ref, np.int16),
+             np.ascontiguousarray(strand, np.uint8)]
+        n_reads, n_cals = len(a[2]), len(a[4])
+        req = Request(0, n_reads, n_cals, self.n_refs, a)
+        p = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+        rid = ctypes.c_int64(0)
+        rc = lib().sw_server_submit(self._h, p(a[0]), len(a[0]), p(a[1]), p(a[2]), n_reads, p(a[3]), p(a[4]),
+                                    p(a[5]), p(a[6]), n_cals, p(req.score), p(req.ref_end), p(req.read_end),
+                                    p(req.best_score), p(req.best_slot), p(req.n_tied), ctypes.byref(rid))
+        _check(rc, "sw_server_submit")
+        req.id = int(rid.value)
+        self.requests[req.id] = req
+        return req
+
+    def submit_batch(self, batch) -> Request:
+        return self.submit(batch.read_codes, batch.read_off, batch.read_len, batch.cal_ptr, batch.cal_pos,
+                           batch.cal_ref, batch.strand)
+
+    def wait(self, req: Request, timeout_ms: int = -1) -> bool:
+        done = ctypes.c_int32(0)
+        _check(lib().sw_server_wait(self._h, req.id, timeout_ms, ctypes.byref(done)), "sw_server_wait")
+        return bool(done.value)
+
+    def info(self, req: Request):
+        st = ctypes.c_int32(0)
+        t = [ctypes.c_double(0) for _ in range(3)]
+        _check(lib().sw_server_request_info(self._h, req.id, ctypes.byref(st), *[ctypes.byref(x) for x in t]),
+               "sw_server_request_info")
+        return int(st.value), t[0].value, t[1].value, t[2].value
+
+    def release(self, req: Request):
+        _check(lib().sw_server_release(self._h, req.id), "sw_server_release")
+        self.requests.pop(req.id, None)
+
+    def stats(self):
+        st = _ServerStats()
+        _check(lib().sw_server_stats(self._h, ctypes.byref(st)), "sw_server_stats")
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().sw_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def error_count(reset: bool = False) -> int:

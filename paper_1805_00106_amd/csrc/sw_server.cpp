@@ -1,0 +1,626 @@
+// Served execution: resident references, admission by device-memory footprint,
+// continuous batching of admitted requests into device steps, and per-request
+// timestamps for latency.  Contracts are in include/sw_align.h.
+//
+// The paper's V2 host keeps the reference resident on the accelerator and
+// streams each read followed by its CALs to it, with separate threads feeding
+// and draining the device (sections 4.2 and 4.3).  Here one scheduler thread
+// plays those roles: it admits requests into a device arena, packs chunks of
+// every admitted request into each device step, and drains finished requests,
+// so requests that arrive while a step runs join the next one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/sw_align.h"
+#include "sw_api_internal.h"
+#include "sw_launch.h"
+#include "sw_serve.h"
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// First-fit allocator over [0, size) with coalescing of freed blocks.
+class Arena {
+ public:
+  explicit Arena(size_t size) : size_(size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t *off) {
+    bytes = up256(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = up256(std::max<size_t>(bytes, 1));
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+enum ReqState { RS_PENDING = 0, RS_ADMITTED = 1, RS_DRAINING = 2, RS_DONE = 3, RS_FAILED = 4 };
+
+struct Layout {  // byte offsets of one request's arrays inside its arena block
+  size_t codes, words, word_off, len, cal_ptr, cal_pos, cal_ref, strand;
+  size_t score, ref_end, read_end, best_score, best_slot, n_tied;
+  size_t in_end, total;
+};
+
+struct Request {
+  int64_t id = 0;
+  int32_t n_reads = 0;
+  int64_t n_cals = 0, n_codes = 0, n_words = 0;
+  // host copies of the inputs (the caller may reuse its buffers after submit)
+  std::vector<uint8_t> codes;
+  std::vector<int64_t> code_off, cal_ptr, cal_pos;
+  std::vector<int32_t> len;
+  std::vector<int16_t> cal_ref;
+  std::vector<uint8_t> strand;
+  // caller's output buffers (host), filled at completion
+  int32_t *o_score;
+  int64_t *o_ref_end;
+  int16_t *o_read_end;
+  int32_t *o_best_score;
+  int64_t *o_best_slot;
+  int32_t *o_n_tied;
+  Layout lay{};
+  size_t off = 0;
+  int64_t next_read = 0;  // first read not yet placed in a step
+  int64_t reads_done = 0;
+  int state = RS_PENDING;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+struct StepSlot {  // device buffers of one step (two are used alternately)
+  uint32_t *words = nullptr;
+  int64_t *word_off = nullptr, *cal_ptr = nullptr, *cal_pos = nullptr;
+  int32_t *read_len = nullptr;
+  int16_t *cal_ref = nullptr;
+  uint8_t *strand = nullptr;
+  int32_t *score = nullptr;
+  int64_t *ref_end = nullptr;
+  int16_t *read_end = nullptr;
+  int32_t *best_score = nullptr;
+  int64_t *best_slot = nullptr;
+  int32_t *n_tied = nullptr;
+  swk::ServeChunk *chunks_dev = nullptr;
+  swk::ServeChunk *chunks_host = nullptr;  // pinned
+  void *base = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<std::pair<std::shared_ptr<Request>, int64_t>> parts;  // request and reads placed
+};
+
+}  // namespace
+
+struct sw_server {
+  sw_server_opts_t opts{};
+  sw_scoring_t sc{};
+  swapi::ScoreMode mode{};
+  int32_t n_refs = 0;
+  sw_refset_t refs{};
+  std::vector<int64_t> ref_off, ref_len;
+  bool refs_set = false;
+  void *arena_dev = nullptr;
+  uint8_t *arena_host = nullptr;  // pinned mirror of the arena
+  std::unique_ptr<Arena> arena;
+  sw_ctx_t *ctx = nullptr;
+  hipStream_t compute = nullptr, copy = nullptr;
+  StepSlot slots[2];
+  int next_slot = 0;
+  std::deque<std::shared_ptr<Request>> pending;
+  std::deque<std::shared_ptr<Request>> admitted;  // admitted, not fully placed in steps
+  std::list<std::shared_ptr<Request>> draining;
+  std::deque<StepSlot *> in_flight;
+  std::map<int64_t, std::shared_ptr<Request>> all;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread worker;
+  std::atomic<bool> stop{false};
+  int64_t next_id = 1;
+  int last_error = 0;
+  int64_t steps = 0, step_reads = 0, step_cals = 0;
+};
+
+namespace {
+
+Layout make_layout(int32_t n_reads, int64_t n_cals, int64_t n_codes, int32_t n_refs) {
+  Layout L{};
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t r = o;
+    o = up256(o + bytes);
+    return r;
+  };
+  L.codes = put(n_codes);
+  L.words = put(sizeof(uint32_t) * ((n_codes + 15) / 16));
+  L.word_off = put(sizeof(int64_t) * n_reads);
+  L.len = put(sizeof(int32_t) * n_reads);
+  L.cal_ptr = put(sizeof(int64_t) * (n_reads + 1));
+  L.cal_pos = put(sizeof(int64_t) * n_cals);
+  L.cal_ref = put(sizeof(int16_t) * n_cals);
+  L.strand = put(n_cals);
+  L.in_end = o;
+  L.score = put(sizeof(int32_t) * 2 * n_cals);
+  L.ref_end = put(sizeof(int64_t) * 2 * n_cals);
+  L.read_end = put(sizeof(int16_t) * 2 * n_cals);
+  L.best_score = put(sizeof(int32_t) * n_reads * n_refs);
+  L.best_slot = put(sizeof(int64_t) * n_reads * n_refs);
+  L.n_tied = put(sizeof(int32_t) * n_reads * n_refs);
+  L.total = o;
+  return L;
+}
+
+template <class T>
+T *dptr(sw_server *s, const Request &r, size_t field) {
+  return reinterpret_cast<T *>((char *)s->arena_dev + r.off + field);
+}
+template <class T>
+T *hptr(sw_server *s, const Request &r, size_t field) {
+  return reinterpret_cast<T *>(s->arena_host + r.off + field);
+}
+
+// Admission (scheduler thread, lock held): reserve the footprint, stage the
+// inputs through the pinned mirror, upload, and pack the reads on the device.
+bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
+  size_t off = 0;
+  if (!s->arena->alloc(rq->lay.total, &off)) return false;
+  rq->off = off;
+  Request &r = *rq;
+  std::memcpy(hptr<uint8_t>(s, r, r.lay.codes), r.codes.data(), r.n_codes);
+  int64_t *wo = hptr<int64_t>(s, r, r.lay.word_off);
+  for (int32_t i = 0; i < r.n_reads; ++i) wo[i] = r.code_off[i] / 16;
+  std::memcpy(hptr<int32_t>(s, r, r.lay.len), r.len.data(), sizeof(int32_t) * r.n_reads);
+  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_ptr), r.cal_ptr.data(), sizeof(int64_t) * (r.n_reads + 1));
+  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_pos), r.cal_pos.data(), sizeof(int64_t) * r.n_cals);
+  std::memcpy(hptr<int16_t>(s, r, r.lay.cal_ref), r.cal_ref.data(), sizeof(int16_t) * r.n_cals);
+  std::memcpy(hptr<uint8_t>(s, r, r.lay.strand), r.strand.data(), r.n_cals);
+  hipMemcpyAsync((char *)s->arena_dev + off, s->arena_host + off, r.lay.in_end, hipMemcpyHostToDevice, s->copy);
+  sw_pack_2bit(dptr<uint8_t>(s, r, r.lay.codes), r.n_codes, dptr<uint32_t>(s, r, r.lay.words),
+               (sw_stream_t)s->copy);
+  hipEventRecord(r.ev_in, s->copy);
+  r.t_admit = now_s();
+  r.state = RS_ADMITTED;
+  r.codes.clear();
+  r.codes.shrink_to_fit();
+  return true;
+}
+
+// Build and launch one step from the admitted requests (scheduler thread, lock held).
+bool launch_step(sw_server *s) {
+  StepSlot &st = s->slots[s->next_slot];
+  if (st.busy || s->admitted.empty()) return false;
+  const int64_t max_reads = s->opts.max_step_reads, max_cals = s->opts.max_step_cals;
+  const int64_t words_per_read = (s->mode.max_read_len + 15) / 16;
+  int64_t nr = 0, nc = 0, nw = 0;
+  int nch = 0;
+  st.parts.clear();
+  for (auto &rq : s->admitted) {
+    if (nch >= s->opts.max_step_chunks) break;
+    Request &r = *rq;
+    int64_t r0 = r.next_read, r1 = r0;
+    // take whole reads while the step has room (a single read always fits an
+    // empty step: submit bounds the CALs of one read by the step capacity)
+    while (r1 < r.n_reads && nr + (r1 - r0) < max_reads) {
+      if (nc + (r.cal_ptr[r1 + 1] - r.cal_ptr[r0]) > max_cals) break;
+      ++r1;
+    }
+    if (r1 == r0) break;
+    swk::ServeChunk &c = st.chunks_host[nch++];
+    c.words = dptr<uint32_t>(s, r, r.lay.words);
+    c.word_off = dptr<int64_t>(s, r, r.lay.word_off);
+    c.len = dptr<int32_t>(s, r, r.lay.len);
+    c.cal_ptr = dptr<int64_t>(s, r, r.lay.cal_ptr);
+    c.cal_pos = dptr<int64_t>(s, r, r.lay.cal_pos);
+    c.cal_ref = dptr<int16_t>(s, r, r.lay.cal_ref);
+    c.strand = dptr<uint8_t>(s, r, r.lay.strand);
+    c.score = dptr<int32_t>(s, r, r.lay.score);
+    c.ref_end = dptr<int64_t>(s, r, r.lay.ref_end);
+    c.read_end = dptr<int16_t>(s, r, r.lay.read_end);
+    c.best_score = dptr<int32_t>(s, r, r.lay.best_score);
+    c.best_slot = dptr<int64_t>(s, r, r.lay.best_slot);
+    c.n_tied = dptr<int32_t>(s, r, r.lay.n_tied);
+    c.r0 = r0;
+    c.r1 = r1;
+    c.step_r0 = nr;
+    c.step_c0 = nc;
+    c.step_w0 = nw;
+    // the chunk's words are contiguous in the request (16-aligned code offsets)
+    const int64_t w_first = r.code_off[r0] / 16;
+    const int64_t w_last = r.code_off[r1 - 1] / 16 + (r.len[r1 - 1] + 15) / 16;
+    nw += w_last - w_first;
+    nr += r1 - r0;
+    nc += r.cal_ptr[r1] - r.cal_ptr[r0];
+    r.next_read = r1;
+    st.parts.emplace_back(rq, r1 - r0);
+    hipStreamWaitEvent(s->compute, r.ev_in, 0);
+  }
+  (void)words_per_read;
+  while (!s->admitted.empty() && s->admitted.front()->next_read >= s->admitted.front()->n_reads)
+    s->admitted.pop_front();
+  if (nch == 0) return false;
+  hipStream_t cs = s->compute;
+  hipMemcpyAsync(st.chunks_dev, st.chunks_host, sizeof(swk::ServeChunk) * nch, hipMemcpyHostToDevice, cs);
+  swk::launch_serve_gather(st.chunks_dev, nch, nr, nc, st.words, st.word_off, st.read_len, st.cal_ptr, st.cal_pos,
+                           st.cal_ref, st.strand, cs);
+  int rc = SW_OK;
+  if (nc > 0) {
+    rc = sw_align_batch_ctx(s->ctx, st.words, st.word_off, st.read_len, (int32_t)nr, &s->refs, st.cal_ptr,
+                            st.cal_pos, st.cal_ref, st.strand, nc, &s->sc, st.score, st.ref_end, st.read_end,
+                            (sw_stream_t)cs);
+  }
+  if (rc == SW_OK)
+    rc = sw_reduce_best(st.cal_ptr, st.cal_ref, (int32_t)nr, s->n_refs, st.score, st.best_score, st.best_slot,
+                        st.n_tied, (sw_stream_t)cs);
+  if (rc != SW_OK) s->last_error = rc;
+  swk::launch_serve_scatter(st.chunks_dev, nch, nr, nc, s->n_refs, st.score, st.ref_end, st.read_end, st.best_score,
+                            st.best_slot, st.n_tied, cs);
+  hipEventRecord(st.done, cs);
+  st.busy = true;
+  s->in_flight.push_back(&st);
+  s->next_slot ^= 1;
+  s->steps++;
+  s->step_reads += nr;
+  s->step_cals += nc;
+  return true;
+}
+
+// Retire finished steps; start the download of requests whose reads are all done.
+void retire_steps(sw_server *s) {
+  while (!s->in_flight.empty() && hipEventQuery(s->in_flight.front()->done) == hipSuccess) {
+    StepSlot &st = *s->in_flight.front();
+    s->in_flight.pop_front();
+    for (auto &p : st.parts) {
+      Request &r = *p.first;
+      r.reads_done += p.second;
+      if (r.reads_done == r.n_reads) {
+        hipStreamWaitEvent(s->copy, st.done, 0);
+        hipMemcpyAsync(s->arena_host + r.off + r.lay.in_end, (char *)s->arena_dev + r.off + r.lay.in_end,
+                       r.lay.total - r.lay.in_end, hipMemcpyDeviceToHost, s->copy);
+        hipEventRecord(r.ev_out, s->copy);
+        r.state = RS_DRAINING;
+        s->draining.push_back(p.first);
+      }
+    }
+    st.parts.clear();
+    st.busy = false;
+  }
+}
+
+void finish_downloads(sw_server *s) {
+  bool any = false;
+  for (auto it = s->draining.begin(); it != s->draining.end();) {
+    Request &r = **it;
+    if (hipEventQuery(r.ev_out) != hipSuccess) {
+      ++it;
+      continue;
+    }
+    std::memcpy(r.o_score, hptr<int32_t>(s, r, r.lay.score), sizeof(int32_t) * 2 * r.n_cals);
+    std::memcpy(r.o_ref_end, hptr<int64_t>(s, r, r.lay.ref_end), sizeof(int64_t) * 2 * r.n_cals);
+    std::memcpy(r.o_read_end, hptr<int16_t>(s, r, r.lay.read_end), sizeof(int16_t) * 2 * r.n_cals);
+    if (r.o_best_score)
+      std::memcpy(r.o_best_score, hptr<int32_t>(s, r, r.lay.best_score), sizeof(int32_t) * r.n_reads * s->n_refs);
+    if (r.o_best_slot)
+      std::memcpy(r.o_best_slot, hptr<int64_t>(s, r, r.lay.best_slot), sizeof(int64_t) * r.n_reads * s->n_refs);
+    if (r.o_n_tied)
+      std::memcpy(r.o_n_tied, hptr<int32_t>(s, r, r.lay.n_tied), sizeof(int32_t) * r.n_reads * s->n_refs);
+    s->arena->release(r.off, r.lay.total);
+    r.t_done = now_s();
+    r.state = RS_DONE;
+    it = s->draining.erase(it);
+    any = true;
+  }
+  if (any) s->cv_done.notify_all();
+}
+
+void serve_loop(sw_server *s) {
+  hipSetDevice(s->opts.device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    while (!s->pending.empty()) {  // admission, in arrival order
+      if (!admit(s, s->pending.front())) break;
+      s->admitted.push_back(s->pending.front());
+      s->pending.pop_front();
+    }
+    while (launch_step(s)) {
+    }
+    retire_steps(s);
+    finish_downloads(s);
+    const bool idle = s->pending.empty() && s->admitted.empty() && s->in_flight.empty() && s->draining.empty();
+    if (s->stop && idle) break;
+    if (idle)
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    else
+      s->cv_work.wait_for(lk, std::chrono::microseconds(50));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
+  if (!opts || !out) return SW_ERR_INVALID_ARG;
+  *out = nullptr;
+  swapi::ScoreMode m;
+  int rc = swapi::validate_scoring(&opts->scoring, &m);
+  if (rc) return rc;
+  if (opts->memory_budget < (1 << 20) || opts->max_step_reads < 1 || opts->max_step_cals < 1 ||
+      opts->max_step_chunks < 1 || opts->max_step_chunks > 4096)
+    return SW_ERR_INVALID_ARG;
+  hipError_t e = hipSetDevice(opts->device);
+  if (e != hipSuccess) return swapi::hip_fail(e);
+  auto *s = new (std::nothrow) sw_server();
+  if (!s) return SW_ERR_NOMEM;
+  s->opts = *opts;
+  s->sc = opts->scoring;
+  s->mode = m;
+  s->arena.reset(new Arena(opts->memory_budget));
+  if (hipMalloc(&s->arena_dev, opts->memory_budget) != hipSuccess ||
+      hipHostMalloc((void **)&s->arena_host, opts->memory_budget, hipHostMallocDefault) != hipSuccess) {
+    sw_server_destroy(s);
+    return SW_ERR_NOMEM;
+  }
+  if ((e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking)) != hipSuccess) {
+    sw_server_destroy(s);
+    return swapi::hip_fail(e);
+  }
+  const int64_t R = opts->max_step_reads, C = opts->max_step_cals;
+  const int64_t W = R * ((m.max_read_len + 15) / 16);
+  for (auto &st : s->slots) {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      size_t r = o;
+      o = up256(o + b);
+      return r;
+    };
+    const size_t o_words = take(4 * W), o_wo = take(8 * R), o_len = take(4 * R), o_cp = take(8 * (R + 1)),
+                 o_pos = take(8 * C), o_ref = take(2 * C), o_str = take(C), o_sc = take(4 * 2 * C),
+                 o_re = take(8 * 2 * C), o_qe = take(2 * 2 * C), o_bs = take(4 * R * SW_MAX_REFS),
+                 o_bl = take(8 * R * SW_MAX_REFS), o_nt = take(4 * R * SW_MAX_REFS),
+                 o_ch = take(sizeof(swk::ServeChunk) * opts->max_step_chunks);
+    if (hipMalloc(&st.base, o) != hipSuccess ||
+        hipHostMalloc((void **)&st.chunks_host, sizeof(swk::ServeChunk) * opts->max_step_chunks,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+      sw_server_destroy(s);
+      return SW_ERR_NOMEM;
+    }
+    char *b = (char *)st.base;
+    st.words = (uint32_t *)(b + o_words);
+    st.word_off = (int64_t *)(b + o_wo);
+    st.read_len = (int32_t *)(b + o_len);
+    st.cal_ptr = (int64_t *)(b + o_cp);
+    st.cal_pos = (int64_t *)(b + o_pos);
+    st.cal_ref = (int16_t *)(b + o_ref);
+    st.strand = (uint8_t *)(b + o_str);
+    st.score = (int32_t *)(b + o_sc);
+    st.ref_end = (int64_t *)(b + o_re);
+    st.read_end = (int16_t *)(b + o_qe);
+    st.best_score = (int32_t *)(b + o_bs);
+    st.best_slot = (int64_t *)(b + o_bl);
+    st.n_tied = (int32_t *)(b + o_nt);
+    st.chunks_dev = (swk::ServeChunk *)(b + o_ch);
+  }
+  sw_ctx_opts_t co{};
+  co.device = opts->device;
+  co.max_reads = (int32_t)R;
+  co.max_cals = C;
+  co.use_graph = 0;  // step shapes change every step
+  co.autotune = opts->autotune;
+  co.tune_cache = nullptr;
+  rc = sw_ctx_create(&co, &s->ctx);
+  if (rc) {
+    sw_server_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return SW_OK;
+}
+
+int sw_server_set_refs(sw_server_t *s, const sw_refset_t *refs) {
+  if (!s) return SW_ERR_INVALID_ARG;
+  swk::RefTable T;
+  int rc = swapi::validate_refs(refs, 1, &T);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->worker.joinable()) return SW_ERR_STATE;  // references are fixed once serving starts
+  s->ref_off.assign(refs->word_offset, refs->word_offset + refs->n_refs);
+  s->ref_len.assign(refs->length, refs->length + refs->n_refs);
+  s->refs.words = refs->words;
+  s->refs.word_offset = s->ref_off.data();
+  s->refs.length = s->ref_len.data();
+  s->refs.n_refs = refs->n_refs;
+  s->n_refs = refs->n_refs;
+  s->refs_set = true;
+  s->worker = std::thread(serve_loop, s);
+  return SW_OK;
+}
+
+int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes, const int64_t *read_code_off,
+                     const int32_t *read_len, int32_t n_reads, const int64_t *cal_ptr, const int64_t *cal_pos,
+                     const int16_t *cal_ref, const uint8_t *strand, int64_t n_cals, int32_t *score, int64_t *ref_end,
+                     int16_t *read_end, int32_t *best_score, int64_t *best_slot, int32_t *n_tied, int64_t *req_id) {
+  const double t = now_s();
+  if (!s || !req_id) return SW_ERR_INVALID_ARG;
+  if (!s->refs_set) return SW_ERR_STATE;
+  if (n_reads < 1 || n_cals < 0 || n_codes < 0) return SW_ERR_INVALID_ARG;
+  if (!read_codes || !read_code_off || !read_len || !cal_ptr || !score || !ref_end || !read_end)
+    return SW_ERR_INVALID_ARG;
+  if (n_cals > 0 && (!cal_pos || !cal_ref || !strand)) return SW_ERR_INVALID_ARG;
+  if (n_reads > s->opts.max_step_reads) return SW_ERR_INVALID_ARG;
+  if (cal_ptr[0] != 0 || cal_ptr[n_reads] != n_cals) return SW_ERR_INVALID_ARG;
+  for (int32_t i = 0; i < n_reads; ++i) {
+    if (cal_ptr[i + 1] < cal_ptr[i]) return SW_ERR_INVALID_ARG;
+    if (cal_ptr[i + 1] - cal_ptr[i] > s->opts.max_step_cals) return SW_ERR_INVALID_ARG;
+    if (read_code_off[i] % 16 || read_code_off[i] < 0 || read_len[i] < 0 ||
+        read_len[i] > s->mode.max_read_len || read_code_off[i] + read_len[i] > n_codes)
+      return SW_ERR_INVALID_ARG;
+  }
+  auto rq = std::make_shared<Request>();
+  Request &r = *rq;
+  r.n_reads = n_reads;
+  r.n_cals = n_cals;
+  r.n_codes = n_codes;
+  r.lay = make_layout(n_reads, n_cals, n_codes, s->n_refs);
+  if (r.lay.total > s->arena->size()) return SW_ERR_REJECTED;
+  r.codes.assign(read_codes, read_codes + n_codes);
+  r.code_off.assign(read_code_off, read_code_off + n_reads);
+  r.len.assign(read_len, read_len + n_reads);
+  r.cal_ptr.assign(cal_ptr, cal_ptr + n_reads + 1);
+  if (n_cals) {
+    r.cal_pos.assign(cal_pos, cal_pos + n_cals);
+    r.cal_ref.assign(cal_ref, cal_ref + n_cals);
+    r.strand.assign(strand, strand + n_cals);
+  }
+  r.o_score = score;
+  r.o_ref_end = ref_end;
+  r.o_read_end = read_end;
+  r.o_best_score = best_score;
+  r.o_best_slot = best_slot;
+  r.o_n_tied = n_tied;
+  r.t_submit = t;
+  if (hipEventCreateWithFlags(&r.ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&r.ev_out, hipEventDisableTiming) != hipSuccess)
+    return SW_ERR_NOMEM;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return SW_ERR_STATE;
+    r.id = s->next_id++;
+    s->pending.push_back(rq);
+    s->all[r.id] = rq;
+  }
+  s->cv_work.notify_one();
+  *req_id = r.id;
+  return SW_OK;
+}
+
+int sw_server_wait(sw_server_t *s, int64_t req_id, int32_t timeout_ms, int32_t *done) {
+  if (!s || !done) return SW_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(req_id);
+  if (it == s->all.end()) return SW_ERR_INVALID_ARG;
+  auto rq = it->second;
+  auto pred = [&] { return rq->state == RS_DONE; };
+  if (timeout_ms < 0)
+    s->cv_done.wait(lk, pred);
+  else
+    s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred);
+  *done = rq->state == RS_DONE;
+  return s->last_error ? s->last_error : SW_OK;
+}
+
+int sw_server_request_info(sw_server_t *s, int64_t req_id, int32_t *state, double *t_submit, double *t_admit,
+                           double *t_done) {
+  if (!s) return SW_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(req_id);
+  if (it == s->all.end()) return SW_ERR_INVALID_ARG;
+  const Request &r = *it->second;
+  if (state) *state = r.state;
+  if (t_submit) *t_submit = r.t_submit;
+  if (t_admit) *t_admit = r.t_admit;
+  if (t_done) *t_done = r.t_done;
+  return SW_OK;
+}
+
+int sw_server_release(sw_server_t *s, int64_t req_id) {
+  if (!s) return SW_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(req_id);
+  if (it == s->all.end()) return SW_ERR_INVALID_ARG;
+  if (it->second->state != RS_DONE) return SW_ERR_STATE;
+  hipEventDestroy(it->second->ev_in);
+  hipEventDestroy(it->second->ev_out);
+  s->all.erase(it);
+  return SW_OK;
+}
+
+int sw_server_stats(sw_server_t *s, sw_server_stats_t *out) {
+  if (!s || !out) return SW_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->steps = s->steps;
+  out->step_reads = s->step_reads;
+  out->step_cals = s->step_cals;
+  out->pending = (int64_t)s->pending.size();
+  out->in_flight_requests = (int64_t)(s->admitted.size() + s->draining.size());
+  out->arena_used = (int64_t)s->arena->used();
+  out->arena_size = (int64_t)s->arena->size();
+  return s->last_error ? s->last_error : SW_OK;
+}
+
+int sw_server_destroy(sw_server_t *s) {
+  if (!s) return SW_OK;
+  if (s->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv_work.notify_all();
+    s->worker.join();  // drains every submitted request first
+  }
+  hipSetDevice(s->opts.device);
+  if (s->compute) hipStreamSynchronize(s->compute);
+  if (s->copy) hipStreamSynchronize(s->copy);
+  for (auto &kv : s->all) {
+    if (kv.second->ev_in) hipEventDestroy(kv.second->ev_in);
+    if (kv.second->ev_out) hipEventDestroy(kv.second->ev_out);
+  }
+  if (s->ctx) sw_ctx_destroy(s->ctx);
+  for (auto &st : s->slots) {
+    if (st.base) hipFree(st.base);
+    if (st.chunks_host) hipHostFree(st.chunks_host);
+    if (st.done) hipEventDestroy(st.done);
+  }
+  if (s->arena_dev) hipFree(s->arena_dev);
+  if (s->arena_host) hipHostFree(s->arena_host);
+  if (s->compute) hipStreamDestroy(s->compute);
+  if (s->copy) hipStreamDestroy(s->copy);
+  delete s;
+  return SW_OK;
+}
+
+}  // extern "C"

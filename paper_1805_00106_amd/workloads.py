@@ -547,9 +547,10 @@ def config5_arrivals(rate_per_s: float, n_requests: int, seed: int = 0):
     return t, sizes
 
 
-def config5_request(refs, n_reads: int, seed: int, band: int = 32) -> Batch:
+def config5_request(refs, n_reads: int, seed: int, band: int = 32, ref_pack=None) -> Batch:
     """One served request: reads of length U{75..250} with U{1..32} CALs on random
-    references (the first CAL is the true locus)."""
+    references (the first CAL is the true locus).  ``ref_pack`` = (codes, offsets,
+    lengths) of the concatenated references, shared instead of copied."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([ROOT_SEED + 5, 7, seed])))
     lens = rng.integers(75, 251, n_reads).astype(np.int64)
     src = rng.integers(0, len(refs), n_reads)
@@ -577,5 +578,9 @@ def config5_request(refs, n_reads: int, seed: int, band: int = 32) -> Batch:
     strand = np.full(total, 3, np.int64)
     sc = Scoring(2, -3, 5, 2, band)
     mat = _reads_matrix(reads, lens)
-    return _vector_batch(list(refs), mat, lens, counts, cal_pos, cal_ref, strand, sc,
-                         src.astype(np.int64), pos, rev.astype(np.int64), f"request{seed}")
+    b = _vector_batch([], mat, lens, counts, cal_pos, cal_ref, strand, sc,
+                      src.astype(np.int64), pos, rev.astype(np.int64), f"request{seed}")
+    if ref_pack is None:
+        ref_pack = concat_aligned(list(refs))
+    b.ref_codes, b.ref_off, b.ref_len = ref_pack[0], ref_pack[1], np.asarray(ref_pack[2], np.int64)
+    return b
