@@ -192,6 +192,93 @@ class Leg:
         self.ctx.close()
 
 
+def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9)):
+    """Config 5: two resident references, Poisson arrivals of log-uniform request
+    sizes, p50/p99 latency (scheduled arrival -> completion) at three loads
+    relative to the measured saturated throughput."""
+    import threading
+    import torch
+    import paper_1805_00106_amd as sw
+    from paper_1805_00106_amd import workloads as wl
+
+    t_gen = time.perf_counter()
+    refs = wl.config5_references(scale=scale)
+    pack = wl.concat_aligned(refs)
+    refs = [pack[0][int(o):int(o) + int(n)] for o, n in zip(pack[1], pack[2])]  # views, no second copy
+    codes = torch.from_numpy(pack[0]).cuda()
+    rs = sw.RefSet.from_codes(codes, pack[1], pack[2])
+    torch.cuda.synchronize()
+    del codes
+    torch.cuda.empty_cache()
+    _, sizes = wl.config5_arrivals(1.0, pool_size, seed=0)
+    pool = [wl.config5_request(refs, int(n), 10_000 + k, ref_pack=pack) for k, n in enumerate(sizes)]
+    pool_cells = [cells_of(b) for b in pool]
+    t_gen = time.perf_counter() - t_gen
+    sc = sw.Scoring.make(2, -3, 5, 2, 32, sw.PREC_AUTO, max_read_len=250)
+    srv = sw.Server(sc, memory_budget=2 << 30, max_step_reads=16384, max_step_cals=1 << 18, max_step_chunks=1024)
+    srv.set_refs(rs)
+
+    # saturated throughput: the whole pool queued at once
+    for b in pool[:8]:  # warm-up
+        srv.wait(srv.submit_batch(b))
+    t0 = time.monotonic()
+    hs = [srv.submit_batch(b) for b in pool]
+    for h in hs:
+        srv.wait(h)
+    dt = time.monotonic() - t0
+    for h in hs:
+        srv.release(h)
+    sat_reads = sum(b.n_reads for b in pool) / dt
+    sat_gcups = sum(pool_cells) / dt / 1e9
+    mean_reads = float(np.mean([b.n_reads for b in pool]))
+
+    results = []
+    for load in loads:
+        rate = load * sat_reads / mean_reads          # requests per second
+        g = np.random.default_rng(int(load * 1000))
+        arrivals = np.cumsum(g.exponential(1.0 / rate, per_load))
+        picks = g.integers(0, pool_size, per_load)
+        handles = [None] * per_load
+        start = time.monotonic() + 0.05
+
+        def feeder():
+            for i in range(per_load):
+                delay = start + arrivals[i] - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+                handles[i] = srv.submit_batch(pool[picks[i]])
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        lat = np.zeros(per_load)
+        done_last = 0.0
+        for i, h in enumerate(handles):
+            srv.wait(h)
+            _, _, _, t_done = srv.info(h)
+            lat[i] = t_done - (start + arrivals[i])
+            done_last = max(done_last, t_done)
+            srv.release(h)
+        keep = lat[per_load // 10:]                    # 10% warm-up dropped
+        span = done_last - start
+        results.append({"load": load, "offered_requests_per_s": round(rate, 1), "requests": per_load,
+                        "p50_ms": round(float(np.percentile(keep, 50)) * 1e3, 3),
+                        "p99_ms": round(float(np.percentile(keep, 99)) * 1e3, 3),
+                        "mean_ms": round(float(keep.mean()) * 1e3, 3),
+                        "achieved_reads_per_s": round(sum(pool[k].n_reads for k in picks) / span, 1),
+                        "achieved_gcups": round(sum(pool_cells[k] for k in picks) / span / 1e9, 1)})
+    stats = srv.stats()
+    srv.close()
+    return {"workload": f"config5: resident references of {int(pack[2][0]):,} and {int(pack[2][1]):,} bp "
+                        f"(random + 5% planted repeats, {sum(int(x) for x in pack[2]) / 4e9:.2f} GB 2-bit), "
+                        f"Poisson arrivals, requests log-uniform 1..10000 reads (pool of {pool_size}), "
+                        "L U{75..250}, CALs U{1..32} per read, band 32, both strands",
+            "saturated": {"reads_per_s": round(sat_reads, 1), "gcups": round(sat_gcups, 1),
+                          "requests_per_s": round(pool_size / dt, 1)},
+            "mean_request_reads": round(mean_reads, 1), "loads": results, "steps": stats["steps"],
+            "gen_s": round(t_gen, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +288,10 @@ def main():
     ap.add_argument("--config3-reads", type=int, default=2_000_000,
                     help="reads of the uneven-length leg (0 skips it)")
     ap.add_argument("--config3-band", type=int, default=32)
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0 skips it)")
+    ap.add_argument("--serve-pool", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -251,6 +342,8 @@ def main():
         leg3.free()
         del leg3
 
+    served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests) if args.serve_scale > 0 else None
+
     step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
     gcups = cells / (step_ms * 1e-3) / 1e9
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
@@ -279,6 +372,10 @@ def main():
     }
     if c3:
         res["config3"] = c3
+    if served:
+        res["served"] = served
+        res["p50_ms"] = served["loads"][-1]["p50_ms"]
+        res["p99_ms"] = served["loads"][-1]["p99_ms"]
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(batch)
     print(json.dumps(res))
