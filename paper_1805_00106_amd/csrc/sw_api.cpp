@@ -148,17 +148,38 @@ int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainP
   ScoreMode m;
   int rc = validate_scoring(sc, &m);
   if (rc) return rc;
+  // Kernel family: the intra-task kernel (one wavefront per task, lanes =
+  // window columns) has the lowest latency per task and wins when the batch is
+  // too small to give every SIMD a few inter-task tiles; it computes in int32.
+  const int cus = device_cus();
+  bool intra = sc->kernel == SW_KERNEL_INTRA;
+  if (sc->kernel == SW_KERNEL_AUTO) intra = sc->precision != SW_PREC_INT16 && 2 * n_cals <= 4 * (int64_t)cus;
+  p->intra = intra;
+  if (intra) {
+    if (sc->precision == SW_PREC_INT16) return SW_ERR_INVALID_ARG;  // the intra kernel is int32 only
+    m.int16 = false;
+  }
   p->mode = m;
+  p->wwords = (m.wcap + 15) / 16;
+  p->rwords = (m.max_read_len + 15) / 16;
+  p->cal_read_off = 0;
+  p->scratch_off = align_up((size_t)std::max<int64_t>(n_cals, 1) * sizeof(int32_t), 256);
+  if (intra) {
+    p->strip_rows = 0;
+    p->n_tasks = 2 * n_cals;
+    const size_t lds = (size_t)m.max_read_len * 16 + (size_t)p->wwords * 4;
+    int occ = swk::intra_blocks_per_cu(lds);
+    if (occ <= 0) occ = 8;
+    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(p->n_tasks, (int64_t)cus * occ));
+    p->bytes = p->scratch_off;
+    return SW_OK;
+  }
   p->strip_rows = strip_override > 0 ? strip_override : choose_strip_rows(m.int16, m.max_read_len);
   if (!strip_rows_supported(m.int16, p->strip_rows)) return SW_ERR_INVALID_ARG;
   p->n_tasks = m.int16 ? n_cals : 2 * n_cals;
-  p->wwords = (m.wcap + 15) / 16;
-  p->rwords = (m.max_read_len + 15) / 16;
   const int64_t n_tiles = (p->n_tasks + 63) / 64;
-  const int64_t resident = (int64_t)device_cus() * blocks_per_cu(m.int16, p->strip_rows);
+  const int64_t resident = (int64_t)cus * blocks_per_cu(m.int16, p->strip_rows);
   p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, resident));
-  p->cal_read_off = 0;
-  p->scratch_off = align_up((size_t)std::max<int64_t>(n_cals, 1) * sizeof(int32_t), 256);
   p->bytes = p->scratch_off + (size_t)p->grid * (size_t)m.wcap * 64 * sizeof(uint2);
   return SW_OK;
 }
@@ -225,7 +246,7 @@ int run_plain(const PlainPlan &plan, const swk::RefTable &T, const uint32_t *rea
   A.band = sc->band;
   A.strip_rows = plan.strip_rows;
   A.k = make_consts(sc);
-  e = swk::launch_inter(plan.mode.int16, A, T, plan.grid, st);
+  e = plan.intra ? swk::launch_intra(A, T, plan.grid, st) : swk::launch_inter(plan.mode.int16, A, T, plan.grid, st);
   if (e != hipSuccess) return hip_fail(e);
   return SW_OK;
 }

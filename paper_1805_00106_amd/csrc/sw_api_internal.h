@@ -19,6 +19,7 @@ struct ScoreMode {
 
 struct PlainPlan {
   ScoreMode mode;
+  bool intra;  // one wavefront per task instead of one CAL per lane
   int strip_rows;
   int64_t n_tasks;
   int wwords, rwords;

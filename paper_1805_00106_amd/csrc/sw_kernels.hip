@@ -609,6 +609,147 @@ __global__ __launch_bounds__(64) void k_inter32_queue(const AlignArgs A, const R
   }
 }
 
+// --------------------------------------------------------------------------- intra-task kernel
+//
+// One wavefront per task (one strand of one CAL).  Lane j holds window column
+// 64*s + j of strip s; the strip is swept along anti-diagonals: at step t lane
+// j computes row i = t - j.  Every dependency on column j-1 is a one-lane
+// shift of a value computed one step earlier (wave_shr:1 DPP): E(i, j) is
+// computed by lane j-1 for lane j, the diagonal H(i-1, j-1) is lane j-1's H
+// from two steps earlier, and the read base of row i travels with the
+// anti-diagonal.  Lane 0 receives its left boundary through the `old` operand
+// of the shift: column -1 values for the first strip, and for later strips the
+// values lane 63 of the previous strip left in LDS, one entry per row.
+//
+// Values are V*4096 + tag(t), tag(t) = 4095 - t (t < 4096 within a strip), so
+// the zero term is the wave-uniform tag, every move carries its tag change in
+// its constant (E and F: -1, diagonal: -2), and a per-lane running max orders a
+// column's cells by (V, then smallest row).  The strip hand-over through LDS
+// crosses 64 steps of the timeline, so lane 0 adds 64 to what it reads.
+
+__device__ __forceinline__ int32_t shr1(int32_t old, int32_t src) {
+  return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+
+__global__ __launch_bounds__(64) void k_intra32(const AlignArgs A, const RefTable T) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const int lane = threadIdx.x;
+  load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
+  int4 *rows = reinterpret_cast<int4 *>(smem);                   // [max_read_len]: q, E, H of lane 63
+  uint32_t *win = smem + 4 * A.max_read_len;                      // [wwords]
+  const DpConst &K = A.k;
+  const int32_t SM = K.sm32 - 1, SX = K.sx32 - 1;                 // diagonal: tag -2
+  const int32_t GOE = K.goe_e32, GE = K.ge_e32;                   // E and F moves: tag -1
+
+  for (int64_t tk = blockIdx.x; tk < A.n_tasks; tk += gridDim.x) {
+    const int64_t c = tk >> 1;
+    const int h = (int)(tk & 1);
+    LaneTask t{};
+    if (lane == 0) t = load_task(A, rt_len, c, 1 << h);
+    const int L = __shfl(t.L, 0, 64);
+    if (L == 0) continue;
+    const int W = __shfl(t.W, 0, 64);
+    const int k = __shfl(t.k, 0, 64);
+    const int r = __shfl(t.r, 0, 64);
+    const int64_t ws = (int64_t)__shfl((int)(t.ws & 0xffffffff), 0, 64) |
+                       ((int64_t)__shfl((int)(t.ws >> 32), 0, 64) << 32);
+    __syncthreads();
+    // stage the oriented read (one code per row) and the window words
+    const uint32_t *rp = A.reads + A.read_word_off[r];
+    for (int i = lane; i < L; i += 64) {
+      const int src = h == 0 ? i : L - 1 - i;
+      const uint32_t b = (rp[src >> 4] >> (2 * (src & 15))) & 3u;
+      rows[i].x = (int32_t)(h == 0 ? b : 3u - b);
+    }
+    const int64_t first = rt_off[k] + (ws >> 4);
+    const int64_t last = rt_off[k] + ((rt_len[k] - 1) >> 4);
+    const uint32_t sh = 2u * (uint32_t)(ws & 15);
+    const int nww = (W + 15) >> 4;
+    for (int q = lane; q < nww; q += 64) {
+      const uint32_t lo = A.ref_words[first + q];
+      const uint32_t hi = (first + q + 1 <= last) ? A.ref_words[first + q + 1] : 0u;
+      win[q] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+    }
+    __syncthreads();
+
+    uint64_t best = 0;
+    const int nstrips = (W + 63) >> 6;
+    for (int s = 0; s < nstrips; ++s) {
+      const int col = 64 * s + lane;
+      const int32_t w = col < W ? (int32_t)((win[col >> 4] >> (2 * (col & 15))) & 3u) : 5;
+      const int width = min(64, W - 64 * s);
+      const int nsteps = L + width - 1;
+      // registers of lane j before its row 0 (boundary row -1 and the F entering row 0)
+      int32_t H = 4096 - lane;               // H(-1, j): lane j+1's first diagonal (tag(j + 1) + 2)
+      int32_t Hd1 = 4097 - lane;              // lane 0: H(-1, -1), its diagonal at step 0
+      int32_t F = 4095 - lane - (GOE - 1);    // F(0, j) = H(-1, j) - go - ge at step j
+      int32_t Eout = 0, Ein = 0;
+      int32_t q = 0;
+      int32_t M = 0;
+      for (int st = 0; st < nsteps; ++st) {
+        const int32_t zt = 4095 - st;
+        // lane 0 boundary for this step: row st at column 64s - 1
+        int32_t e_b, h_b, q_b;
+        if (st < L) {
+          const int4 rb = rows[st];
+          q_b = rb.x;
+          if (s == 0) {
+            e_b = zt - (GOE - 1);             // E(st, 0) = 0 - go - ge
+          } else {
+            e_b = rb.y + 64;
+          }
+        } else {
+          q_b = 4;
+          e_b = zt - (GOE - 1);
+        }
+        // H(st, 64s - 1): lane 0 uses it as its diagonal at step st + 1 (tag + 2)
+        if (s == 0 || st >= L) {
+          h_b = zt + 1;                        // column -1: H = 0
+        } else {
+          h_b = rows[st].z + 64;
+        }
+        // shifts from lane j-1 (full exec)
+        q = shr1(q_b, q);
+        Ein = shr1(e_b, Eout);
+        const int32_t Hs = shr1(h_b, H);      // lane j-1's H of the previous step
+        const int i = st - lane;
+        if (i >= 0 && i < L) {
+          const int32_t Hdiag = Hd1;          // lane j-1's H two steps back
+          const int32_t sub = q == w ? SM : SX;
+          int32_t Hn = max(max(Hdiag + sub, Ein), F);
+          Hn = max(Hn, zt);
+          M = max(M, Hn);
+          const int32_t U = Hn - GOE;
+          Eout = max(Ein - GE, U);
+          F = max(F - GE, U);
+          H = Hn;
+          if (lane == 63) {
+            rows[i].y = Eout;
+            rows[i].z = Hn;
+          }
+        }
+        Hd1 = Hs;
+      }
+      const int32_t v = M >> 12;
+      if (v > 0 && col < W) {
+        const int32_t row = (4095 - (M & 4095)) - lane;
+        const uint64_t kk = cell_key(v, col, row);
+        best = kk > best ? kk : best;
+      }
+      __syncthreads();
+    }
+    // wave max of the 64-bit keys
+    for (int m = 32; m; m >>= 1) {
+      const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(best >> 32), m, 64) << 32) |
+                         (uint32_t)__shfl_xor((int)(best & 0xffffffffu), m, 64);
+      best = o > best ? o : best;
+    }
+    if (lane == 0) write_result(A, 2 * c + h, best, ws);
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------------------------- Score Tracker
 
 // One thread per read: best slot per reference, lowest slot among ties, tie count.
@@ -905,6 +1046,20 @@ int queue_blocks_per_cu(bool int16) {
   const void *f = int16 ? reinterpret_cast<const void *>(&k_inter16_queue)
                         : reinterpret_cast<const void *>(&k_inter32_queue);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, 8192) != hipSuccess) return 0;
+  return n;
+}
+
+hipError_t launch_intra(const AlignArgs &A, const RefTable &T, int grid, hipStream_t st) {
+  const size_t lds = (size_t)A.max_read_len * sizeof(int4) + (size_t)A.wwords * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_intra32, dim3(grid), dim3(64), lds, st, A, T);
+  return hipGetLastError();
+}
+
+int intra_blocks_per_cu(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_intra32), 64, lds) !=
+      hipSuccess)
+    return 0;
   return n;
 }
 

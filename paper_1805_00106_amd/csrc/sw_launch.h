@@ -49,6 +49,8 @@ hipError_t launch_batch_plan(const BatchBufs &B, const int32_t *read_len, int32_
                              const BinParams &P, hipStream_t st);
 hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
 int queue_blocks_per_cu(bool int16);
+hipError_t launch_intra(const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
+int intra_blocks_per_cu(size_t lds);
 // Address of the library's device-resident invalid-task counter on the current device.
 unsigned long long *error_counter();
 

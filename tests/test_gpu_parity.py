@@ -20,6 +20,13 @@ PRECISIONS = [sw.PREC_INT16, sw.PREC_INT32]
 
 def _case(batch, precision, **kw):
     exp, _ = oracle_align(batch)
+    if precision == sw.PREC_INT32 and "kernel" not in kw:
+        # int32 runs both kernel families: one CAL strand per lane, one wavefront per task
+        for kernel in (sw.KERNEL_INTER, sw.KERNEL_INTRA):
+            got = gpu_align(batch, precision, kernel=kernel, **kw)
+            assert_same(got, exp, f"{batch.name} prec={precision} kernel={kernel} {kw}")
+        return
+    kw.setdefault("kernel", sw.KERNEL_INTER)
     got = gpu_align(batch, precision, **kw)
     assert_same(got, exp, f"{batch.name} prec={precision} {kw}")
 
@@ -31,6 +38,20 @@ def test_config1_int32_full():
 
 def test_config1_int16():
     _case(wl.config1(), sw.PREC_INT16)
+
+
+def test_auto_kernel_choice_small_and_large():
+    """AUTO picks the wavefront-per-task kernel for tiny batches, one CAL per lane otherwise."""
+    small = wl.random_small_batch(50, n_reads=20, read_len=(30, 150), band=20)
+    _case(small, sw.PREC_AUTO, kernel=sw.KERNEL_AUTO)
+    _case(wl.config1(n_reads=2000), sw.PREC_AUTO, kernel=sw.KERNEL_AUTO)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_intra_long_reads_many_strips(seed):
+    """Wide windows: several 64-column strips handed over through LDS."""
+    b = wl.random_small_batch(60 + seed, n_reads=25, read_len=(150, 400), ref_len=(500, 5000), band=100)
+    _case(b, sw.PREC_INT32, kernel=sw.KERNEL_INTRA, max_read_len=400)
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
