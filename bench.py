@@ -108,6 +108,38 @@ def parity_sample(batch, out, n=300, seed=7):
     return bool(np.array_equal(gs, s) and np.array_equal(gr, r) and np.array_equal(ge, e))
 
 
+def small_batch_latency(batch, n_reads=24, reps=20):
+    """Latency of one tiny plain call (a few reads' CALs) with each kernel family:
+    one CAL per lane leaves most of the GPU idle and runs each alignment serially
+    in one lane; one wavefront per task spreads each alignment over 64 lanes."""
+    import torch
+    import paper_1805_00106_amd as sw
+    sub = batch.subset_reads(np.arange(n_reads))
+    refs = sw.RefSet.from_codes(torch.from_numpy(sub.ref_codes).cuda(), sub.ref_off, sub.ref_len)
+    db = sw.DeviceBatch.upload(sub)
+    out = sw.Outputs(db.n_cals)
+    res = {"reads": n_reads, "cals": sub.n_cals}
+    results = {}
+    for name, kern, prec in (("inter_int16", sw.KERNEL_INTER, sw.PREC_INT16),
+                             ("inter_int32", sw.KERNEL_INTER, sw.PREC_INT32),
+                             ("intra_int32", sw.KERNEL_INTRA, sw.PREC_INT32)):
+        sc = sw.Scoring.make(2, -3, 5, 2, 32, prec, kern, 100)
+        ws = torch.empty(max(1, sw.workspace_bytes(db.n_reads, db.n_cals, sc)), dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            sw.align_batch(db, refs, sc, out, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            sw.align_batch(db, refs, sc, out, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_us"] = round(e0.elapsed_time(e1) / reps * 1e3, 1)
+        results[name] = out.score.clone()
+    res["same_outputs"] = bool(all(torch.equal(results["inter_int16"], v) for v in results.values()))
+    return res
+
+
 class Leg:
     """One workload resident on the GPU, timed on the plain and the batched path."""
 
@@ -190,6 +222,49 @@ class Leg:
 
     def free(self):
         self.ctx.close()
+
+
+def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD):
+    """Config 4: two references (A random, B = A diverged by 15% substitutions and
+    2%/base indels); reads 70/30 from B/A; each read goes to the reference with
+    the strictly higher best score (section 6.2).  Reports the outcome fractions
+    against the planted source and the scoring throughput."""
+    import torch
+    import paper_1805_00106_amd as sw
+    from paper_1805_00106_amd import workloads as wl
+
+    t_gen = time.perf_counter()
+    b = wl.config4(n_reads=n_reads)
+    t_gen = time.perf_counter() - t_gen
+    leg = Leg(b, 150, 3, 1)
+    cls_t = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        leg.step(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(leg.stream)
+    leg.step(True)
+    assert sw.lib().sw_classify(sw._ptr(leg.bs), b.n_reads, b.n_refs, threshold, sw._ptr(cls_t),
+                                sw._stream(leg.stream)) == 0
+    e1.record(leg.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cls = cls_t.cpu().numpy()
+    truth = b.true_ref
+    frac = lambda m: round(float(np.mean(m)), 5)
+    out = {"workload": f"config4: A = {int(b.ref_len[0]):,} bp random, B = A + 15% substitutions + 2%/base indels "
+                       f"({int(b.ref_len[1]):,} bp); {b.n_reads:,} reads of 150 bp, 70% from B / 30% from A, "
+                       "1% substitutions; homologous locus + Poisson(2) decoys per reference; band 32; both strands",
+           "threshold": threshold, "cals": b.n_cals, "cells": leg.cells,
+           "ms_per_step": round(ms, 3), "gcups": round(leg.cells / (ms * 1e-3) / 1e9, 1),
+           "reads_per_s": round(b.n_reads / (ms * 1e-3), 1),
+           "correct": frac(cls == truth), "incorrect": frac((cls >= 0) & (cls != truth)),
+           "tie": frac(cls == -2), "unaligned": frac(cls == -1),
+           "by_source": {src: {"correct": frac(cls[truth == k] == k), "tie": frac(cls[truth == k] == -2),
+                               "unaligned": frac(cls[truth == k] == -1)} for k, src in ((0, "A"), (1, "B"))},
+           "gen_s": round(t_gen, 1)}
+    leg.free()
+    return out
 
 
 def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9)):
@@ -288,6 +363,8 @@ def main():
     ap.add_argument("--config3-reads", type=int, default=2_000_000,
                     help="reads of the uneven-length leg (0 skips it)")
     ap.add_argument("--config3-band", type=int, default=32)
+    ap.add_argument("--config4-reads", type=int, default=1_000_000,
+                    help="reads of the two-reference classification leg (0 skips it)")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=300)
@@ -313,6 +390,7 @@ def main():
     leg = Leg(batch, int(batch.read_len.max()), args.steps, args.warmup)
     r2 = leg.run()
     parity = None if args.no_parity else parity_sample(batch, leg.out)
+    small = small_batch_latency(batch)
     n_reads, n_cals, cells = leg.db.n_reads, leg.db.n_cals, leg.cells
     leg.free()
     del leg
@@ -342,12 +420,13 @@ def main():
         leg3.free()
         del leg3
 
+    c4 = classification_leg(args.config4_reads) if args.config4_reads else None
     served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests) if args.serve_scale > 0 else None
 
     step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
     gcups = cells / (step_ms * 1e-3) / 1e9
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
-    traffic = load_traffic("inter16", "config2")
+    traffic = load_traffic("inter16_queue", "config2")
     roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_INT16_TOPS, 2),
             "unit": "Tops/s (int16 lane-ops)", "frac": round(achieved / PEAK_INT16_TOPS, 4), "traffic": traffic,
             "kernel": "k_inter16_queue", "kernel_ms": round(kern_ms, 3),
@@ -366,12 +445,15 @@ def main():
                   "reads_per_s": round(n_reads / (r2["plain_ms"] * 1e-3), 1),
                   "kernel_ms": round(r2["plain_kern_ms"], 3)},
         "plain_equals_batched": r2["plain_equals_batched"],
+        "small_batch_latency": small,
         "aligned_fraction": round(r2["aligned_fraction"], 4), "aligned_threshold": ALIGNED_THRESHOLD,
         "wall_s_timed": round(r2["wall"], 3), "gen_s": round(t_gen, 1), "parity_sample_ok": parity,
         "roofline": roof,
     }
     if c3:
         res["config3"] = c3
+    if c4:
+        res["config4"] = c4
     if served:
         res["served"] = served
         res["p50_ms"] = served["loads"][-1]["p50_ms"]

@@ -173,8 +173,10 @@ def _mutate_with_indels(rng: np.random.Generator, seq: np.ndarray, sub_rate: flo
         pos = rng.integers(0, n, n_ev)
         ln = rng.integers(1, 4, n_ev)
         is_del = rng.random(n_ev) < 0.5
-        for p, l, d in zip(pos[is_del], ln[is_del], is_del[is_del]):
-            keep[p:p + l] = 0
+        dp, dl = pos[is_del], ln[is_del]
+        for k in range(3):  # deletion lengths are 1..3
+            sel = dl > k
+            keep[np.minimum(dp[sel] + k, n - 1)] = 0
         np.add.at(ins_after, pos[~is_del], ln[~is_del])
     counts = keep + ins_after
     total = int(counts.sum())
@@ -228,41 +230,55 @@ def _repeat_index(copies):
     return arr[order]
 
 
-def _sample_reads(rng_reads, rng_err, genome: np.ndarray, lens: np.ndarray, sub_rate: float,
-                  indel_rate: float, strand_p_rev: float = 0.5):
+def _sample_reads_matrix(rng_reads, rng_err, genome: np.ndarray, lens: np.ndarray, sub_rate: float,
+                         indel_rate: float, strand_p_rev: float = 0.5):
     """Draw reads from ``genome`` with the sequencer error model.
 
-    Returns (list of read code arrays, start positions, strand flags).
+    Returns ([n, max_len] uint8 code matrix, row r valid up to lens[r]; start
+    positions; strand flags).
     """
     n = len(lens)
     glen = len(genome)
+    lens = np.asarray(lens, dtype=np.int64)
     span = lens + 8
     pos = (rng_reads.random(n) * (glen - span)).astype(np.int64)
     rev = rng_reads.random(n) < strand_p_rev
-    reads = []
     maxspan = int(span.max()) if n else 0
+    Lmax = int(lens.max()) if n else 0
     idx = pos[:, None] + np.arange(maxspan)[None, :]
     np.minimum(idx, glen - 1, out=idx)
-    seg = genome[idx]
-    seg = _substitute(rng_err, seg, sub_rate)
-    n_ev = rng_err.binomial(lens.astype(np.int64), indel_rate) if indel_rate > 0 else np.zeros(n, np.int64)
-    for r in range(n):
+    seg = _substitute(rng_err, genome[idx], sub_rate)
+    mat = np.ascontiguousarray(seg[:, :Lmax])
+    n_ev = rng_err.binomial(lens, indel_rate) if indel_rate > 0 else np.zeros(n, np.int64)
+    for r in np.nonzero(n_ev)[0]:
         L = int(lens[r])
-        s = seg[r]
-        if n_ev[r]:
-            s = s.copy()
-            for _ in range(int(n_ev[r])):
-                p = int(rng_err.integers(2, L - 2))
-                ln = int(rng_err.integers(1, 4))
-                if rng_err.random() < 0.5:
-                    s = np.concatenate([s[:p], s[p + ln:]])
-                else:
-                    s = np.concatenate([s[:p], rng_err.integers(0, 4, ln, dtype=np.uint8), s[p:]])
-        s = s[:L]
-        if rev[r]:
-            s = (3 - s[::-1]).astype(np.uint8)
-        reads.append(np.ascontiguousarray(s, dtype=np.uint8))
-    return reads, pos, rev
+        row = seg[r].copy()
+        for _ in range(int(n_ev[r])):
+            p = int(rng_err.integers(2, L - 2))
+            ln = int(rng_err.integers(1, 4))
+            if rng_err.random() < 0.5:
+                row = np.concatenate([row[:p], row[p + ln:]])
+            else:
+                row = np.concatenate([row[:p], rng_err.integers(0, 4, ln, dtype=np.uint8), row[p:]])
+        if len(row) < L:  # many deletions ate the slack: extend with random bases
+            row = np.concatenate([row, rng_err.integers(0, 4, L - len(row), dtype=np.uint8)])
+        mat[r, :L] = row[:L]
+    col = np.arange(Lmax)[None, :]
+    rr = np.nonzero(rev)[0]
+    if len(rr):
+        src = lens[rr, None] - 1 - col
+        ok = src >= 0
+        vals = 3 - mat[rr[:, None], np.maximum(src, 0)]
+        mat[rr] = np.where(ok, vals, 0).astype(np.uint8)
+    mat[col >= lens[:, None]] = 0
+    return mat, pos, rev
+
+
+def _sample_reads(rng_reads, rng_err, genome: np.ndarray, lens: np.ndarray, sub_rate: float,
+                  indel_rate: float, strand_p_rev: float = 0.5):
+    """As _sample_reads_matrix, with the reads as a list of code arrays."""
+    mat, pos, rev = _sample_reads_matrix(rng_reads, rng_err, genome, lens, sub_rate, indel_rate, strand_p_rev)
+    return [mat[r, :int(lens[r])].copy() for r in range(len(lens))], pos, rev
 
 
 def _pack_batch(refs, reads, cal_lists, scoring, true_ref, true_pos, true_strand, name):
@@ -324,7 +340,7 @@ def config1(n_reads: int = 1000, ref_len: int = 10_000, read_len: int = 76) -> B
     g = seed_streams(1)
     genome = uniform_genome(g["reference"], ref_len)
     lens = np.full(n_reads, read_len, dtype=np.int64)
-    reads, pos, rev = _sample_reads(g["reads"], g["errors"], genome, lens, 0.01, 0.001)
+    mat, pos, rev = _sample_reads_matrix(g["reads"], g["errors"], genome, lens, 0.01, 0.001)
     decoy = g["cals"].integers(0, ref_len, n_reads)
     counts = np.full(n_reads, 2, dtype=np.int64)
     cal_pos = np.stack([pos, decoy], 1).reshape(-1)
@@ -332,7 +348,7 @@ def config1(n_reads: int = 1000, ref_len: int = 10_000, read_len: int = 76) -> B
     strand = np.full(2 * n_reads, 3, dtype=np.int64)
     cal_pos, cal_ref, strand = _shuffle_rows(g["cals"], counts, cal_pos, cal_ref, strand)
     sc = Scoring(2, -3, 5, 2, 32)
-    return _vector_batch([genome], _reads_matrix(reads, lens), lens, counts, cal_pos, cal_ref, strand,
+    return _vector_batch([genome], mat, lens, counts, cal_pos, cal_ref, strand,
                          sc, np.zeros(n_reads, np.int64), pos, rev.astype(np.int64), "config1")
 
 
@@ -382,7 +398,7 @@ def _homolog_cals(rng, rep, pos, lens, want):
 def _multi_cal_batch(g, genome, copies, n_reads, lens, counts, band, name, sc_int16=True,
                      sub_rate=0.01, indel_rate=0.001):
     ref_len = len(genome)
-    reads, pos, rev = _sample_reads(g["reads"], g["errors"], genome, lens, sub_rate, indel_rate)
+    mat, pos, rev = _sample_reads_matrix(g["reads"], g["errors"], genome, lens, sub_rate, indel_rate)
     rep = _repeat_index(copies)
     homs = _homolog_cals(g["cals"], rep, pos, lens, counts - 1)
     total = int(counts.sum())
@@ -398,7 +414,7 @@ def _multi_cal_batch(g, genome, copies, n_reads, lens, counts, band, name, sc_in
     strand = np.full(total, 3, dtype=np.int64)
     cal_pos, cal_ref, strand = _shuffle_rows(g["cals"], counts, cal_pos, cal_ref, strand)
     sc = Scoring(2, -3, 5, 2, band)
-    return _vector_batch([genome], _reads_matrix(reads, lens), lens, counts, cal_pos, cal_ref, strand,
+    return _vector_batch([genome], mat, lens, counts, cal_pos, cal_ref, strand,
                          sc, np.zeros(n_reads, np.int64), pos, rev.astype(np.int64), name)
 
 
@@ -436,20 +452,18 @@ def config4(n_reads: int = 4_000_000, ref_len: int = 500_000_000, read_len: int 
     lens = np.full(n_reads, read_len, dtype=np.int64)
     from_b = gr["reads"].random(n_reads) < 0.7
     nb = int(from_b.sum())
-    reads = [None] * n_reads
+    mat = np.zeros((n_reads, read_len), dtype=np.uint8)
     src_pos = np.zeros(n_reads, dtype=np.int64)
     rev = np.zeros(n_reads, dtype=bool)
     for flag, genome in ((True, B), (False, A)):
         idx = np.nonzero(from_b == flag)[0]
-        rr, pp, vv = _sample_reads(gr["reads"], gr["errors"], genome, lens[idx], 0.01, 0.0)
-        for k, i in enumerate(idx):
-            reads[i] = rr[k]
+        mm, pp, vv = _sample_reads_matrix(gr["reads"], gr["errors"], genome, lens[idx], 0.01, 0.0)
+        mat[idx] = mm
         src_pos[idx] = pp
         rev[idx] = vv
     # homologous locus on the other reference through the coordinate map
-    b2a = np.searchsorted(a2b, np.arange(len(B)), side="right") - 1
-    b2a = np.clip(b2a, 0, ref_len - 1)
-    pos_a = np.where(from_b, b2a[np.minimum(src_pos, len(B) - 1)], src_pos)
+    b2a = np.clip(np.searchsorted(a2b, np.minimum(src_pos, len(B) - 1), side="right") - 1, 0, ref_len - 1)
+    pos_a = np.where(from_b, b2a, src_pos)
     pos_b = np.where(from_b, src_pos, a2b[np.minimum(src_pos, ref_len - 1)])
     nd_a = gr["cals"].poisson(2.0, n_reads)
     nd_b = gr["cals"].poisson(2.0, n_reads)
@@ -473,7 +487,6 @@ def config4(n_reads: int = 4_000_000, ref_len: int = 500_000_000, read_len: int 
     strand = np.full(total, 3, dtype=np.int64)
     cal_pos, cal_ref, strand = _shuffle_rows(gr["cals"], counts, cal_pos, cal_ref, strand)
     sc = Scoring(2, -3, 5, 2, 32)
-    mat = _reads_matrix(reads, lens)
     return _vector_batch([A, B], mat, lens, counts, cal_pos, cal_ref, strand, sc,
                          from_b.astype(np.int64), src_pos, rev.astype(np.int64), "config4")
 
@@ -554,16 +567,15 @@ def config5_request(refs, n_reads: int, seed: int, band: int = 32, ref_pack=None
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([ROOT_SEED + 5, 7, seed])))
     lens = rng.integers(75, 251, n_reads).astype(np.int64)
     src = rng.integers(0, len(refs), n_reads)
-    reads = [None] * n_reads
+    mat = np.zeros((n_reads, int(lens.max())), np.uint8)
     pos = np.zeros(n_reads, np.int64)
     rev = np.zeros(n_reads, bool)
     for k in range(len(refs)):
         idx = np.nonzero(src == k)[0]
         if len(idx) == 0:
             continue
-        rr, pp, vv = _sample_reads(rng, rng, refs[k], lens[idx], 0.01, 0.001)
-        for j, i in enumerate(idx):
-            reads[i] = rr[j]
+        mm, pp, vv = _sample_reads_matrix(rng, rng, refs[k], lens[idx], 0.01, 0.001)
+        mat[idx, :mm.shape[1]] = mm
         pos[idx] = pp
         rev[idx] = vv
     counts = rng.integers(1, 33, n_reads).astype(np.int64)
@@ -577,7 +589,6 @@ def config5_request(refs, n_reads: int, seed: int, band: int = 32, ref_pack=None
     cal_ref[starts] = src
     strand = np.full(total, 3, np.int64)
     sc = Scoring(2, -3, 5, 2, band)
-    mat = _reads_matrix(reads, lens)
     b = _vector_batch([], mat, lens, counts, cal_pos, cal_ref, strand, sc,
                       src.astype(np.int64), pos, rev.astype(np.int64), f"request{seed}")
     if ref_pack is None:
