@@ -320,27 +320,37 @@ class Server:
         self.n_refs = refs.n_refs
         _check(lib().sw_server_set_refs(self._h, refs.c), "sw_server_set_refs")
 
-    def submit(self, read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref, strand) -> Request:
+    def prepare(self, read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref, strand) -> Request:
+        """Contiguous inputs and freshly allocated host outputs for one submission."""
         import numpy as np
         a = [np.ascontiguousarray(read_codes, np.uint8), np.ascontiguousarray(read_code_off, np.int64),
              np.ascontiguousarray(read_len, np.int32), np.ascontiguousarray(cal_ptr, np.int64),
              np.ascontiguousarray(cal_pos, np.int64), np.ascontiguousarray(cal_ref, np.int16),
              np.ascontiguousarray(strand, np.uint8)]
-        n_reads, n_cals = len(a[2]), len(a[4])
-        req = Request(0, n_reads, n_cals, self.n_refs, a)
+        req = Request(0, len(a[2]), len(a[4]), self.n_refs, a)
         p = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+        req.args = (p(a[0]), len(a[0]), p(a[1]), p(a[2]), req.n_reads, p(a[3]), p(a[4]), p(a[5]), p(a[6]),
+                    len(a[4]), p(req.score), p(req.ref_end), p(req.read_end), p(req.best_score), p(req.best_slot),
+                    p(req.n_tied))
+        return req
+
+    def submit_prepared(self, req: Request) -> Request:
         rid = ctypes.c_int64(0)
-        rc = lib().sw_server_submit(self._h, p(a[0]), len(a[0]), p(a[1]), p(a[2]), n_reads, p(a[3]), p(a[4]),
-                                    p(a[5]), p(a[6]), n_cals, p(req.score), p(req.ref_end), p(req.read_end),
-                                    p(req.best_score), p(req.best_slot), p(req.n_tied), ctypes.byref(rid))
-        _check(rc, "sw_server_submit")
+        _check(lib().sw_server_submit(self._h, *req.args, ctypes.byref(rid)), "sw_server_submit")
         req.id = int(rid.value)
         self.requests[req.id] = req
         return req
 
+    def submit(self, read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref, strand) -> Request:
+        return self.submit_prepared(self.prepare(read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref,
+                                                 strand))
+
+    def prepare_batch(self, batch) -> Request:
+        return self.prepare(batch.read_codes, batch.read_off, batch.read_len, batch.cal_ptr, batch.cal_pos,
+                            batch.cal_ref, batch.strand)
+
     def submit_batch(self, batch) -> Request:
-        return self.submit(batch.read_codes, batch.read_off, batch.read_len, batch.cal_ptr, batch.cal_pos,
-                           batch.cal_ref, batch.strand)
+        return self.submit_prepared(self.prepare_batch(batch))
 
     def wait(self, req: Request, timeout_ms: int = -1) -> bool:
         done = ctypes.c_int32(0)

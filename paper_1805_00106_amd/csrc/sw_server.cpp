@@ -109,6 +109,7 @@ struct Request {
   int64_t next_read = 0;  // first read not yet placed in a step
   int64_t reads_done = 0;
   int state = RS_PENDING;
+  bool staged = false;  // inputs already copied into the pinned mirror at `off`
   double t_submit = 0, t_admit = 0, t_done = 0;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
@@ -129,9 +130,13 @@ struct StepSlot {  // device buffers of one step (two are used alternately)
   swk::ServeChunk *chunks_host = nullptr;  // pinned
   void *base = nullptr;
   hipEvent_t done = nullptr;
+  hipStream_t stream = nullptr;  // each slot computes on its own stream with its own context,
+  sw_ctx_t *ctx = nullptr;       // so consecutive steps overlap on the device
   bool busy = false;
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> parts;  // request and reads placed
 };
+
+constexpr int kSlots = 3;
 
 }  // namespace
 
@@ -146,9 +151,8 @@ struct sw_server {
   void *arena_dev = nullptr;
   uint8_t *arena_host = nullptr;  // pinned mirror of the arena
   std::unique_ptr<Arena> arena;
-  sw_ctx_t *ctx = nullptr;
-  hipStream_t compute = nullptr, copy = nullptr;
-  StepSlot slots[2];
+  hipStream_t copy = nullptr;
+  StepSlot slots[kSlots];
   int next_slot = 0;
   std::deque<std::shared_ptr<Request>> pending;
   std::deque<std::shared_ptr<Request>> admitted;  // admitted, not fully placed in steps
@@ -202,29 +206,42 @@ T *hptr(sw_server *s, const Request &r, size_t field) {
   return reinterpret_cast<T *>(s->arena_host + r.off + field);
 }
 
-// Admission (scheduler thread, lock held): reserve the footprint, stage the
-// inputs through the pinned mirror, upload, and pack the reads on the device.
-bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
-  size_t off = 0;
-  if (!s->arena->alloc(rq->lay.total, &off)) return false;
-  rq->off = off;
-  Request &r = *rq;
-  std::memcpy(hptr<uint8_t>(s, r, r.lay.codes), r.codes.data(), r.n_codes);
+// Copy a request's inputs into its block of the pinned mirror.
+void stage_inputs(sw_server *s, Request &r, const uint8_t *codes, const int64_t *code_off, const int32_t *len,
+                  const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand) {
+  std::memcpy(hptr<uint8_t>(s, r, r.lay.codes), codes, r.n_codes);
   int64_t *wo = hptr<int64_t>(s, r, r.lay.word_off);
-  for (int32_t i = 0; i < r.n_reads; ++i) wo[i] = r.code_off[i] / 16;
-  std::memcpy(hptr<int32_t>(s, r, r.lay.len), r.len.data(), sizeof(int32_t) * r.n_reads);
-  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_ptr), r.cal_ptr.data(), sizeof(int64_t) * (r.n_reads + 1));
-  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_pos), r.cal_pos.data(), sizeof(int64_t) * r.n_cals);
-  std::memcpy(hptr<int16_t>(s, r, r.lay.cal_ref), r.cal_ref.data(), sizeof(int16_t) * r.n_cals);
-  std::memcpy(hptr<uint8_t>(s, r, r.lay.strand), r.strand.data(), r.n_cals);
-  hipMemcpyAsync((char *)s->arena_dev + off, s->arena_host + off, r.lay.in_end, hipMemcpyHostToDevice, s->copy);
+  for (int32_t i = 0; i < r.n_reads; ++i) wo[i] = code_off[i] / 16;
+  std::memcpy(hptr<int32_t>(s, r, r.lay.len), len, sizeof(int32_t) * r.n_reads);
+  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_ptr), cal_ptr, sizeof(int64_t) * (r.n_reads + 1));
+  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_pos), cal_pos, sizeof(int64_t) * r.n_cals);
+  std::memcpy(hptr<int16_t>(s, r, r.lay.cal_ref), cal_ref, sizeof(int16_t) * r.n_cals);
+  std::memcpy(hptr<uint8_t>(s, r, r.lay.strand), strand, r.n_cals);
+  r.staged = true;
+}
+
+// Admission (scheduler thread, lock held): reserve the footprint if the
+// request did not get it at submit, stage the inputs, upload them and pack the
+// reads on the device.
+bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
+  Request &r = *rq;
+  if (!r.staged) {
+    size_t off = 0;
+    if (!s->arena->alloc(r.lay.total, &off)) return false;
+    r.off = off;
+    stage_inputs(s, r, r.codes.data(), r.code_off.data(), r.len.data(), r.cal_ptr.data(), r.cal_pos.data(),
+                 r.cal_ref.data(), r.strand.data());
+  }
+  hipMemcpyAsync((char *)s->arena_dev + r.off, s->arena_host + r.off, r.lay.in_end, hipMemcpyHostToDevice, s->copy);
   sw_pack_2bit(dptr<uint8_t>(s, r, r.lay.codes), r.n_codes, dptr<uint32_t>(s, r, r.lay.words),
                (sw_stream_t)s->copy);
   hipEventRecord(r.ev_in, s->copy);
   r.t_admit = now_s();
   r.state = RS_ADMITTED;
-  r.codes.clear();
-  r.codes.shrink_to_fit();
+  std::vector<uint8_t>().swap(r.codes);
+  std::vector<int64_t>().swap(r.cal_pos);
+  std::vector<int16_t>().swap(r.cal_ref);
+  std::vector<uint8_t>().swap(r.strand);
   return true;
 }
 
@@ -275,19 +292,19 @@ bool launch_step(sw_server *s) {
     nc += r.cal_ptr[r1] - r.cal_ptr[r0];
     r.next_read = r1;
     st.parts.emplace_back(rq, r1 - r0);
-    hipStreamWaitEvent(s->compute, r.ev_in, 0);
+    hipStreamWaitEvent(st.stream, r.ev_in, 0);
   }
   (void)words_per_read;
   while (!s->admitted.empty() && s->admitted.front()->next_read >= s->admitted.front()->n_reads)
     s->admitted.pop_front();
   if (nch == 0) return false;
-  hipStream_t cs = s->compute;
+  hipStream_t cs = st.stream;
   hipMemcpyAsync(st.chunks_dev, st.chunks_host, sizeof(swk::ServeChunk) * nch, hipMemcpyHostToDevice, cs);
   swk::launch_serve_gather(st.chunks_dev, nch, nr, nc, st.words, st.word_off, st.read_len, st.cal_ptr, st.cal_pos,
                            st.cal_ref, st.strand, cs);
   int rc = SW_OK;
   if (nc > 0) {
-    rc = sw_align_batch_ctx(s->ctx, st.words, st.word_off, st.read_len, (int32_t)nr, &s->refs, st.cal_ptr,
+    rc = sw_align_batch_ctx(st.ctx, st.words, st.word_off, st.read_len, (int32_t)nr, &s->refs, st.cal_ptr,
                             st.cal_pos, st.cal_ref, st.strand, nc, &s->sc, st.score, st.ref_end, st.read_end,
                             (sw_stream_t)cs);
   }
@@ -300,7 +317,7 @@ bool launch_step(sw_server *s) {
   hipEventRecord(st.done, cs);
   st.busy = true;
   s->in_flight.push_back(&st);
-  s->next_slot ^= 1;
+  s->next_slot = (s->next_slot + 1) % kSlots;
   s->steps++;
   s->step_reads += nr;
   s->step_cals += nc;
@@ -309,6 +326,7 @@ bool launch_step(sw_server *s) {
 
 // Retire finished steps; start the download of requests whose reads are all done.
 void retire_steps(sw_server *s) {
+  // steps retire in launch order (a request's chunks complete in order)
   while (!s->in_flight.empty() && hipEventQuery(s->in_flight.front()->done) == hipSuccess) {
     StepSlot &st = *s->in_flight.front();
     s->in_flight.pop_front();
@@ -403,8 +421,7 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
     sw_server_destroy(s);
     return SW_ERR_NOMEM;
   }
-  if ((e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking)) != hipSuccess) {
+  if ((e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking)) != hipSuccess) {
     sw_server_destroy(s);
     return swapi::hip_fail(e);
   }
@@ -425,7 +442,8 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
     if (hipMalloc(&st.base, o) != hipSuccess ||
         hipHostMalloc((void **)&st.chunks_host, sizeof(swk::ServeChunk) * opts->max_step_chunks,
                       hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) != hipSuccess) {
       sw_server_destroy(s);
       return SW_ERR_NOMEM;
     }
@@ -452,10 +470,12 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
   co.use_graph = 0;  // step shapes change every step
   co.autotune = opts->autotune;
   co.tune_cache = nullptr;
-  rc = sw_ctx_create(&co, &s->ctx);
-  if (rc) {
-    sw_server_destroy(s);
-    return rc;
+  for (auto &st : s->slots) {
+    rc = sw_ctx_create(&co, &st.ctx);
+    if (rc) {
+      sw_server_destroy(s);
+      return rc;
+    }
   }
   *out = s;
   return SW_OK;
@@ -507,14 +527,26 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
   r.n_codes = n_codes;
   r.lay = make_layout(n_reads, n_cals, n_codes, s->n_refs);
   if (r.lay.total > s->arena->size()) return SW_ERR_REJECTED;
-  r.codes.assign(read_codes, read_codes + n_codes);
+  // the step builder needs the read offsets, lengths and CAL rows on the host
   r.code_off.assign(read_code_off, read_code_off + n_reads);
   r.len.assign(read_len, read_len + n_reads);
   r.cal_ptr.assign(cal_ptr, cal_ptr + n_reads + 1);
-  if (n_cals) {
-    r.cal_pos.assign(cal_pos, cal_pos + n_cals);
-    r.cal_ref.assign(cal_ref, cal_ref + n_cals);
-    r.strand.assign(strand, strand + n_cals);
+  bool reserved = false;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    // reserve now if nobody waits ahead (arrival order) and memory is free
+    if (s->pending.empty()) reserved = s->arena->alloc(r.lay.total, &r.off);
+  }
+  if (reserved) {
+    // the caller's thread stages its own inputs into the pinned mirror
+    stage_inputs(s, r, read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref, strand);
+  } else {
+    r.codes.assign(read_codes, read_codes + n_codes);
+    if (n_cals) {
+      r.cal_pos.assign(cal_pos, cal_pos + n_cals);
+      r.cal_ref.assign(cal_ref, cal_ref + n_cals);
+      r.strand.assign(strand, strand + n_cals);
+    }
   }
   r.o_score = score;
   r.o_ref_end = ref_end;
@@ -524,11 +556,21 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
   r.o_n_tied = n_tied;
   r.t_submit = t;
   if (hipEventCreateWithFlags(&r.ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&r.ev_out, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&r.ev_out, hipEventDisableTiming) != hipSuccess) {
+    if (reserved) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->arena->release(r.off, r.lay.total);
+    }
     return SW_ERR_NOMEM;
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return SW_ERR_STATE;
+    if (s->stop) {
+      if (reserved) s->arena->release(r.off, r.lay.total);
+      hipEventDestroy(r.ev_in);
+      hipEventDestroy(r.ev_out);
+      return SW_ERR_STATE;
+    }
     r.id = s->next_id++;
     s->pending.push_back(rq);
     s->all[r.id] = rq;
@@ -603,21 +645,22 @@ int sw_server_destroy(sw_server_t *s) {
     s->worker.join();  // drains every submitted request first
   }
   hipSetDevice(s->opts.device);
-  if (s->compute) hipStreamSynchronize(s->compute);
+  for (auto &st : s->slots)
+    if (st.stream) hipStreamSynchronize(st.stream);
   if (s->copy) hipStreamSynchronize(s->copy);
   for (auto &kv : s->all) {
     if (kv.second->ev_in) hipEventDestroy(kv.second->ev_in);
     if (kv.second->ev_out) hipEventDestroy(kv.second->ev_out);
   }
-  if (s->ctx) sw_ctx_destroy(s->ctx);
   for (auto &st : s->slots) {
+    if (st.ctx) sw_ctx_destroy(st.ctx);
+    if (st.stream) hipStreamDestroy(st.stream);
     if (st.base) hipFree(st.base);
     if (st.chunks_host) hipHostFree(st.chunks_host);
     if (st.done) hipEventDestroy(st.done);
   }
   if (s->arena_dev) hipFree(s->arena_dev);
   if (s->arena_host) hipHostFree(s->arena_host);
-  if (s->compute) hipStreamDestroy(s->compute);
   if (s->copy) hipStreamDestroy(s->copy);
   delete s;
   return SW_OK;
