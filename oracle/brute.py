@@ -69,10 +69,12 @@ def transcripts(m: int, n: int):
     return out
 
 
-def local_batch(Q: np.ndarray, Wm: np.ndarray, match=2, mismatch=-3, gap_open=5, gap_extend=2):
+def local_batch(Q: np.ndarray, Wm: np.ndarray, match=2, mismatch=-3, gap_open=5, gap_extend=2, final_row=False):
     """Brute-force local alignment of N pairs of equal shape.
 
-    Q: [N, m] read codes, Wm: [N, n] window codes.
+    Q: [N, m] read codes, Wm: [N, n] window codes.  With final_row, only
+    alignments whose last read base is the read's last base count (the V1
+    array's output: the best cell of the final row).
     Returns (score, ref_end, read_end) int64 arrays of length N.
     """
     Q = np.asarray(Q, dtype=np.int64)
@@ -93,6 +95,8 @@ def local_batch(Q: np.ndarray, Wm: np.ndarray, match=2, mismatch=-3, gap_open=5,
             for p, (a, c) in enumerate(starts):
                 b, d = a + mm - 1, c + nn - 1
                 np.maximum(Hend[:, b, d], G[:, p], out=Hend[:, b, d])
+    if final_row:
+        Hend[:, :m - 1, :] = _NEG
     flat = Hend.reshape(N, m * n)
     best = np.maximum(flat.max(axis=1), 0)
     score = best.copy()

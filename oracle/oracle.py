@@ -19,7 +19,7 @@ _lib = None
 class _Scoring(ctypes.Structure):
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
                 ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
-                ("band", ctypes.c_int32)]
+                ("band", ctypes.c_int32), ("final_row", ctypes.c_int32)]
 
 
 def lib():
@@ -36,11 +36,11 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _sc(match, mismatch, gap_open, gap_extend, band=0):
-    return _Scoring(int(match), int(mismatch), int(gap_open), int(gap_extend), int(band))
+def _sc(match, mismatch, gap_open, gap_extend, band=0, final_row=False):
+    return _Scoring(int(match), int(mismatch), int(gap_open), int(gap_extend), int(band), int(bool(final_row)))
 
 
-def gotoh_pairs(qs, ws, match=2, mismatch=-3, gap_open=5, gap_extend=2):
+def gotoh_pairs(qs, ws, match=2, mismatch=-3, gap_open=5, gap_extend=2, final_row=False):
     """Score a list of (q, w) code arrays.  Returns (score, ref_end, read_end) int64 arrays."""
     n = len(qs)
     ql = np.array([len(q) for q in qs], dtype=np.int64)
@@ -55,7 +55,7 @@ def gotoh_pairs(qs, ws, match=2, mismatch=-3, gap_open=5, gap_extend=2):
     score = np.zeros(n, np.int64)
     re = np.zeros(n, np.int64)
     qe = np.zeros(n, np.int64)
-    sc = _sc(match, mismatch, gap_open, gap_extend)
+    sc = _sc(match, mismatch, gap_open, gap_extend, 0, final_row)
     lib().oracle_gotoh_many(_p(qc), _p(qo), _p(ql), _p(wc), _p(wo), _p(wl), ctypes.c_int64(n),
                             ctypes.byref(sc), _p(score), _p(re), _p(qe))
     return score, re, qe
@@ -66,7 +66,7 @@ def gotoh(q, w, **kw):
     return int(s[0]), int(r[0]), int(e[0])
 
 
-def align_batch(batch, n_threads: int = 1, max_read_len: int = MAX_READ_LEN):
+def align_batch(batch, n_threads: int = 1, max_read_len: int = MAX_READ_LEN, final_row: bool = False):
     """Oracle of the batch entry point on a workloads.Batch.  Returns
     (score int32[2n], ref_end int64[2n], read_end int16[2n], n_errors)."""
     sc = batch.scoring
@@ -86,7 +86,7 @@ def align_batch(batch, n_threads: int = 1, max_read_len: int = MAX_READ_LEN):
         cal_ref=np.ascontiguousarray(batch.cal_ref, np.int16),
         strand=np.ascontiguousarray(batch.strand, np.uint8),
     )
-    s = _sc(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band)
+    s = _sc(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, final_row)
     f = lib().oracle_align_batch
     f.restype = ctypes.c_int64
     errs = f(_p(arrs["read_codes"]), _p(arrs["read_off"]), _p(arrs["read_len"]),
@@ -108,6 +108,23 @@ def reduce_best(cal_ptr, cal_ref, n_reads, n_refs, score):
     lib().oracle_reduce_best(_p(cal_ptr), _p(cal_ref), ctypes.c_int32(n_reads), ctypes.c_int32(n_refs),
                              _p(score), _p(bs), _p(bl), _p(nt))
     return bs.reshape(n_reads, n_refs), bl.reshape(n_reads, n_refs), nt.reshape(n_reads, n_refs)
+
+
+def topk(cal_ptr, n_reads, score, k):
+    cal_ptr = np.ascontiguousarray(cal_ptr, np.int64)
+    score = np.ascontiguousarray(score, np.int32)
+    ts = np.zeros(n_reads * k, np.int32)
+    tl = np.zeros(n_reads * k, np.int64)
+    lib().oracle_topk(_p(cal_ptr), ctypes.c_int32(n_reads), _p(score), ctypes.c_int32(k), _p(ts), _p(tl))
+    return ts.reshape(n_reads, k), tl.reshape(n_reads, k)
+
+
+def tied_flags(cal_ptr, n_reads, score):
+    cal_ptr = np.ascontiguousarray(cal_ptr, np.int64)
+    score = np.ascontiguousarray(score, np.int32)
+    fl = np.zeros(len(score), np.uint8)
+    lib().oracle_tied_flags(_p(cal_ptr), ctypes.c_int32(n_reads), _p(score), _p(fl))
+    return fl
 
 
 def classify(best_score, threshold):

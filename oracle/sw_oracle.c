@@ -22,12 +22,16 @@
  *     each CAL (section 3.1): the reverse strand aligns the reverse complement
  *     of the read (complement = 3 - code with A,C,G,T = 0,1,2,3, Fig. 3)
  *     against the forward reference window.
- *   - The Score Tracker keeps the best-scoring CAL per read (sections 3.6, 4.2).
+ *   - The Score Tracker keeps the best-scoring CAL per read (sections 3.6, 4.2),
+ *     or some number of the best CALs, or all CALs tied for the best score
+ *     (the variants section 4.2 lists).
  *
  * Readings of points the paper leaves open (each is also listed in the design
  * notes of the repository):
- *   - score = the maximum over every cell of H (a full local maximum), not only
- *     the final row;
+ *   - score = the maximum over every cell of H (a full local maximum) by
+ *     default; the final-row mode keeps only the last read row, which is the
+ *     paper's own V1 output (the best cell of the final row, sections 3.5 and
+ *     3.6), so the alignment ends at the read's last base;
  *   - window = [p - band, p + L + band) clipped to the reference;
  *   - ties inside a task: highest score, then smallest reference end, then
  *     smallest read end; score 0 reports both ends as -1;
@@ -45,6 +49,10 @@
 
 typedef struct {
   int32_t match, mismatch, gap_open, gap_extend, band;
+  /* 0: best cell anywhere (full local maximum); 1: best cell of the final row
+   * only, i.e. the alignment must end at the last read base (the V1 array's
+   * output, sections 3.5 and 3.6) */
+  int32_t final_row;
 } oracle_scoring_t;
 
 /* Result of one task. */
@@ -88,8 +96,9 @@ static oracle_hit_t gotoh_full(const uint8_t *q, int64_t L, const uint8_t *w, in
   }
   /* best cell: highest score, then smallest window column, then smallest read row */
   oracle_hit_t best = {0, -1, -1};
+  const int64_t i_first = sc->final_row ? L : 1;
   for (int64_t j = 1; j <= W; ++j) {
-    for (int64_t i = 1; i <= L; ++i) {
+    for (int64_t i = i_first; i <= L; ++i) {
       int64_t v = AT(H, i, j);
       if (v > best.score) {
         best.score = v;
@@ -275,6 +284,55 @@ void oracle_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t 
         }
       }
     }
+  }
+}
+
+/*
+ * Score Tracker variants (section 4.2: the single best CAL, some number of
+ * highest-scoring CALs, or all CALs tied for the highest score).
+ * Top k slots of each read over all its CALs and strands: highest score first,
+ * lower slot index first among equal scores; negative scores are skipped and
+ * missing entries are (-1, -1).  Outputs [n_reads * k].
+ */
+void oracle_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *top_score,
+                 int64_t *top_slot) {
+  for (int64_t r = 0; r < n_reads; ++r) {
+    for (int32_t t = 0; t < k; ++t) {
+      top_score[r * k + t] = -1;
+      top_slot[r * k + t] = -1;
+    }
+    for (int64_t slot = 2 * cal_ptr[r]; slot < 2 * cal_ptr[r + 1]; ++slot) {
+      int32_t s = score[slot];
+      if (s < 0) continue;
+      /* insert into the sorted list if it beats the last entry */
+      int32_t pos = k;
+      while (pos > 0) {
+        int32_t ps = top_score[r * k + pos - 1];
+        int64_t pl = top_slot[r * k + pos - 1];
+        int beats = pl < 0 || s > ps || (s == ps && slot < pl);
+        if (!beats) break;
+        pos--;
+      }
+      if (pos >= k) continue;
+      for (int32_t t = k - 1; t > pos; --t) {
+        top_score[r * k + t] = top_score[r * k + t - 1];
+        top_slot[r * k + t] = top_slot[r * k + t - 1];
+      }
+      top_score[r * k + pos] = s;
+      top_slot[r * k + pos] = slot;
+    }
+  }
+}
+
+/* Slots whose score equals the best score of their read over all references
+ * (and is non-negative): flag 1, else 0.  Output [2 * n_cals]. */
+void oracle_tied_flags(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags) {
+  for (int64_t r = 0; r < n_reads; ++r) {
+    int32_t best = -1;
+    for (int64_t slot = 2 * cal_ptr[r]; slot < 2 * cal_ptr[r + 1]; ++slot)
+      if (score[slot] > best) best = score[slot];
+    for (int64_t slot = 2 * cal_ptr[r]; slot < 2 * cal_ptr[r + 1]; ++slot)
+      flags[slot] = (best >= 0 && score[slot] == best) ? 1 : 0;
   }
 }
 

@@ -320,3 +320,88 @@ def test_planted_error_free_reads_recover_their_locus():
         assert score[slot] == 2 * 76
         assert ref_end[slot] == pos[r] + 75
         assert read_end[slot] == 75
+
+
+# ------------------------------------------------------------------ final-row mode and tracker variants
+#
+# The V1 array reports the best cell of the matrix's final row (sections 3.5
+# and 3.6): the alignment must end at the read's last base.  The brute force
+# restricts its end cells to that row; it shares no code with the recurrences.
+
+@pytest.mark.parametrize("m,n", [(1, 3), (2, 3), (3, 4), (4, 4)])
+def test_final_row_exhaustive_brute_force(m, n):
+    Q, W, s, r, e = brute.exhaustive(m, n, final_row=True)
+    os_, or_, oe = o.gotoh_pairs(list(Q), list(W), final_row=True)
+    np.testing.assert_array_equal(os_, s)
+    np.testing.assert_array_equal(or_, r)
+    np.testing.assert_array_equal(oe, e)
+    assert np.all((e == m - 1) | (s == 0))
+
+
+@pytest.mark.parametrize("sc", SCORINGS)
+def test_final_row_random_brute_force(sc):
+    rng = np.random.default_rng(77)
+    N, m, n = 120, 5, 7
+    Q = rng.integers(0, 4, (N, m)).astype(np.uint8)
+    W = rng.integers(0, 4, (N, n)).astype(np.uint8)
+    for k in range(0, N, 2):   # planted near-copies so gapped end-anchored alignments occur
+        Q[k] = np.resize(np.delete(W[k], rng.integers(0, n)), m)
+    s, r, e = brute.local_batch(Q, W, final_row=True, **sc)
+    os_, or_, oe = o.gotoh_pairs(list(Q), list(W), final_row=True, **sc)
+    np.testing.assert_array_equal(os_, s)
+    np.testing.assert_array_equal(or_, r)
+    np.testing.assert_array_equal(oe, e)
+
+
+def test_final_row_closed_forms():
+    """L = 76 with the workloads' scoring: a mismatch at the read's last base costs the
+    full-local score one base (2(L-1), ending one row early) but the final-row score keeps
+    the mismatch (2(L-1) - 3, ending at row L-1)."""
+    ref = _base_ref()
+    read = ref[50:126].copy()
+    assert o.gotoh(read, ref) == (152, 125, 75)
+    assert o.gotoh(read, ref, final_row=True) == (152, 125, 75)
+    read[-1] = (read[-1] + 1) % 4
+    assert o.gotoh(read, ref) == (150, 124, 74)
+    assert o.gotoh(read, ref, final_row=True) == (147, 125, 75)
+
+
+def test_final_row_never_exceeds_local_and_agrees_when_local_ends_last():
+    for q, w in _pairs(31):
+        full = o.gotoh(q, w)
+        fr = o.gotoh(q, w, final_row=True)
+        assert 0 <= fr[0] <= full[0]
+        if full[0] > 0 and full[2] == len(q) - 1:
+            assert fr == full
+        if fr[0] > 0:
+            assert fr[2] == len(q) - 1
+
+
+def _slots_of(b, score, r):
+    return [(int(score[s]), s) for c in range(b.cal_ptr[r], b.cal_ptr[r + 1]) for s in (2 * c, 2 * c + 1)]
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 64])
+def test_topk_and_tied_definitions(k):
+    b = wl.random_small_batch(8, n_reads=70, max_cals=9, n_refs=2, band=6)
+    score, _, _, _ = o.align_batch(b)
+    score = score.copy()
+    score[::7] = np.where(score[::7] >= 0, score[::7] // 8 * 8, score[::7])   # many equal scores
+    ts, tl = o.topk(b.cal_ptr, b.n_reads, score, k)
+    fl = o.tied_flags(b.cal_ptr, b.n_reads, score)
+    for r in range(b.n_reads):
+        valid = sorted([t for t in _slots_of(b, score, r) if t[0] >= 0], key=lambda t: (-t[0], t[1]))
+        want = valid[:k] + [(-1, -1)] * (k - min(k, len(valid)))
+        assert list(zip(ts[r].tolist(), tl[r].tolist())) == want
+        top = valid[0][0] if valid else None
+        for s_, slot in _slots_of(b, score, r):
+            assert fl[slot] == (1 if top is not None and s_ == top else 0)
+    # top-1 agrees with the single-best tracker reduced over references
+    t1s, t1l = o.topk(b.cal_ptr, b.n_reads, score, 1)
+    bs, bl, nt = o.reduce_best(b.cal_ptr, b.cal_ref, b.n_reads, b.n_refs, score)
+    for r in range(b.n_reads):
+        row = [(int(bs[r, j]), int(bl[r, j])) for j in range(b.n_refs) if bl[r, j] >= 0]
+        row.sort(key=lambda t: (-t[0], t[1]))
+        assert (int(t1s[r, 0]), int(t1l[r, 0])) == (row[0] if row else (-1, -1))
+        assert int(fl[2 * b.cal_ptr[r]:2 * b.cal_ptr[r + 1]].sum()) == sum(
+            int(nt[r, j]) for j in range(b.n_refs) if row and bs[r, j] == row[0][0])
