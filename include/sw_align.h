@@ -72,6 +72,12 @@ typedef struct ihipStream_t *sw_stream_t; /* a hipStream_t */
 #define SW_KERNEL_INTER 1 /* one CAL per lane (both strands in one lane) */
 #define SW_KERNEL_INTRA 2 /* one wavefront per CAL, lanes hold window columns */
 
+/* which cells may end an alignment */
+#define SW_MODE_LOCAL 0     /* any cell: the full local maximum */
+#define SW_MODE_FINAL_ROW 1 /* the last read row only: the best cell of the final row
+                               of the matrix, so the alignment ends at the read's last
+                               base (sections 3.5 and 3.6; read_end is then L-1) */
+
 /* strand mask bits of a CAL (section 3.1: a strand bit is kept with each CAL) */
 #define SW_STRAND_FWD 1
 #define SW_STRAND_REV 2
@@ -86,6 +92,7 @@ typedef struct {
   int32_t kernel;       /* SW_KERNEL_* */
   int32_t max_read_len; /* upper bound on every read length of the call, 1..SW_MAX_READ_LEN
                            (0 means SW_MAX_READ_LEN); reads above it are flagged as errors */
+  int32_t mode;         /* SW_MODE_*; 0 (zero-initialised) is SW_MODE_LOCAL */
 } sw_scoring_t;
 
 /* References resident in device memory (the paper keeps the whole 2-bit
@@ -157,6 +164,29 @@ int sw_error_count(int64_t *n_invalid, int reset);
 int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
                    const int32_t *score, int32_t *best_score, int64_t *best_slot, int32_t *n_tied,
                    sw_stream_t stream);
+
+/*
+ * Score Tracker variants (section 4.2: keep the best CAL, a number of
+ * highest-scoring CALs, or every CAL tied for the highest score).
+ *
+ * sw_topk: the k best slots of each read over all its CALs and both strands,
+ * highest score first and the lower slot index first among equal scores.
+ *   k           1..SW_MAX_TOPK
+ *   top_score   device [n_reads*k] scores, -1 past the read's valid slots
+ *   top_slot    device [n_reads*k] slot indices (2c fwd, 2c+1 rev), -1 likewise
+ * Slots with negative scores (not requested, invalid) are skipped.
+ *
+ * sw_tied_flags: flags[slot] = 1 if the slot's score equals the highest
+ * non-negative score of its read over all its slots, else 0.
+ *   flags       device [2*n_cals]; n_cals = cal_ptr[n_reads] (read on device)
+ * Both are asynchronous on `stream`; invalid host arguments return
+ * SW_ERR_INVALID_ARG before any device work.
+ */
+#define SW_MAX_TOPK 64
+int sw_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *top_score,
+            int64_t *top_slot, sw_stream_t stream);
+int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
+                  sw_stream_t stream);
 
 /*
  * Classification of reads between references by best score (section 6.2,

@@ -15,9 +15,9 @@ import torch  # load torch's HIP runtime before the library so both share it
 
 __all__ = [
     "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
-    "reduce_best", "classify", "error_count", "SwError", "Context", "Outputs", "Server", "Request",
+    "reduce_best", "topk", "tied_flags", "classify", "error_count", "SwError", "Context", "Outputs", "Server", "Request",
     "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
-    "MAX_READ_LEN", "MAX_REFS",
+    "MODE_LOCAL", "MODE_FINAL_ROW", "MAX_READ_LEN", "MAX_REFS", "MAX_TOPK",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +25,9 @@ LIB_PATH = os.path.join(HERE, "libswalign.so")
 
 PREC_AUTO, PREC_INT16, PREC_INT32 = 0, 1, 2
 KERNEL_AUTO, KERNEL_INTER, KERNEL_INTRA = 0, 1, 2
+MODE_LOCAL, MODE_FINAL_ROW = 0, 1
 MAX_READ_LEN = 1024
+MAX_TOPK = 64
 MAX_REFS = 64
 
 _lib = None
@@ -43,12 +45,12 @@ class SwError(RuntimeError):
 class Scoring(ctypes.Structure):
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap_open", ctypes.c_int32),
                 ("gap_extend", ctypes.c_int32), ("band", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("max_read_len", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("max_read_len", ctypes.c_int32), ("mode", ctypes.c_int32)]
 
     @classmethod
     def make(cls, match=2, mismatch=-3, gap_open=5, gap_extend=2, band=32, precision=PREC_AUTO,
-             kernel=KERNEL_AUTO, max_read_len=0):
-        return cls(match, mismatch, gap_open, gap_extend, band, precision, kernel, max_read_len)
+             kernel=KERNEL_AUTO, max_read_len=0, mode=MODE_LOCAL):
+        return cls(match, mismatch, gap_open, gap_extend, band, precision, kernel, max_read_len, mode)
 
 
 class _RefSetC(ctypes.Structure):
@@ -94,6 +96,8 @@ def lib():
         L.sw_error_count.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.sw_reduce_best.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
         L.sw_classify.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.sw_topk.argtypes = [vp, i32, vp, i32, vp, vp, vp]
+        L.sw_tied_flags.argtypes = [vp, i32, vp, vp, vp]
         L.sw_ctx_create.argtypes = [ctypes.POINTER(_CtxOpts), ctypes.POINTER(vp)]
         L.sw_ctx_destroy.argtypes = [vp]
         L.sw_align_batch_ctx.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, vp, i64,
@@ -234,6 +238,23 @@ def reduce_best(db: DeviceBatch, n_refs: int, score: torch.Tensor, stream=None):
     _check(lib().sw_reduce_best(_ptr(db.cal_ptr), _ptr(db.cal_ref), n, n_refs, _ptr(score), _ptr(bs), _ptr(bl),
                                 _ptr(nt), _stream(stream)), "sw_reduce_best")
     return bs.view(n, n_refs), bl.view(n, n_refs), nt.view(n, n_refs)
+
+
+def topk(db: DeviceBatch, score: torch.Tensor, k: int, stream=None):
+    """The k best slots of each read (score, slot), highest score first; -1 past the valid slots."""
+    n = db.n_reads
+    ts = torch.empty(n * k, dtype=torch.int32, device=score.device)
+    tl = torch.empty(n * k, dtype=torch.int64, device=score.device)
+    _check(lib().sw_topk(_ptr(db.cal_ptr), n, _ptr(score), k, _ptr(ts), _ptr(tl), _stream(stream)), "sw_topk")
+    return ts.view(n, k), tl.view(n, k)
+
+
+def tied_flags(db: DeviceBatch, score: torch.Tensor, stream=None) -> torch.Tensor:
+    """1 for every slot whose score equals its read's best score, else 0."""
+    fl = torch.empty(score.numel(), dtype=torch.uint8, device=score.device)
+    _check(lib().sw_tied_flags(_ptr(db.cal_ptr), db.n_reads, _ptr(score), _ptr(fl), _stream(stream)),
+           "sw_tied_flags")
+    return fl
 
 
 def classify(best_score: torch.Tensor, threshold: int, stream=None) -> torch.Tensor:

@@ -25,6 +25,7 @@ int validate_scoring(const sw_scoring_t *sc, ScoreMode *mode) {
   if (!sc) return SW_ERR_INVALID_ARG;
   if (sc->precision < SW_PREC_AUTO || sc->precision > SW_PREC_INT32) return SW_ERR_INVALID_ARG;
   if (sc->kernel < SW_KERNEL_AUTO || sc->kernel > SW_KERNEL_INTRA) return SW_ERR_INVALID_ARG;
+  if (sc->mode != SW_MODE_LOCAL && sc->mode != SW_MODE_FINAL_ROW) return SW_ERR_INVALID_ARG;
   if (sc->match < 1 || sc->mismatch > 0 || sc->gap_open < 0 || sc->gap_extend < 1) return SW_ERR_SCORING;
   if (sc->band < 0 || sc->band > SW_MAX_BAND) return SW_ERR_SCORING;
   int mrl = sc->max_read_len == 0 ? SW_MAX_READ_LEN : sc->max_read_len;
@@ -74,6 +75,7 @@ DpConstHost make_consts(const sw_scoring_t *sc) {
   k.sm32 = sc->match * 4096 - 1;
   k.sx32 = sc->mismatch * 4096 - 1;
   k.e0_32 = 0;
+  k.final_row = sc->mode == SW_MODE_FINAL_ROW ? 1 : 0;
   return k;
 }
 
@@ -347,6 +349,24 @@ int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_rea
   if (!cal_ptr || !cal_ref || !score || !best_score || !best_slot || !n_tied) return SW_ERR_INVALID_ARG;
   hipError_t e = swk::launch_reduce(cal_ptr, cal_ref, n_reads, n_refs, score, best_score, best_slot, n_tied,
                                     (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+int sw_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *top_score,
+            int64_t *top_slot, sw_stream_t stream) {
+  if (n_reads < 0 || k < 1 || k > SW_MAX_TOPK) return SW_ERR_INVALID_ARG;
+  if (n_reads == 0) return SW_OK;
+  if (!cal_ptr || !score || !top_score || !top_slot) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_topk(cal_ptr, n_reads, score, k, top_score, top_slot, (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
+                  sw_stream_t stream) {
+  if (n_reads < 0) return SW_ERR_INVALID_ARG;
+  if (n_reads == 0) return SW_OK;
+  if (!cal_ptr || !score || !flags) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_tied(cal_ptr, n_reads, score, flags, (hipStream_t)stream);
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 

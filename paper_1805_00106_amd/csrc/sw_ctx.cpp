@@ -196,7 +196,7 @@ std::string graph_key(const CallArgs &a, const swapi::ScoreMode &m, const TunedP
                 (const void *)a.cal_ref, (const void *)a.strand, (const void *)a.score, (long long)a.n_cals,
                 a.sc->match, a.sc->mismatch, a.sc->gap_open, a.sc->gap_extend, a.sc->band, m.max_read_len,
                 (const void *)a.ref_end, (const void *)a.read_end, (const void *)nullptr, (int)m.int16, t.bin_width,
-                t.descending, grid, 0);
+                t.descending, grid, a.sc->mode);
   std::string s(k);
   for (int i = 0; i < a.refs->n_refs; ++i) {
     char r[64];

@@ -30,6 +30,8 @@ struct DpConst {
   uint32_t xlo, dlo, xhi, dhi;  // substitution table bytes (see the kernel)
   // int32 (K = 12)
   int32_t goe_e32, ge_e32, goe_f32, ge_f32, sm32, sx32, e0_32;
+  // 1: only the last read row may hold the best cell (read-end-anchored scoring)
+  int32_t final_row;
 };
 
 struct AlignArgs {

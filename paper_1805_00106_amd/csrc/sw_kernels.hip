@@ -365,6 +365,12 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
       }
       if (!LAST) scr[c * 64 + lane] = make_uint2(bits(Hl[R - 1]), bits(F));
     }
+    if (K.final_row) {
+      // read-end-anchored scoring: only row L-1 may hold the best cell
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r0 + r != L - 1) M[r] = pair(0u);
+    }
     fold16<R>(M, r0, tb, best_f, best_r);
     if (tend < Wmax) {
       // next tile: restart the row maxima and re-base the carried tags by +64
@@ -528,7 +534,13 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       const int32_t zt = 4095 - c;
       if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
       int32_t w = (int32_t)((wd >> (2 * (c & 15))) & 3u);
-      if (c >= W) w = 5;  // past the window: never matches
+      // past the lane's window: a wall (no diagonal move enters these columns, so
+      // no cell there can beat a real cell of its row, which the final-row mode needs)
+      int32_t sx = K.sx32;
+      if (c >= W) {
+        w = 5;
+        sx = -(1 << 30);
+      }
       int32_t hup, F;
       if (s == 0) {
         hup = zt;
@@ -544,7 +556,7 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       hup_prev = hup;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int32_t sub = q[r] == w ? K.sm32 : K.sx32;
+        const int32_t sub = q[r] == w ? K.sm32 : sx;
         int32_t H = max(max(Hd + sub, E[r]), F);
         H = max(H, zt);
         M[r] = max(M[r], H);
@@ -559,7 +571,7 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
     for (int r = 0; r < R; ++r) {
       const int i = r0 + r;
       int32_t v = M[r] >> 12;
-      if (i < L && v > 0) {
+      if (i < L && v > 0 && (!K.final_row || i == L - 1)) {
         uint64_t kk = cell_key(v, 4095 - (M[r] & 4095), i);
         best = kk > best ? kk : best;
       }
@@ -674,6 +686,7 @@ __global__ __launch_bounds__(64) void k_intra32(const AlignArgs A, const RefTabl
     __syncthreads();
 
     uint64_t best = 0;
+    const int row_lo = K.final_row ? L - 1 : 0;  // first row that may hold the best cell
     const int nstrips = (W + 63) >> 6;
     for (int s = 0; s < nstrips; ++s) {
       const int col = 64 * s + lane;
@@ -719,7 +732,7 @@ __global__ __launch_bounds__(64) void k_intra32(const AlignArgs A, const RefTabl
           const int32_t sub = q == w ? SM : SX;
           int32_t Hn = max(max(Hdiag + sub, Ein), F);
           Hn = max(Hn, zt);
-          M = max(M, Hn);
+          M = max(M, i >= row_lo ? Hn : 0);
           const int32_t U = Hn - GOE;
           Eout = max(Ein - GE, U);
           F = max(F - GE, U);
@@ -820,6 +833,50 @@ __global__ void k_reduce_best(const int64_t *__restrict__ cal_ptr, const int16_t
       }
     }
   }
+}
+
+// One thread per read: the k best slots over all CALs and strands (highest
+// score, then lowest slot), kept sorted in the output rows by insertion.
+__global__ void k_topk(const int64_t *__restrict__ cal_ptr, int32_t n_reads, const int32_t *__restrict__ score,
+                       int32_t k, int32_t *__restrict__ top_score, int64_t *__restrict__ top_slot) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  int32_t *ts = top_score + r * k;
+  int64_t *tl = top_slot + r * k;
+  int n = 0;              // entries filled
+  int32_t last = INT32_MAX; // score of entry k-1 once the list is full
+  const int64_t s_end = 2 * cal_ptr[r + 1];
+  for (int64_t slot = 2 * cal_ptr[r]; slot < s_end; ++slot) {
+    const int32_t s = score[slot];
+    if (s < 0) continue;
+    // slots arrive in increasing order, so an equal score never displaces an entry
+    if (n == k && s <= last) continue;
+    int pos = n < k ? n : k - 1;
+    while (pos > 0 && ts[pos - 1] < s) {
+      ts[pos] = ts[pos - 1];
+      tl[pos] = tl[pos - 1];
+      --pos;
+    }
+    ts[pos] = s;
+    tl[pos] = slot;
+    if (n < k) ++n;
+    if (n == k) last = ts[k - 1];
+  }
+  for (int i = n; i < k; ++i) {
+    ts[i] = -1;
+    tl[i] = -1;
+  }
+}
+
+// One thread per read: mark every slot whose score equals the read's best.
+__global__ void k_tied(const int64_t *__restrict__ cal_ptr, int32_t n_reads, const int32_t *__restrict__ score,
+                       uint8_t *__restrict__ flags) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  const int64_t a = 2 * cal_ptr[r], b = 2 * cal_ptr[r + 1];
+  int32_t best = -1;
+  for (int64_t slot = a; slot < b; ++slot) best = max(best, score[slot]);
+  for (int64_t slot = a; slot < b; ++slot) flags[slot] = (best >= 0 && score[slot] == best) ? 1 : 0;
 }
 
 __global__ void k_classify(const int32_t *__restrict__ best_score, int32_t n_reads, int32_t n_refs,
@@ -1068,6 +1125,20 @@ hipError_t launch_reduce(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t
   if (n_reads == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_best, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, cal_ref,
                      n_reads, n_refs, score, bs, bl, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *ts,
+                       int64_t *tl, hipStream_t st) {
+  if (n_reads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_topk, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, n_reads, score, k, ts, tl);
+  return hipGetLastError();
+}
+
+hipError_t launch_tied(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
+                       hipStream_t st) {
+  if (n_reads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tied, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, n_reads, score, flags);
   return hipGetLastError();
 }
 

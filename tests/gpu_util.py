@@ -6,30 +6,38 @@ import paper_1805_00106_amd as sw
 from oracle import oracle as orc
 
 
-def scoring_for(batch, precision, kernel=0, max_read_len=None):
+def scoring_for(batch, precision, kernel=0, max_read_len=None, mode=sw.MODE_LOCAL):
     sc = batch.scoring
     mrl = int(batch.read_len.max()) if max_read_len is None and batch.n_reads else (max_read_len or 0)
     return sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, precision, kernel,
-                           max(mrl, 1) if mrl else 0)
+                           max(mrl, 1) if mrl else 0, mode)
 
 
-def gpu_align(batch, precision=sw.PREC_AUTO, kernel=0, max_read_len=None, reduce=True):
+def gpu_align(batch, precision=sw.PREC_AUTO, kernel=0, max_read_len=None, reduce=True, mode=sw.MODE_LOCAL,
+              topk=0):
     refs = sw.RefSet.from_codes(torch.from_numpy(batch.ref_codes).cuda(), batch.ref_off, batch.ref_len)
     db = sw.DeviceBatch.upload(batch)
-    scoring = scoring_for(batch, precision, kernel, max_read_len)
+    scoring = scoring_for(batch, precision, kernel, max_read_len, mode)
     out = sw.align_batch(db, refs, scoring)
     res = dict(score=out.score, ref_end=out.ref_end, read_end=out.read_end)
     if reduce:
         bs, bl, nt = sw.reduce_best(db, batch.n_refs, out.score)
         res.update(best_score=bs, best_slot=bl, n_tied=nt)
+    if topk:
+        ts, tl = sw.topk(db, out.score, topk)
+        res.update(top_score=ts, top_slot=tl, tied=sw.tied_flags(db, out.score))
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in res.items()}
 
 
-def oracle_align(batch, threads=8):
-    s, r, e, errs = orc.align_batch(batch, n_threads=threads)
+def oracle_align(batch, threads=8, mode=sw.MODE_LOCAL, topk=0):
+    s, r, e, errs = orc.align_batch(batch, n_threads=threads, final_row=mode == sw.MODE_FINAL_ROW)
     bs, bl, nt = orc.reduce_best(batch.cal_ptr, batch.cal_ref, batch.n_reads, batch.n_refs, s)
-    return dict(score=s, ref_end=r, read_end=e, best_score=bs, best_slot=bl, n_tied=nt), errs
+    res = dict(score=s, ref_end=r, read_end=e, best_score=bs, best_slot=bl, n_tied=nt)
+    if topk:
+        ts, tl = orc.topk(batch.cal_ptr, batch.n_reads, s, topk)
+        res.update(top_score=ts, top_slot=tl, tied=orc.tied_flags(batch.cal_ptr, batch.n_reads, s))
+    return res, errs
 
 
 def assert_same(got, exp, what=""):

@@ -27,6 +27,7 @@ def sw():
 def test_header_declares_entry_points():
     names = _declared_functions()
     for n in ("sw_align_batch", "sw_workspace_bytes", "sw_reduce_best", "sw_classify", "sw_pack_2bit",
+              "sw_topk", "sw_tied_flags",
               "sw_ctx_create", "sw_align_batch_ctx", "sw_strerror"):
         assert n in names
 
@@ -62,7 +63,7 @@ def _call(sw, sc, refs=None, n_cals=4, workspace=None, n_reads=2):
 @pytest.mark.parametrize("field,value,code", [
     ("match", 0, -2), ("mismatch", 1, -2), ("gap_open", -1, -2), ("gap_extend", 0, -2), ("band", -1, -2),
     ("band", 5000, -2), ("precision", 7, -1), ("kernel", 9, -1), ("max_read_len", 5000, -3),
-    ("max_read_len", -3, -1),
+    ("max_read_len", -3, -1), ("mode", 2, -1), ("mode", -1, -1),
 ])
 def test_scoring_validation(sw, field, value, code):
     sc = sw.Scoring.make(max_read_len=100)
@@ -105,3 +106,16 @@ def test_reduce_and_classify_validation(sw):
     assert L.sw_reduce_best(p, p, 1, 65, p, p, p, p, None) == -8
     assert L.sw_classify(p, 1, 0, 0, p, None) == -1
     assert L.sw_pack_2bit(p, -1, p, None) == -1
+
+
+def test_topk_and_tied_validation(sw):
+    L = sw.lib()
+    p = ctypes.c_void_p(16)
+    assert L.sw_topk(p, -1, p, 1, p, p, None) == -1
+    assert L.sw_topk(p, 1, p, 0, p, p, None) == -1
+    assert L.sw_topk(p, 1, p, sw.MAX_TOPK + 1, p, p, None) == -1
+    assert L.sw_topk(None, 1, p, 1, p, p, None) == -1
+    assert L.sw_topk(p, 0, p, 1, p, p, None) == 0
+    assert L.sw_tied_flags(p, -1, p, p, None) == -1
+    assert L.sw_tied_flags(p, 1, None, p, None) == -1
+    assert L.sw_tied_flags(p, 0, p, p, None) == 0

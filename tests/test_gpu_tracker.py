@@ -1,0 +1,88 @@
+"""GPU parity of the Score Tracker variants and the final-row (read-end-anchored)
+mode against the oracle: bit-exact scores, ends, top-k lists and tie flags."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1805_00106_amd as sw
+from paper_1805_00106_amd import workloads as wl
+from tests.gpu_util import assert_same, gpu_align, oracle_align, scoring_for
+
+pytestmark = pytest.mark.gpu
+
+FR = sw.MODE_FINAL_ROW
+KERNELS = [(sw.PREC_INT16, sw.KERNEL_INTER), (sw.PREC_INT32, sw.KERNEL_INTER), (sw.PREC_INT32, sw.KERNEL_INTRA)]
+
+
+def _fr_case(batch, **kw):
+    exp, _ = oracle_align(batch, mode=FR)
+    for prec, kern in KERNELS:
+        got = gpu_align(batch, prec, kernel=kern, mode=FR, **kw)
+        assert_same(got, exp, f"{batch.name} final-row prec={prec} kernel={kern} {kw}")
+    assert np.all((exp["read_end"] == batch.read_len[_slot_read(batch)] - 1) | (exp["score"] <= 0))
+
+
+def _slot_read(batch):
+    return np.repeat(np.repeat(np.arange(batch.n_reads), np.diff(batch.cal_ptr)), 2)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_final_row_ragged(seed):
+    """Ragged reads 1..120 bp (several strips of rows), clipped windows, strand masks."""
+    _fr_case(wl.random_small_batch(40 + seed, n_reads=90, read_len=(1, 120), band=10))
+
+
+def test_final_row_long_reads_many_tiles():
+    """Windows up to 378 columns: several 64-column tiles per strip."""
+    b = wl.random_small_batch(45, n_reads=40, read_len=(150, 250), ref_len=(300, 3000), band=64)
+    _fr_case(b, max_read_len=250)
+
+
+def test_final_row_config2_shape():
+    _fr_case(wl.config2(n_reads=2000))
+
+
+def test_final_row_single_base_and_homopolymers():
+    _fr_case(wl.random_small_batch(46, n_reads=60, read_len=(1, 1), band=3))
+    _fr_case(wl.random_small_batch(47, n_reads=40, read_len=(1, 90), band=20, homopolymer=True))
+
+
+def test_final_row_batched_context_replays():
+    b = wl.config3(n_reads=600, band=32)
+    exp, _ = oracle_align(b, mode=FR)
+    refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
+    db = sw.DeviceBatch.upload(b)
+    ctx = sw.Context(b.n_reads, b.n_cals)
+    out = sw.Outputs(db.n_cals)
+    for mode in (FR, sw.MODE_LOCAL, FR):
+        want = exp if mode == FR else oracle_align(b)[0]
+        sc = scoring_for(b, sw.PREC_INT16, max_read_len=250, mode=mode)
+        for rep in range(2):
+            out.score.fill_(-7)
+            torch.cuda.synchronize()
+            ctx.align(db, refs, sc, out)
+            torch.cuda.synchronize()
+            got = dict(score=out.score.cpu().numpy(), ref_end=out.ref_end.cpu().numpy(),
+                       read_end=out.read_end.cpu().numpy())
+            assert_same(got, want, f"ctx mode={mode} rep={rep} ({ctx.last_plan()})")
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, sw.MAX_TOPK])
+def test_topk_and_tied_flags(k):
+    b = wl.random_small_batch(50, n_reads=150, max_cals=12, n_refs=2, band=6, read_len=(1, 40))
+    exp, _ = oracle_align(b, topk=k)
+    got = gpu_align(b, sw.PREC_INT16, topk=k)
+    assert_same(got, exp, f"top-{k}")
+
+
+def test_topk_many_ties_and_invalid_slots():
+    """Homopolymer reads give many equal scores; invalid CALs (INT32_MIN) and
+    unrequested strands (-1) must be skipped."""
+    b = wl.random_small_batch(51, n_reads=80, max_cals=10, band=8, read_len=(1, 30), homopolymer=True)
+    b.cal_pos = b.cal_pos.copy()
+    b.cal_pos[::5] = -3
+    exp, errs = oracle_align(b, topk=4)
+    assert errs > 0
+    got = gpu_align(b, sw.PREC_INT16, topk=4)
+    assert_same(got, exp, "top-4 with ties and invalid slots")
