@@ -98,6 +98,41 @@ def align_batch(batch, n_threads: int = 1, max_read_len: int = MAX_READ_LEN, fin
     return score, ref_end, read_end, int(errs)
 
 
+CIGAR_CHARS = {1: "I", 2: "D", 4: "S", 7: "=", 8: "X"}
+
+
+def cigar_string(ops):
+    """Text form of (length << 4) | op entries."""
+    return "".join(f"{int(v) >> 4}{CIGAR_CHARS[int(v) & 15]}" for v in ops)
+
+
+def traceback(batch, score, ref_end, read_end, slots, cap=64, max_read_len: int = MAX_READ_LEN):
+    """Start and CIGAR of each slot in `slots` (see oracle_traceback).  Returns
+    (ref_start int64[n], read_start int16[n], n_ops int32[n], cigar uint32[n, cap])."""
+    sc = batch.scoring
+    slots = np.ascontiguousarray(slots, np.int64)
+    n = len(slots)
+    score = np.ascontiguousarray(score, np.int32)
+    ref_end = np.ascontiguousarray(ref_end, np.int64)
+    read_end = np.ascontiguousarray(read_end, np.int16)
+    rs = np.zeros(n, np.int64)
+    qs = np.zeros(n, np.int16)
+    nops = np.zeros(n, np.int32)
+    cig = np.zeros(max(n, 1) * cap, np.uint32)
+    arrs = [np.ascontiguousarray(batch.read_codes, np.uint8), np.ascontiguousarray(batch.read_off, np.int64),
+            np.ascontiguousarray(batch.read_len, np.int32), np.ascontiguousarray(batch.ref_codes, np.uint8),
+            np.ascontiguousarray(batch.ref_off, np.int64), np.ascontiguousarray(batch.ref_len, np.int64),
+            np.ascontiguousarray(batch.cal_ptr, np.int64), np.ascontiguousarray(batch.cal_pos, np.int64),
+            np.ascontiguousarray(batch.cal_ref, np.int16)]
+    s_ = _sc(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band)
+    lib().oracle_traceback(_p(arrs[0]), _p(arrs[1]), _p(arrs[2]), ctypes.c_int32(batch.n_reads), _p(arrs[3]),
+                           _p(arrs[4]), _p(arrs[5]), ctypes.c_int32(batch.n_refs), _p(arrs[6]), _p(arrs[7]),
+                           _p(arrs[8]), ctypes.c_int64(batch.n_cals), ctypes.byref(s_),
+                           ctypes.c_int32(max_read_len), _p(score), _p(ref_end), _p(read_end), _p(slots),
+                           ctypes.c_int64(n), ctypes.c_int32(cap), _p(rs), _p(qs), _p(nops), _p(cig))
+    return rs, qs, nops, cig[:n * cap].reshape(n, cap)
+
+
 def reduce_best(cal_ptr, cal_ref, n_reads, n_refs, score):
     cal_ptr = np.ascontiguousarray(cal_ptr, np.int64)
     cal_ref = np.ascontiguousarray(cal_ref, np.int16)

@@ -361,3 +361,175 @@ void oracle_classify(const int32_t *best_score, int32_t n_reads, int32_t n_refs,
     else cls[r] = arg;
   }
 }
+
+/*
+ * Start position and CIGAR of selected slots (the alignment behind a score;
+ * section 7 names CIGAR generation as the step that follows scoring).
+ *
+ * For slot 2c+h with a positive score, the full H, E, F matrices of the task
+ * are rebuilt and walked backwards from the reported end cell.  Several
+ * alignments can reach the same score; this walk fixes one by taking, at every
+ * cell, the first move that explains its value:
+ *   - in H: the diagonal first, then the gap consuming a read base (F), then
+ *     the gap consuming a window base (E); a diagonal step that lands on a
+ *     cell with H = 0 (or on the boundary) ends the walk: the alignment starts
+ *     at the cell it left;
+ *   - in F or E: leave the gap (it was opened from H) whenever that explains
+ *     the value, otherwise extend it.
+ * Operations use the BAM numbering: 1 = I (read base, no window base),
+ * 2 = D (window base, no read base), 4 = S (soft clip), 7 = '=' (match),
+ * 8 = X (mismatch); each entry is (length << 4) | op, in forward reference
+ * order, with the read's unaligned head and tail as soft clips.
+ * Outputs per entry t of `slots`: ref_start (absolute forward position),
+ * read_start (in the oriented read), n_ops and cigar[t*cap .. t*cap+n_ops).
+ * n_ops = 0 with starts -1 when the slot is -1 or its score is not positive;
+ * n_ops = -1 when more than `cap` operations are needed; n_ops = -2 when the
+ * slot, its task or its reported end is invalid (the end cell's H differs from
+ * the reported score).
+ */
+typedef struct {
+  uint32_t op, len;
+} oracle_run_t;
+
+static void push_op(oracle_run_t *runs, int64_t *n, uint32_t op) {
+  if (*n > 0 && runs[*n - 1].op == op) {
+    runs[*n - 1].len++;
+  } else {
+    runs[*n].op = op;
+    runs[*n].len = 1;
+    (*n)++;
+  }
+}
+
+void oracle_traceback(const uint8_t *read_codes, const int64_t *read_off, const int32_t *read_len, int32_t n_reads,
+                      const uint8_t *ref_codes, const int64_t *ref_off, const int64_t *ref_len, int32_t n_refs,
+                      const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref, int64_t n_cals,
+                      const oracle_scoring_t *sc, int32_t max_read_len, const int32_t *score, const int64_t *ref_end,
+                      const int16_t *read_end, const int64_t *slots, int64_t n_slots, int32_t cap,
+                      int64_t *out_ref_start, int16_t *out_read_start, int32_t *out_n_ops, uint32_t *cigar) {
+  const int64_t go = sc->gap_open, ge = sc->gap_extend;
+  for (int64_t t = 0; t < n_slots; ++t) {
+    out_ref_start[t] = -1;
+    out_read_start[t] = -1;
+    out_n_ops[t] = 0;
+    const int64_t slot = slots[t];
+    if (slot == -1) continue;
+    if (slot < 0 || slot >= 2 * n_cals) {
+      out_n_ops[t] = -2;
+      continue;
+    }
+    const int64_t c = slot >> 1;
+    const int h = (int)(slot & 1);
+    if (score[slot] <= 0) continue;
+    /* owning read: the r with cal_ptr[r] <= c < cal_ptr[r+1] (bisection over
+     * the non-decreasing row pointer) */
+    int64_t r = -1;
+    if (n_reads > 0 && cal_ptr[0] <= c && c < cal_ptr[n_reads]) {
+      int64_t lo = 0, hi = n_reads; /* cal_ptr[lo] <= c < cal_ptr[hi] */
+      while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (cal_ptr[mid] <= c) lo = mid; else hi = mid;
+      }
+      r = lo;
+    }
+    const int64_t k = cal_ref[c];
+    const int64_t p = cal_pos[c];
+    const int64_t L = r >= 0 ? read_len[r] : 0;
+    if (r < 0 || k < 0 || k >= n_refs || L < 1 || L > max_read_len || p < 0 || p >= ref_len[k]) {
+      out_n_ops[t] = -2;
+      continue;
+    }
+    int64_t ws = p - sc->band;
+    if (ws < 0) ws = 0;
+    int64_t we = p + L + sc->band;
+    if (we > ref_len[k]) we = ref_len[k];
+    const int64_t W = we - ws;
+    const int64_t ie = read_end[slot], je = ref_end[slot] - ws; /* 0-based end cell */
+    if (ie < 0 || ie >= L || je < 0 || je >= W) {
+      out_n_ops[t] = -2;
+      continue;
+    }
+    uint8_t *q = (uint8_t *)malloc((size_t)L);
+    const uint8_t *read = read_codes + read_off[r];
+    for (int64_t i = 0; i < L; ++i) q[i] = h == 0 ? read[i] : (uint8_t)(3 - read[L - 1 - i]);
+    const uint8_t *w = ref_codes + ref_off[k] + ws;
+    const int64_t cols = W + 1;
+    int64_t *H = (int64_t *)malloc((size_t)(3 * (L + 1) * cols) * sizeof(int64_t));
+    int64_t *E = H + (L + 1) * cols;
+    int64_t *F = E + (L + 1) * cols;
+#define AT(M, i, j) M[(i) * cols + (j)]
+    for (int64_t j = 0; j <= W; ++j) {
+      AT(H, 0, j) = 0;
+      AT(E, 0, j) = ORACLE_NEG_INF;
+      AT(F, 0, j) = ORACLE_NEG_INF;
+    }
+    for (int64_t i = 1; i <= L; ++i) {
+      AT(H, i, 0) = 0;
+      AT(E, i, 0) = ORACLE_NEG_INF;
+      AT(F, i, 0) = ORACLE_NEG_INF;
+      for (int64_t j = 1; j <= W; ++j) {
+        const int64_t s = q[i - 1] == w[j - 1] ? sc->match : sc->mismatch;
+        AT(E, i, j) = max2(AT(E, i, j - 1) - ge, AT(H, i, j - 1) - go - ge);
+        AT(F, i, j) = max2(AT(F, i - 1, j) - ge, AT(H, i - 1, j) - go - ge);
+        AT(H, i, j) = max2(max2(AT(H, i - 1, j - 1) + s, AT(E, i, j)), max2(AT(F, i, j), 0));
+      }
+    }
+    /* 1-based walk from the end cell; runs are collected end first */
+    int64_t i = ie + 1, j = je + 1;
+    if (AT(H, i, j) != score[slot]) {
+      out_n_ops[t] = -2;
+      free(H);
+      free(q);
+      continue;
+    }
+    oracle_run_t *runs = (oracle_run_t *)malloc((size_t)(L + W + 2) * sizeof(oracle_run_t));
+    int64_t n = 0;
+    if (L - i > 0) {
+      runs[0].op = 4;
+      runs[0].len = (uint32_t)(L - i);
+      n = 1;
+    }
+    enum { ST_H, ST_E, ST_F } st = ST_H;
+    for (;;) {
+      if (st == ST_H) {
+        if (i == 0 || j == 0 || AT(H, i, j) == 0) break; /* the previous diagonal step was the first pair */
+        const int64_t s = q[i - 1] == w[j - 1] ? sc->match : sc->mismatch;
+        if (AT(H, i, j) == AT(H, i - 1, j - 1) + s) {
+          push_op(runs, &n, q[i - 1] == w[j - 1] ? 7u : 8u);
+          --i;
+          --j;
+        } else if (AT(H, i, j) == AT(F, i, j)) {
+          st = ST_F;
+        } else {
+          st = ST_E;
+        }
+      } else if (st == ST_F) {
+        push_op(runs, &n, 1u);
+        if (AT(F, i, j) == AT(H, i - 1, j) - go - ge) st = ST_H;
+        --i;
+      } else {
+        push_op(runs, &n, 2u);
+        if (AT(E, i, j) == AT(H, i, j - 1) - go - ge) st = ST_H;
+        --j;
+      }
+    }
+#undef AT
+    /* (i, j) is now the 1-based predecessor of the first aligned pair */
+    if (i > 0) {
+      runs[n].op = 4;
+      runs[n].len = (uint32_t)i;
+      n++;
+    }
+    if (n > cap) {
+      out_n_ops[t] = -1;
+    } else {
+      out_ref_start[t] = ws + j;
+      out_read_start[t] = (int16_t)i;
+      out_n_ops[t] = (int32_t)n;
+      for (int64_t x = 0; x < n; ++x) cigar[t * cap + x] = (runs[n - 1 - x].len << 4) | runs[n - 1 - x].op;
+    }
+    free(runs);
+    free(H);
+    free(q);
+  }
+}

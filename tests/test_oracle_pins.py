@@ -405,3 +405,153 @@ def test_topk_and_tied_definitions(k):
         assert (int(t1s[r, 0]), int(t1l[r, 0])) == (row[0] if row else (-1, -1))
         assert int(fl[2 * b.cal_ptr[r]:2 * b.cal_ptr[r + 1]].sum()) == sum(
             int(nt[r, j]) for j in range(b.n_refs) if row and bs[r, j] == row[0][0])
+
+
+# ------------------------------------------------------------------ traceback (start + CIGAR)
+#
+# The rescorer below walks a CIGAR over the read and the window and adds up
+# the transcript score by the affine-gap definition; it shares nothing with the
+# recurrences.  A traceback is pinned when its CIGAR is well formed, consumes
+# exactly the reported spans, agrees with the bases ('=' vs 'X') and rescores
+# to the reported (brute-force-pinned) best score.
+
+def _ops(cig, n):
+    return [(int(v) >> 4, int(v) & 15) for v in cig[:n]]
+
+
+def _rescore(ops, q, w, read_start, win_start, match, mismatch, gap_open, gap_extend):
+    assert all(n > 0 for n, _ in ops)
+    assert all(a[1] != b[1] for a, b in zip(ops, ops[1:])), "adjacent runs of one op"
+    body = list(ops)
+    head = body.pop(0)[0] if body and body[0][1] == 4 else 0
+    tail = body.pop()[0] if body and body[-1][1] == 4 else 0
+    assert head == read_start
+    assert body and body[0][1] in (7, 8) and body[-1][1] in (7, 8), "alignment must start and end on a pair"
+    i, j, total = read_start, win_start, 0
+    for n, op in body:
+        assert op in (1, 2, 7, 8)
+        if op in (7, 8):
+            for _ in range(n):
+                assert (q[i] == w[j]) == (op == 7)
+                total += match if op == 7 else mismatch
+                i += 1
+                j += 1
+        elif op == 1:
+            total -= gap_open + n * gap_extend
+            i += n
+        else:
+            total -= gap_open + n * gap_extend
+            j += n
+    assert i + tail == len(q)
+    return total, i - 1, j - 1
+
+
+def _trace_pairs(pairs, sc=None, cap=64):
+    sc = sc or dict(match=2, mismatch=-3, gap_open=5, gap_extend=2)
+    index = {}
+    refs = []
+    for _, w in pairs:       # one reference per distinct window (reference ids are int16)
+        if bytes(w) not in index:
+            index[bytes(w)] = len(refs)
+            refs.append(w)
+    reads = [q for q, _ in pairs]
+    cals = [[(0, index[bytes(w)], 1)] for _, w in pairs]
+    band = max(len(w) for w in refs)
+    b = wl._pack_batch(refs, reads, cals, wl.Scoring(**sc, band=band), None, None, None, "pairs")
+    score, ref_end, read_end, errs = o.align_batch(b)
+    assert errs == 0
+    slots = np.arange(0, 2 * len(pairs), 2)
+    rs, qs, nops, cig = o.traceback(b, score, ref_end, read_end, slots, cap=cap)
+    return b, score[slots], ref_end[slots], read_end[slots], rs, qs, nops, cig
+
+
+def _check_traces(pairs, sc=None):
+    scd = sc or dict(match=2, mismatch=-3, gap_open=5, gap_extend=2)
+    b, s, re_, qe, rs, qs, nops, cig = _trace_pairs(pairs, sc)
+    for t, (q, w) in enumerate(pairs):
+        if s[t] <= 0:
+            assert (nops[t], rs[t], qs[t]) == (0, -1, -1)
+            continue
+        assert nops[t] > 0
+        total, qend, wend = _rescore(_ops(cig[t], nops[t]), q, w, int(qs[t]), int(rs[t]), **scd)
+        assert (total, qend, wend) == (s[t], qe[t], re_[t])
+    return b, s, rs, qs, nops, cig
+
+
+@pytest.mark.parametrize("sc", SCORINGS)
+def test_traceback_rescores_to_best_score_random(sc):
+    _check_traces(_pairs(41, n=150), sc)
+
+
+@pytest.mark.parametrize("m,n", [(3, 4), (4, 4), (3, 5)])
+def test_traceback_exhaustive_tiny(m, n):
+    """Every pair of tiny strings: the traced alignment is optimal (its rescored
+    value equals the brute-force maximum) and ends at the reported cell."""
+    Q, W, s, r, e = brute.exhaustive(m, n)
+    pairs = list(zip(Q, W))
+    b, s2, rs, qs, nops, cig = _check_traces(pairs)
+    np.testing.assert_array_equal(s2, s)
+
+
+def test_traceback_closed_forms():
+    ref = _base_ref()
+    cases = []
+    read = ref[50:126].copy()
+    cases.append((read, "76=", 50))
+    read = ref[50:126].copy()
+    read[38] = (read[38] + 1) % 4
+    cases.append((read, "38=1X37=", 50))
+    read = np.concatenate([ref[50:88], ref[89:127]])
+    cases.append((read, None, 50))      # 76 '=' around one 1-base D
+    extra = np.array([(ref[88] + 2) % 4], np.uint8)
+    read = np.concatenate([ref[50:88], extra, ref[88:125]])
+    cases.append((read, None, 50))      # 75 '=' around one 1-base I
+    b, s, rs, qs, nops, cig = _check_traces([(q, ref) for q, _, _ in cases])
+    for t, (q, want, start) in enumerate(cases):
+        text = o.cigar_string(cig[t][:nops[t]])
+        assert rs[t] == start and qs[t] == 0
+        if want:
+            assert text == want
+    ops2 = _ops(cig[2], nops[2])
+    assert [op for _, op in ops2] == [7, 2, 7] and ops2[1][0] == 1 and ops2[0][0] + ops2[2][0] == 76
+    ops3 = _ops(cig[3], nops[3])
+    assert [op for _, op in ops3] == [7, 1, 7] and ops3[1][0] == 1 and ops3[0][0] + ops3[2][0] == 75
+
+
+def test_traceback_soft_clips_and_reverse_strand():
+    """A read whose middle 40 bases come from the reference: soft clips at both
+    ends.  The reverse strand traces the reverse complement of the read."""
+    ref = _base_ref(3, 300)
+    rng = np.random.default_rng(5)
+    mid = ref[100:140]
+    read = np.concatenate([rng.integers(0, 4, 18).astype(np.uint8), mid, rng.integers(0, 4, 18).astype(np.uint8)])
+    rc = (3 - read[::-1]).astype(np.uint8)
+    cals = [[(82, 0, 3)], [(82, 0, 3)]]
+    b = wl._pack_batch([ref], [read, rc], cals, wl.Scoring(band=32), None, None, None, "clips")
+    score, ref_end, read_end, _ = o.align_batch(b)
+    rs, qs, nops, cig = o.traceback(b, score, ref_end, read_end, [0, 1, 2, 3], cap=32)
+    # slot 0 (forward of read) and slot 3 (reverse of its reverse complement) are the same alignment
+    assert score[0] == score[3] >= 80
+    for t in (0, 3):
+        text = o.cigar_string(cig[t][:nops[t]])
+        assert text.endswith("S") and text[0].isdigit() and "S" in text[:4]
+        assert rs[t] == ref_end[t] - sum(n for n, op in _ops(cig[t], nops[t]) if op in (2, 7, 8)) + 1
+    assert (rs[0], qs[0], nops[0]) == (rs[3], qs[3], nops[3])
+    np.testing.assert_array_equal(cig[0][:nops[0]], cig[3][:nops[3]])
+
+
+def test_traceback_skip_capacity_and_invalid():
+    ref = _base_ref()
+    read = ref[50:126].copy()
+    read[10] = (read[10] + 1) % 4
+    read[60] = (read[60] + 1) % 4
+    b = wl._pack_batch([ref], [read], [[(50, 0, 1)]], wl.Scoring(band=32), None, None, None, "cap")
+    score, ref_end, read_end, _ = o.align_batch(b)
+    rs, qs, nops, cig = o.traceback(b, score, ref_end, read_end, [-1, 0, 0, 1, 7, -5], cap=5)
+    assert list(nops) == [0, 5, 5, 0, -2, -2]          # slot 1 was not requested: score -1
+    rs, qs, nops, cig = o.traceback(b, score, ref_end, read_end, [0], cap=4)
+    assert nops[0] == -1 and rs[0] == -1                # 10= 1X 49= 1X 15= needs 5 entries
+    bad = score.copy()
+    bad[0] += 1
+    rs, qs, nops, cig = o.traceback(b, bad, ref_end, read_end, [0], cap=8)
+    assert nops[0] == -2                                # reported score does not match the end cell
