@@ -188,6 +188,50 @@ int sw_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32
 int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
                   sw_stream_t stream);
 
+/* ------------------------------------------------------------------ traceback */
+/*
+ * Start position and CIGAR of selected slots.  The paper's hardware reports
+ * only the score and the end (sections 3.5, 3.6); section 7 names CIGAR
+ * generation as the work that follows.  For each entry t of `slots` (a slot
+ * index 2c+h into the outputs of a scoring call, or -1 to skip) the task's
+ * dynamic program is rebuilt up to the reported end cell and walked backwards.
+ * Where several alignments reach the score, the walk takes at every cell the
+ * first move that explains its value: the diagonal, then a gap consuming a read
+ * base, then a gap consuming a window base; inside a gap it returns to H (the
+ * gap was opened there) whenever that explains the value; a diagonal step onto
+ * a cell with H = 0 ends the alignment.
+ *   reads2bit .. n_cals   the arrays of the scoring call (strands come from the slot)
+ *   sc                    the scoring of that call (band, max_read_len and the
+ *                         penalties must match; precision, kernel and mode are
+ *                         not used)
+ *   score, ref_end, read_end   device [2*n_cals]: the scoring call's outputs
+ *   slots                 device [n_slots] int64
+ *   cap                   CIGAR entries per slot (>= 1)
+ * Outputs, device:
+ *   ref_start  [n_slots]  absolute forward position of the first aligned window
+ *                         base; -1 when n_ops <= 0
+ *   read_start [n_slots]  first aligned base of the oriented read; -1 likewise
+ *   n_ops      [n_slots]  entries written; 0 for a skipped slot or a score <= 0;
+ *                         -1 if more than cap entries are needed; -2 if the slot,
+ *                         its task or its end cell is invalid (the end cell's H
+ *                         differs from the reported score), counted by
+ *                         sw_error_count()
+ *   cigar      [n_slots*cap]  (length << 4) | op in forward reference order, BAM
+ *                         op codes: 1 I (read base only), 2 D (window base only),
+ *                         4 S (soft clip: unaligned head and tail of the read),
+ *                         7 '=' (match), 8 X (mismatch)
+ * `workspace` must hold sw_traceback_workspace_bytes(n_slots, sc) bytes (0 when
+ * the per-task buffers fit in on-chip memory: reads up to a few hundred bases)
+ * and must not be used by an overlapping call.
+ */
+int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
+                 int32_t n_reads, const sw_refset_t *refs, const int64_t *cal_ptr, const int64_t *cal_pos,
+                 const int16_t *cal_ref, int64_t n_cals, const sw_scoring_t *sc, const int32_t *score,
+                 const int64_t *ref_end, const int16_t *read_end, const int64_t *slots, int64_t n_slots,
+                 int32_t cap, int64_t *ref_start, int16_t *read_start, int32_t *n_ops, uint32_t *cigar,
+                 void *workspace, size_t workspace_bytes, sw_stream_t stream);
+size_t sw_traceback_workspace_bytes(int64_t n_slots, const sw_scoring_t *sc);
+
 /*
  * Classification of reads between references by best score (section 6.2,
  * xenograft case study): cls[r] = the reference with the strictly highest best

@@ -15,7 +15,7 @@ import torch  # load torch's HIP runtime before the library so both share it
 
 __all__ = [
     "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
-    "reduce_best", "topk", "tied_flags", "classify", "error_count", "SwError", "Context", "Outputs", "Server", "Request",
+    "reduce_best", "topk", "tied_flags", "classify", "error_count", "traceback", "cigar_text", "SwError", "Context", "Outputs", "Server", "Request",
     "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
     "MODE_LOCAL", "MODE_FINAL_ROW", "MAX_READ_LEN", "MAX_REFS", "MAX_TOPK",
 ]
@@ -97,6 +97,11 @@ def lib():
         L.sw_reduce_best.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
         L.sw_classify.argtypes = [vp, i32, i32, i32, vp, vp]
         L.sw_topk.argtypes = [vp, i32, vp, i32, vp, vp, vp]
+        L.sw_traceback.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, i64,
+                                   ctypes.POINTER(Scoring), vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp,
+                                   ctypes.c_size_t, vp]
+        L.sw_traceback_workspace_bytes.argtypes = [i64, ctypes.POINTER(Scoring)]
+        L.sw_traceback_workspace_bytes.restype = ctypes.c_size_t
         L.sw_tied_flags.argtypes = [vp, i32, vp, vp, vp]
         L.sw_ctx_create.argtypes = [ctypes.POINTER(_CtxOpts), ctypes.POINTER(vp)]
         L.sw_ctx_destroy.argtypes = [vp]
@@ -255,6 +260,46 @@ def tied_flags(db: DeviceBatch, score: torch.Tensor, stream=None) -> torch.Tenso
     _check(lib().sw_tied_flags(_ptr(db.cal_ptr), db.n_reads, _ptr(score), _ptr(fl), _stream(stream)),
            "sw_tied_flags")
     return fl
+
+
+def traceback(db: DeviceBatch, refs: "RefSet", sc: Scoring, out: "Outputs", slots: torch.Tensor, cap: int = 64,
+              stream=None):
+    """Start position and CIGAR of each slot in `slots` (int64 device tensor, -1 to skip), from
+    the outputs `out` of a scoring call on the same batch.  Returns (ref_start, read_start,
+    n_ops, cigar[n, cap]); entries are (length << 4) | op with BAM op codes."""
+    slots = slots.to(device=out.score.device, dtype=torch.int64).contiguous()
+    n = slots.numel()
+    dev = out.score.device
+    rs = torch.empty(n, dtype=torch.int64, device=dev)
+    qs = torch.empty(n, dtype=torch.int16, device=dev)
+    nops = torch.empty(n, dtype=torch.int32, device=dev)
+    cig = torch.zeros(max(n, 1) * cap, dtype=torch.int32, device=dev)
+    nb = lib().sw_traceback_workspace_bytes(n, ctypes.byref(sc))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    _check(lib().sw_traceback(_ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len), db.n_reads, refs.c,
+                              _ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref), db.n_cals, ctypes.byref(sc),
+                              _ptr(out.score), _ptr(out.ref_end), _ptr(out.read_end), _ptr(slots), n, cap,
+                              _ptr(rs), _ptr(qs), _ptr(nops), _ptr(cig), _ptr(ws), nb, _stream(stream)),
+           "sw_traceback")
+    return rs, qs, nops, cig[:n * cap].view(n, cap)
+
+
+_OP_TEXT = {1: "I", 2: "D", 4: "S", 7: "=", 8: "X"}
+
+
+def cigar_text(entries, n_ops: int, extended: bool = True) -> str:
+    """SAM text of one CIGAR row; extended=False folds '=' and 'X' into 'M'."""
+    out = []
+    for v in list(entries)[:max(n_ops, 0)]:
+        v = int(v) & 0xFFFFFFFF
+        op = _OP_TEXT[v & 15]
+        if not extended and op in "=X":
+            op = "M"
+        if out and out[-1][1] == op:
+            out[-1][0] += v >> 4
+        else:
+            out.append([v >> 4, op])
+    return "".join(f"{n}{op}" for n, op in out)
 
 
 def classify(best_score: torch.Tensor, threshold: int, stream=None) -> torch.Tensor:

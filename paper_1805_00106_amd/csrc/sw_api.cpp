@@ -352,6 +352,96 @@ int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_rea
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 
+namespace {
+
+// Grid and workspace of a traceback launch.
+struct TraceLaunch {
+  swk::TracePlan P;
+  int grid;
+  size_t bytes;  // workspace: per-block plane buffers when they do not fit in LDS
+};
+
+int trace_launch(int64_t n_slots, const sw_scoring_t *sc, TraceLaunch *t) {
+  ScoreMode m;
+  int rc = validate_scoring(sc, &m);
+  if (rc) return rc;
+  t->P = swk::trace_plan(m.max_read_len, m.wcap);
+  const int64_t resident = (int64_t)device_cus() * swk::trace_blocks_per_cu(t->P);
+  t->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_slots, resident));
+  t->bytes = t->P.lds_planes ? 0 : (size_t)t->grid * t->P.planes_bytes;
+  return SW_OK;
+}
+
+}  // namespace
+
+size_t sw_traceback_workspace_bytes(int64_t n_slots, const sw_scoring_t *sc) {
+  if (n_slots <= 0) return 0;
+  TraceLaunch t;
+  if (trace_launch(n_slots, sc, &t) != SW_OK) return 0;
+  return t.bytes;
+}
+
+int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len, int32_t n_reads,
+                 const sw_refset_t *refs, const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref,
+                 int64_t n_cals, const sw_scoring_t *sc, const int32_t *score, const int64_t *ref_end,
+                 const int16_t *read_end, const int64_t *slots, int64_t n_slots, int32_t cap, int64_t *ref_start,
+                 int16_t *read_start, int32_t *n_ops, uint32_t *cigar, void *workspace, size_t workspace_bytes,
+                 sw_stream_t stream) {
+  ScoreMode m;
+  int rc = validate_scoring(sc, &m);
+  if (rc) return rc;
+  if (n_reads < 0 || n_cals < 0 || n_slots < 0 || cap < 1) return SW_ERR_INVALID_ARG;
+  swk::RefTable T;
+  rc = validate_refs(refs, n_cals, &T);
+  if (rc) return rc;
+  if (n_slots == 0) return SW_OK;
+  if (!reads2bit || !read_word_off || !read_len || !cal_ptr || !cal_pos || !cal_ref || !score || !ref_end ||
+      !read_end || !slots || !ref_start || !read_start || !n_ops || !cigar)
+    return SW_ERR_INVALID_ARG;
+  TraceLaunch tl;
+  rc = trace_launch(n_slots, sc, &tl);
+  if (rc) return rc;
+  if (tl.bytes > 0 && (!workspace || workspace_bytes < tl.bytes)) return SW_ERR_WORKSPACE;
+  unsigned long long *err = swk::error_counter();
+  if (!err) return hip_fail(hipErrorInvalidDevice);
+  swk::TraceArgs A{};
+  A.reads = reads2bit;
+  A.read_word_off = read_word_off;
+  A.read_len = read_len;
+  A.n_reads = n_reads;
+  A.n_refs = refs->n_refs;
+  A.ref_words = refs->words;
+  A.cal_ptr = cal_ptr;
+  A.cal_pos = cal_pos;
+  A.cal_ref = cal_ref;
+  A.n_cals = n_cals;
+  A.score = score;
+  A.ref_end = ref_end;
+  A.read_end = read_end;
+  A.slots = slots;
+  A.n_slots = n_slots;
+  A.cap = cap;
+  A.ref_start = ref_start;
+  A.read_start = read_start;
+  A.n_ops = n_ops;
+  A.cigar = cigar;
+  A.planes_global = tl.P.lds_planes ? nullptr : static_cast<uint64_t *>(workspace);
+  A.planes_stride = (int64_t)(tl.P.planes_bytes / 8);
+  A.err = err;
+  A.max_read_len = m.max_read_len;
+  A.band = sc->band;
+  A.match = sc->match;
+  A.mismatch = sc->mismatch;
+  A.goe = sc->gap_open + sc->gap_extend;
+  A.ge = sc->gap_extend;
+  A.q_bytes = tl.P.q_bytes;
+  A.win_words = tl.P.win_words;
+  A.run_cap = tl.P.run_cap;
+  A.planes_lds_off = (int64_t)tl.P.planes_lds_off;
+  hipError_t e = swk::launch_trace(A, T, tl.P, tl.grid, (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
 int sw_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *top_score,
             int64_t *top_slot, sw_stream_t stream) {
   if (n_reads < 0 || k < 1 || k > SW_MAX_TOPK) return SW_ERR_INVALID_ARG;

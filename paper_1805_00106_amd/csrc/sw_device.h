@@ -67,4 +67,35 @@ struct AlignArgs {
   DpConst k;
 };
 
+// Traceback launch (start position and CIGAR of selected slots).
+struct TraceArgs {
+  const uint32_t *reads;
+  const int64_t *read_word_off;
+  const int32_t *read_len;
+  int32_t n_reads;
+  int32_t n_refs;
+  const uint32_t *ref_words;
+  const int64_t *cal_ptr;
+  const int64_t *cal_pos;
+  const int16_t *cal_ref;
+  int64_t n_cals;
+  const int32_t *score;      // scoring outputs, indexed by slot
+  const int64_t *ref_end;
+  const int16_t *read_end;
+  const int64_t *slots;      // [n_slots] slot to trace, -1 to skip
+  int64_t n_slots;
+  int32_t cap;               // CIGAR entries per traced slot
+  int64_t *ref_start;
+  int16_t *read_start;
+  int32_t *n_ops;
+  uint32_t *cigar;           // [n_slots][cap]
+  uint64_t *planes_global;   // per-block plane buffers when they do not fit in LDS
+  int64_t planes_stride;     // 64-bit words per block in planes_global
+  unsigned long long *err;
+  int32_t max_read_len, band;
+  int32_t match, mismatch, goe, ge;
+  int32_t q_bytes, win_words, run_cap;
+  int64_t planes_lds_off;
+};
+
 }  // namespace swk

@@ -55,6 +55,16 @@ hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T,
 int queue_blocks_per_cu(bool int16);
 hipError_t launch_intra(const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
 int intra_blocks_per_cu(size_t lds);
+// Traceback: LDS layout and plane storage of one launch.
+constexpr size_t kTraceLdsLimit = 64 * 1024;  // plane buffers move to device memory above this
+struct TracePlan {
+  int q_bytes, win_words, run_cap;
+  size_t planes_lds_off, planes_bytes, lds;
+  bool lds_planes;
+};
+TracePlan trace_plan(int max_read_len, int wcap);
+int trace_blocks_per_cu(const TracePlan &P);
+hipError_t launch_trace(const TraceArgs &A, const RefTable &T, const TracePlan &P, int grid, hipStream_t st);
 // Address of the library's device-resident invalid-task counter on the current device.
 unsigned long long *error_counter();
 

@@ -1,0 +1,328 @@
+// Traceback kernel for gfx950: start position and CIGAR of selected tasks.
+//
+// One wavefront per traced slot.  The task's dynamic program is rebuilt over
+// the rectangle that ends at its reported end cell (rows 0..read_end, window
+// columns 0..ref_end - ws): every value of that rectangle depends only on
+// cells above and to the left, so it equals the scoring pass.  Lane j holds
+// window column 64*s + j of strip s and the strip is swept along
+// anti-diagonals (step t: lane j computes row t - j), as in the wavefront-
+// per-task scoring kernel but with plain int32 values: no position tracking is
+// needed here.
+//
+// Each step stores four 64-bit ballots (one bit per lane, so one bit per
+// cell) to a plane buffer:
+//   P0, P1  source of H(i,j):  0 diagonal, 1 gap consuming a read base (F),
+//           2 gap consuming a window base (E), 3 H(i,j) = 0
+//           (the first source in this order that reaches the value)
+//   P2      E(i,j+1) is opened from H(i,j)  (open preferred on a tie)
+//   P3      F(i+1,j) is opened from H(i,j)  (open preferred on a tie)
+// The walk then runs backwards from the end cell with those rules; it is wave
+// uniform and its only memory traffic is one plane word per move.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_device.h"
+#include "sw_launch.h"
+
+namespace swk {
+
+namespace {
+
+__device__ __forceinline__ int32_t shr1(int32_t old, int32_t src) {
+  return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+
+// Owner read of CAL c: the r with cal_ptr[r] <= c < cal_ptr[r+1], by a 64-way
+// search (each round the lanes probe 64 evenly spaced row pointers).  Returns
+// -1 when c is outside [cal_ptr[0], cal_ptr[n_reads]).  Terminates for any
+// contents of cal_ptr: the interval shrinks every round.
+__device__ int64_t owner_read(const int64_t *cal_ptr, int32_t n_reads, int64_t c, int lane) {
+  if (n_reads < 1 || c < cal_ptr[0] || c >= cal_ptr[n_reads]) return -1;
+  int64_t lo = 0, hi = n_reads;
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t p = lo + (int64_t)lane * step;
+    const bool le = p < hi && cal_ptr[p] <= c;
+    const uint64_t m = __ballot(le);
+    const int k = 63 - __builtin_clzll(m | 1ull);
+    const int64_t nlo = lo + (int64_t)k * step;
+    hi = nlo + step < hi ? nlo + step : hi;
+    lo = nlo;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int plane_bit(const uint64_t *planes, int stride, int i, int j, int k) {
+  const int s = j >> 6, l = j & 63;
+  return (int)((planes[((int64_t)s * stride + i + l) * 4 + k] >> l) & 1ull);
+}
+
+}  // namespace
+
+template <bool LDS_PLANES>
+__global__ __launch_bounds__(64) void k_trace(const TraceArgs A, const RefTable T) {
+  extern __shared__ __align__(16) uint8_t tsm[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const int lane = threadIdx.x;
+  for (int i = 0; i < A.n_refs; ++i)
+    if (lane == i) {
+      rt_off[i] = T.word_off[i];
+      rt_len[i] = T.len[i];
+    }
+  __syncthreads();
+  // LDS: rows (H, E of lane 63 per row) | read codes | window words | runs | planes
+  int2 *rows = reinterpret_cast<int2 *>(tsm);
+  uint8_t *qc = tsm + 8 * A.max_read_len;
+  uint32_t *win = reinterpret_cast<uint32_t *>(qc + A.q_bytes);
+  uint32_t *runs = win + A.win_words;
+  uint64_t *planes = LDS_PLANES ? reinterpret_cast<uint64_t *>(tsm + A.planes_lds_off)
+                                : A.planes_global + (size_t)blockIdx.x * A.planes_stride;
+  const int32_t goe = A.goe, ge = A.ge;
+
+  for (int64_t t = blockIdx.x; t < A.n_slots; t += gridDim.x) {
+    const int64_t slot = A.slots[t];
+    int32_t status = 0;  // 0 ok, -2 invalid
+    if (slot == -1) {
+      if (lane == 0) {
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = 0;
+      }
+      continue;
+    }
+    int64_t r = -1;
+    int L = 0, k = 0, ie = 0, je = 0, n_cols = 0, h = 0;
+    int64_t ws = 0, p = 0;
+    int32_t sc = 0;
+    if (slot < 0 || slot >= 2 * A.n_cals) {
+      status = -2;
+    } else {
+      sc = A.score[slot];
+      if (sc > 0) {
+        const int64_t c = slot >> 1;
+        h = (int)(slot & 1);
+        r = owner_read(A.cal_ptr, A.n_reads, c, lane);
+        if (r < 0) {
+          status = -2;
+        } else {
+          L = A.read_len[r];
+          k = A.cal_ref[c];
+          p = A.cal_pos[c];
+          if (L < 1 || L > A.max_read_len || k < 0 || k >= A.n_refs || p < 0 || p >= rt_len[k]) {
+            status = -2;
+          } else {
+            ws = p - A.band < 0 ? 0 : p - A.band;
+            const int64_t we = min(rt_len[k], p + L + A.band);
+            const int W = (int)(we - ws);
+            ie = A.read_end[slot];
+            const int64_t je64 = A.ref_end[slot] - ws;
+            if (ie < 0 || ie >= L || je64 < 0 || je64 >= W) status = -2;
+            je = (int)je64;
+            n_cols = je + 1;
+          }
+        }
+      }
+    }
+    if (status != 0 || sc <= 0) {
+      if (lane == 0) {
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = status;
+        if (status) atomicAdd(A.err, 1ull);
+      }
+      continue;
+    }
+    const int n_rows = ie + 1;
+    __syncthreads();
+    // stage the oriented read rows and the window columns of the rectangle
+    {
+      const uint32_t *rp = A.reads + A.read_word_off[r];
+      for (int i = lane; i < n_rows; i += 64) {
+        const int src = h == 0 ? i : L - 1 - i;
+        const uint32_t b = (rp[src >> 4] >> (2 * (src & 15))) & 3u;
+        qc[i] = (uint8_t)(h == 0 ? b : 3u - b);
+      }
+      const int64_t first = rt_off[k] + (ws >> 4);
+      const int64_t last = rt_off[k] + ((rt_len[k] - 1) >> 4);
+      const uint32_t sh = 2u * (uint32_t)(ws & 15);
+      const int nww = (n_cols + 15) >> 4;
+      for (int q = lane; q < nww; q += 64) {
+        const uint32_t lo = A.ref_words[first + q];
+        const uint32_t hi = (first + q + 1 <= last) ? A.ref_words[first + q + 1] : 0u;
+        win[q] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+      }
+    }
+    __syncthreads();
+
+    // ---- sweep
+    const int stride = n_rows + 63;  // steps per strip in the plane buffer
+    const int nstrips = (n_cols + 63) >> 6;
+    int32_t endv = 0;
+    for (int s = 0; s < nstrips; ++s) {
+      const int col = 64 * s + lane;
+      const int32_t w = col < n_cols ? (int32_t)((win[col >> 4] >> (2 * (col & 15))) & 3u) : 5;
+      const int width = min(64, n_cols - 64 * s);
+      const int nsteps = n_rows + width - 1;
+      int32_t H = 0;          // lane's H of its last row (row -1: 0)
+      int32_t Hd1 = 0;        // H(i-1, col-1) for the coming step
+      int32_t F = -goe;       // F(0, col)
+      int32_t Eout = 0, q = 0;
+      for (int st = 0; st < nsteps; ++st) {
+        int32_t q_b = 4, e_b = -goe, h_b = 0;
+        if (st < n_rows) {
+          q_b = qc[st];
+          if (s > 0) {
+            const int2 rb = rows[st];
+            h_b = rb.x;
+            e_b = rb.y;
+          }
+        }
+        q = shr1(q_b, q);
+        const int32_t Ein = shr1(e_b, Eout);
+        const int32_t Hs = shr1(h_b, H);
+        const int i = st - lane;
+        const bool act = i >= 0 && i < n_rows && col < n_cols;
+        bool b0 = false, b1 = false, eo = false, fo = false;
+        if (act) {
+          const int32_t diag = Hd1 + (q == w ? A.match : A.mismatch);
+          const int32_t Hn = max(max(diag, Ein), max(F, 0));
+          const bool z = Hn == 0;
+          const bool d = !z && Hn == diag;
+          const bool fsrc = Hn == F;
+          b0 = z || (!d && fsrc);
+          b1 = z || (!d && !fsrc);
+          const int32_t U = Hn - goe;
+          eo = U >= Ein - ge;
+          fo = U >= F - ge;
+          Eout = max(Ein - ge, U);
+          F = max(F - ge, U);
+          H = Hn;
+          if (lane == 63) rows[i] = make_int2(Hn, Eout);
+          if (i == ie && col == je) endv = Hn;
+        }
+        Hd1 = Hs;
+        const uint64_t P0 = __ballot(b0), P1 = __ballot(b1), P2 = __ballot(eo), P3 = __ballot(fo);
+        if (lane == 0) {
+          ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(planes + ((int64_t)s * stride + st) * 4);
+          dst[0] = make_ulonglong2(P0, P1);
+          dst[1] = make_ulonglong2(P2, P3);
+        }
+      }
+      __syncthreads();
+    }
+    endv = __shfl(endv, je & 63, 64);
+    if (endv != sc) {
+      if (lane == 0) {
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = -2;
+        atomicAdd(A.err, 1ull);
+      }
+      continue;
+    }
+
+    // ---- walk (wave uniform), runs collected end first
+    int n = 0;
+    uint32_t cur_op = 0, cur_len = 0;
+    auto emit = [&](uint32_t op) {
+      if (op == cur_op) {
+        ++cur_len;
+      } else {
+        if (cur_len) {
+          if (lane == 0 && n < A.run_cap) runs[n] = (cur_len << 4) | cur_op;
+          ++n;
+        }
+        cur_op = op;
+        cur_len = 1;
+      }
+    };
+    if (L - 1 - ie > 0) {
+      cur_op = 4;
+      cur_len = (uint32_t)(L - 1 - ie);
+    }
+    int i = ie, j = je, state = 0;  // 0 H, 1 F, 2 E
+    for (;;) {
+      if (state == 0) {
+        if (i < 0 || j < 0) break;
+        const int code = plane_bit(planes, stride, i, j, 0) | (plane_bit(planes, stride, i, j, 1) << 1);
+        if (code == 3) break;
+        if (code == 0) {
+          const uint32_t wb = (win[j >> 4] >> (2 * (j & 15))) & 3u;
+          emit(qc[i] == wb ? 7u : 8u);
+          --i;
+          --j;
+        } else {
+          state = code;
+        }
+      } else if (state == 1) {
+        // F(i,j) opened from H(i-1,j)?  (row 0 cannot be in a gap: F(0,j) < 0)
+        emit(1u);
+        if (i == 0 || plane_bit(planes, stride, i - 1, j, 3)) state = 0;
+        --i;
+      } else {
+        // E(i,j) opened from H(i,j-1)?  (column 0 likewise)
+        emit(2u);
+        if (j == 0 || plane_bit(planes, stride, i, j - 1, 2)) state = 0;
+        --j;
+      }
+    }
+    // (i, j) is the cell before the first aligned pair
+    const int read_start = i + 1;
+    if (read_start > 0) {  // the head clip covers every unaligned read base
+      emit(4u);
+      cur_len = (uint32_t)read_start;
+    }
+    if (lane == 0 && n < A.run_cap) runs[n] = (cur_len << 4) | cur_op;
+    ++n;
+    __syncthreads();
+    if (n > A.cap) {
+      if (lane == 0) {
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = -1;
+      }
+    } else {
+      uint32_t *out = A.cigar + t * (int64_t)A.cap;
+      for (int x = lane; x < n; x += 64) out[x] = runs[n - 1 - x];
+      if (lane == 0) {
+        A.ref_start[t] = ws + j + 1;
+        A.read_start[t] = (int16_t)read_start;
+        A.n_ops[t] = n;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+TracePlan trace_plan(int max_read_len, int wcap) {
+  TracePlan P{};
+  P.q_bytes = (max_read_len + 15) / 16 * 16;
+  P.win_words = wcap / 16 + 2;
+  P.run_cap = max_read_len + wcap + 2;
+  const size_t head = 8 * (size_t)max_read_len + P.q_bytes + 4 * (size_t)(P.win_words + P.run_cap);
+  P.planes_lds_off = (head + 31) / 32 * 32;
+  const int nstrips = (wcap + 63) / 64;
+  P.planes_bytes = (size_t)nstrips * (size_t)(max_read_len + 63) * 32;
+  P.lds_planes = P.planes_lds_off + P.planes_bytes <= kTraceLdsLimit;
+  P.lds = P.lds_planes ? P.planes_lds_off + P.planes_bytes : P.planes_lds_off;
+  return P;
+}
+
+int trace_blocks_per_cu(const TracePlan &P) {
+  int n = 0;
+  const void *f = P.lds_planes ? reinterpret_cast<const void *>(&k_trace<true>)
+                               : reinterpret_cast<const void *>(&k_trace<false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, P.lds) != hipSuccess) return 1;
+  return n < 1 ? 1 : n;
+}
+
+hipError_t launch_trace(const TraceArgs &A, const RefTable &T, const TracePlan &P, int grid, hipStream_t st) {
+  if (A.n_slots == 0) return hipSuccess;
+  if (P.lds_planes)
+    hipLaunchKernelGGL(k_trace<true>, dim3(grid), dim3(64), P.lds, st, A, T);
+  else
+    hipLaunchKernelGGL(k_trace<false>, dim3(grid), dim3(64), P.lds, st, A, T);
+  return hipGetLastError();
+}
+
+}  // namespace swk

@@ -27,7 +27,7 @@ def sw():
 def test_header_declares_entry_points():
     names = _declared_functions()
     for n in ("sw_align_batch", "sw_workspace_bytes", "sw_reduce_best", "sw_classify", "sw_pack_2bit",
-              "sw_topk", "sw_tied_flags",
+              "sw_topk", "sw_tied_flags", "sw_traceback", "sw_traceback_workspace_bytes",
               "sw_ctx_create", "sw_align_batch_ctx", "sw_strerror"):
         assert n in names
 
@@ -119,3 +119,24 @@ def test_topk_and_tied_validation(sw):
     assert L.sw_tied_flags(p, -1, p, p, None) == -1
     assert L.sw_tied_flags(p, 1, None, p, None) == -1
     assert L.sw_tied_flags(p, 0, p, p, None) == 0
+
+
+def test_cigar_text(sw):
+    ops = [(3 << 4) | 4, (10 << 4) | 7, (1 << 4) | 8, (5 << 4) | 7, (2 << 4) | 2, (4 << 4) | 7]
+    assert sw.cigar_text(ops, len(ops)) == "3S10=1X5=2D4="
+    assert sw.cigar_text(ops, len(ops), extended=False) == "3S16M2D4M"
+
+
+def test_traceback_validation(sw):
+    L = sw.lib()
+    p = ctypes.c_void_p(16)
+    sc = sw.Scoring.make(max_read_len=100)
+    refs, keep = _refset(sw)
+    args = lambda n_slots, cap, scp: (p, p, p, 1, ctypes.byref(refs), p, p, p, 1, scp, p, p, p, p, n_slots, cap,
+                                      p, p, p, p, None, 0, None)
+    assert L.sw_traceback(*args(1, 0, ctypes.byref(sc))) == -1
+    assert L.sw_traceback(*args(-1, 4, ctypes.byref(sc))) == -1
+    assert L.sw_traceback(*args(1, 4, None)) == -1
+    assert L.sw_traceback(*args(0, 4, ctypes.byref(sc))) == 0
+    bad = sw.Scoring.make(max_read_len=100, match=0)
+    assert L.sw_traceback(*args(1, 4, ctypes.byref(bad))) == -2
