@@ -133,6 +133,25 @@ def traceback(batch, score, ref_end, read_end, slots, cap=64, max_read_len: int 
     return rs, qs, nops, cig[:n * cap].reshape(n, cap)
 
 
+def cal_filter(cal_ptr, cal_pos, cal_ref, strand, n_reads, bucket_bits=0):
+    """Duplicate-CAL filter (oracle_cal_filter).  Returns (out_ptr, out_pos, out_ref, out_strand, cal_map)."""
+    cal_ptr = np.ascontiguousarray(cal_ptr, np.int64)
+    cal_pos = np.ascontiguousarray(cal_pos, np.int64)
+    cal_ref = np.ascontiguousarray(cal_ref, np.int16)
+    strand = np.ascontiguousarray(strand, np.uint8)
+    n = len(cal_pos)
+    op = np.zeros(n_reads + 1, np.int64)
+    opos = np.zeros(max(n, 1), np.int64)
+    oref = np.zeros(max(n, 1), np.int16)
+    ost = np.zeros(max(n, 1), np.uint8)
+    cmap = np.zeros(max(n, 1), np.int64)
+    f = lib().oracle_cal_filter
+    f.restype = ctypes.c_int64
+    m = f(_p(cal_ptr), _p(cal_pos), _p(cal_ref), _p(strand), ctypes.c_int32(n_reads), ctypes.c_int32(bucket_bits),
+          _p(op), _p(opos), _p(oref), _p(ost), _p(cmap))
+    return op, opos[:m], oref[:m], ost[:m], cmap[:n]
+
+
 def reduce_best(cal_ptr, cal_ref, n_reads, n_refs, score):
     cal_ptr = np.ascontiguousarray(cal_ptr, np.int64)
     cal_ref = np.ascontiguousarray(cal_ref, np.int16)

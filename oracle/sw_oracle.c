@@ -533,3 +533,38 @@ void oracle_traceback(const uint8_t *read_codes, const int64_t *read_off, const 
     free(q);
   }
 }
+
+/*
+ * CAL Filter (section 3.3): duplicate CALs of a read are combined into one
+ * reference lookup.  Two CALs of the same read are duplicates when they name
+ * the same reference and their positions fall in the same bucket of
+ * 2^bucket_bits bases (bucket_bits = 0: identical positions).  Each read keeps
+ * the first CAL of every bucket, in input order, with the union of the strand
+ * masks of its duplicates; cal_map[c] is the output CAL that input CAL c was
+ * folded into.  Outputs: out_ptr [n_reads+1], out_pos/out_ref/out_strand
+ * [out_ptr[n_reads]], cal_map [n_cals].  Returns the number of output CALs.
+ */
+int64_t oracle_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref,
+                          const uint8_t *strand, int32_t n_reads, int32_t bucket_bits, int64_t *out_ptr,
+                          int64_t *out_pos, int16_t *out_ref, uint8_t *out_strand, int64_t *cal_map) {
+  int64_t n = 0;
+  out_ptr[0] = 0;
+  for (int64_t r = 0; r < n_reads; ++r) {
+    const int64_t first_out = n;
+    for (int64_t c = cal_ptr[r]; c < cal_ptr[r + 1]; ++c) {
+      int64_t hit = -1;
+      for (int64_t o = first_out; o < n && hit < 0; ++o)
+        if (out_ref[o] == cal_ref[c] && (out_pos[o] >> bucket_bits) == (cal_pos[c] >> bucket_bits)) hit = o;
+      if (hit < 0) {
+        hit = n++;
+        out_pos[hit] = cal_pos[c];
+        out_ref[hit] = cal_ref[c];
+        out_strand[hit] = 0;
+      }
+      out_strand[hit] |= strand[c];
+      cal_map[c] = hit;
+    }
+    out_ptr[r + 1] = n;
+  }
+  return n;
+}

@@ -595,3 +595,40 @@ def config5_request(refs, n_reads: int, seed: int, band: int = 32, ref_pack=None
         ref_pack = concat_aligned(list(refs))
     b.ref_codes, b.ref_off, b.ref_len = ref_pack[0], ref_pack[1], np.asarray(ref_pack[2], np.int64)
     return b
+
+
+def with_duplicate_cals(batch: Batch, seed: int = 0, mean_copies: float = 4.0, jitter_frac: float = 0.3,
+                        max_jitter: int = 3, split_strands: bool = True) -> Batch:
+    """The CAL stream a seed index hands to the CAL Filter (section 3.3): every
+    CAL of ``batch`` arrives several times, once per seed that hit it (1 +
+    Poisson(mean_copies - 1) copies), a fraction of the copies shifted by a few
+    bases (seeds on the far side of an indel), and with ``split_strands`` a
+    both-strand CAL may arrive as separate forward and reverse copies.  The
+    copies of a read are shuffled.  References and reads are unchanged."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([ROOT_SEED, 77, seed])))
+    n = batch.n_cals
+    copies = 1 + rng.poisson(max(mean_copies - 1.0, 0.0), n)
+    src = np.repeat(np.arange(n), copies)
+    pos = batch.cal_pos[src].copy()
+    shift = rng.random(len(src)) < jitter_frac
+    first = np.zeros(len(src), dtype=bool)
+    first[np.cumsum(copies) - copies] = True
+    shift &= ~first  # the first copy keeps the CAL itself
+    delta = rng.integers(1, max_jitter + 1, len(src)) * rng.choice([-1, 1], len(src))
+    ref_len = batch.ref_len[batch.cal_ref[src].astype(np.int64)]
+    pos = np.where(shift, np.clip(pos + delta, 0, ref_len - 1), pos)
+    strand = batch.strand[src].copy()
+    if split_strands:
+        both = (strand == 3) & ~first
+        pick = rng.integers(1, 4, len(src)).astype(np.uint8)
+        strand = np.where(both, pick, strand).astype(np.uint8)
+    ref = batch.cal_ref[src]
+    # shuffle within each read
+    r_of = np.repeat(np.arange(batch.n_reads), np.diff(batch.cal_ptr))[src]
+    order = np.lexsort((rng.random(len(src)), r_of))
+    counts = np.bincount(r_of, minlength=batch.n_reads).astype(np.int64)
+    ptr = np.zeros(batch.n_reads + 1, dtype=np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    return dataclasses.replace(batch, cal_ptr=ptr, cal_pos=pos[order].astype(np.int64),
+                               cal_ref=ref[order].astype(np.int16), strand=strand[order],
+                               name=batch.name + "+dupcals")

@@ -555,3 +555,82 @@ def test_traceback_skip_capacity_and_invalid():
     bad[0] += 1
     rs, qs, nops, cig = o.traceback(b, bad, ref_end, read_end, [0], cap=8)
     assert nops[0] == -2                                # reported score does not match the end cell
+
+
+# ------------------------------------------------------------------ CAL filter (section 3.3)
+#
+# The filter's output is pinned by the properties that define it (checked on
+# the oracle's output, not by re-deriving it) and by scoring: with exact
+# duplicates only, scoring the kept CALs and reading each input CAL's result
+# through cal_map reproduces the unfiltered scores, end positions included.
+
+def _check_filter(b, bits):
+    op, pos, ref, st, cmap = o.cal_filter(b.cal_ptr, b.cal_pos, b.cal_ref, b.strand, b.n_reads, bits)
+    assert op[0] == 0 and np.all(np.diff(op) >= 0) and op[-1] == len(pos)
+    for r in range(b.n_reads):
+        ins = range(b.cal_ptr[r], b.cal_ptr[r + 1])
+        outs = range(op[r], op[r + 1])
+        keys = [(int(ref[x]), int(pos[x]) >> bits) for x in outs]
+        assert len(set(keys)) == len(keys), "kept CALs of a read are pairwise distinct"
+        seen = []
+        for c in ins:
+            x = int(cmap[c])
+            assert x in outs, "input CAL maps into its own read's run"
+            assert (int(ref[x]), int(pos[x]) >> bits) == (int(b.cal_ref[c]), int(b.cal_pos[c]) >> bits)
+            if x not in seen:
+                assert pos[x] == b.cal_pos[c], "a kept CAL is the first CAL of its bucket"
+                seen.append(x)
+        assert seen == list(outs), "kept CALs follow the order of first occurrence"
+        for x in outs:
+            m = 0
+            for c in ins:
+                if cmap[c] == x:
+                    m |= int(b.strand[c])
+            assert st[x] == m, "strand mask is the union of the folded CALs' masks"
+    return op, pos, ref, st, cmap
+
+
+@pytest.mark.parametrize("bits", [0, 2, 5])
+def test_cal_filter_definition(bits):
+    b = wl.with_duplicate_cals(wl.random_small_batch(90, n_reads=120, max_cals=6, band=8), 2)
+    op, pos, ref, st, cmap = _check_filter(b, bits)
+    assert len(pos) < b.n_cals
+    # idempotent: filtering the kept CALs again keeps all of them
+    op2, pos2, ref2, st2, cmap2 = o.cal_filter(op, pos, ref, st, b.n_reads, bits)
+    np.testing.assert_array_equal(op2, op)
+    np.testing.assert_array_equal(pos2, pos)
+    np.testing.assert_array_equal(st2, st)
+    np.testing.assert_array_equal(cmap2, np.arange(len(pos)))
+
+
+def test_cal_filter_without_duplicates_is_identity():
+    rng = np.random.default_rng(91)
+    refs = [wl.uniform_genome(rng, 3000), wl.uniform_genome(rng, 2000)]
+    reads = [wl.uniform_genome(rng, int(rng.integers(1, 60))) for _ in range(80)]
+    # CAL k of read r at (r + 101 k) on reference k % 2: distinct within every read
+    cals = [[((r + 101 * k) % 2000, k % 2, 1 + k % 3) for k in range(r % 6)] for r in range(80)]
+    b = wl._pack_batch(refs, reads, cals, wl.Scoring(band=8), None, None, None, "distinct")
+    op, pos, ref, st, cmap = _check_filter(b, 0)
+    np.testing.assert_array_equal(op, b.cal_ptr)
+    np.testing.assert_array_equal(pos, b.cal_pos)
+    np.testing.assert_array_equal(st, b.strand)
+    np.testing.assert_array_equal(cmap, np.arange(b.n_cals))
+
+
+def test_cal_filter_exact_duplicates_preserve_scores():
+    import dataclasses
+    base = wl.random_small_batch(92, n_reads=100, max_cals=5, band=6)
+    b = wl.with_duplicate_cals(base, 3, jitter_frac=0.0)
+    op, pos, ref, st, cmap = _check_filter(b, 0)
+    kept = dataclasses.replace(b, cal_ptr=op, cal_pos=pos, cal_ref=ref, strand=st)
+    s0, r0, e0, _ = o.align_batch(b)
+    s1, r1, e1, _ = o.align_batch(kept)
+    for c in range(b.n_cals):
+        for h in (0, 1):
+            if b.strand[c] & (1 << h):
+                k = 2 * int(cmap[c]) + h
+                assert (s1[k], r1[k], e1[k]) == (s0[2 * c + h], r0[2 * c + h], e0[2 * c + h])
+    # the reduced per-read best is unchanged as well
+    bs0 = o.reduce_best(b.cal_ptr, b.cal_ref, b.n_reads, b.n_refs, s0)[0]
+    bs1 = o.reduce_best(op, ref, b.n_reads, b.n_refs, s1)[0]
+    np.testing.assert_array_equal(bs0, bs1)
