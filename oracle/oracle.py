@@ -152,6 +152,31 @@ def cal_filter(cal_ptr, cal_pos, cal_ref, strand, n_reads, bucket_bits=0):
     return op, opos[:m], oref[:m], ost[:m], cmap[:n]
 
 
+def find_cals(batch, seed_len=22, stride=1, max_cals_per_seed=0):
+    """Seeds of every read looked up in the reference (oracle_find_cals).  Returns
+    (cal_ptr, cal_pos, cal_ref, strand) for the reads of `batch`."""
+    arrs = [np.ascontiguousarray(batch.ref_codes, np.uint8), np.ascontiguousarray(batch.ref_off, np.int64),
+            np.ascontiguousarray(batch.ref_len, np.int64), np.ascontiguousarray(batch.read_codes, np.uint8),
+            np.ascontiguousarray(batch.read_off, np.int64), np.ascontiguousarray(batch.read_len, np.int32)]
+    ptr = np.zeros(batch.n_reads + 1, np.int64)
+    f = lib().oracle_find_cals
+    f.restype = ctypes.c_int64
+    args = lambda cap, pos, ref, st: (_p(arrs[0]), _p(arrs[1]), _p(arrs[2]), ctypes.c_int32(batch.n_refs),
+                                      _p(arrs[3]), _p(arrs[4]), _p(arrs[5]), ctypes.c_int32(batch.n_reads),
+                                      ctypes.c_int32(seed_len), ctypes.c_int32(stride),
+                                      ctypes.c_int32(max_cals_per_seed), _p(ptr), _p(pos), _p(ref), _p(st),
+                                      ctypes.c_int64(cap))
+    cap = 4 * max(batch.n_reads, 1)
+    while True:
+        pos = np.zeros(cap, np.int64)
+        ref = np.zeros(cap, np.int16)
+        st = np.zeros(cap, np.uint8)
+        n = f(*args(cap, pos, ref, st))
+        if n <= cap:
+            return ptr, pos[:n], ref[:n], st[:n]
+        cap = int(n)
+
+
 def reduce_best(cal_ptr, cal_ref, n_reads, n_refs, score):
     cal_ptr = np.ascontiguousarray(cal_ptr, np.int64)
     cal_ref = np.ascontiguousarray(cal_ref, np.int16)

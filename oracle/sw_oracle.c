@@ -568,3 +568,124 @@ int64_t oracle_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const 
   }
   return n;
 }
+
+/*
+ * Seeding and CAL finding (sections 3.1 and 3.2).
+ *
+ * A seed is a string of seed_len consecutive bases (seed_len <= 32).  The
+ * reference is cut into every overlapping seed; a read is cut into seeds
+ * starting at offsets 0, stride, 2*stride, ... that fit in the read (stride 1:
+ * overlapping seeds, stride = seed_len: non-overlapping ones).  A read seed s
+ * matches reference position x of reference k in the forward orientation when
+ * the reference seed there equals s, and in the reverse orientation when it
+ * equals the reverse complement of s (the index keeps one canonical form per
+ * seed and a strand bit, section 3.1; matching both orientations is what that
+ * construction achieves).  A palindromic seed matches both ways.
+ *
+ * A read seed with more than max_cals_per_seed matches (0: no limit)
+ * contributes nothing (the per-seed CAL limit of the index).  Otherwise each
+ * match becomes one CAL:
+ *   forward: strand 1, position x - o (where read base 0 falls);
+ *   reverse: strand 2, position x - (L - o - seed_len) (where base 0 of the
+ *            read's reverse complement falls);
+ * clipped to [0, length of reference k).  A read's CALs are listed seed by
+ * seed, each seed's matches by (reference, position), the forward match of a
+ * palindrome before the reverse one.
+ *
+ * The reference seeds are found through a sorted array of (seed, reference,
+ * position) triples and binary search, the plainest exact lookup; the hashed
+ * pointer and CAL tables of the paper are a storage layout with the same
+ * answers.  Returns the total number of CALs; only `capacity` are written.
+ */
+typedef struct {
+  uint64_t seed;
+  int32_t ref;
+  int64_t pos;
+} oracle_occ_t;
+
+static uint64_t seed_at(const uint8_t *s, int S) {
+  uint64_t v = 0;
+  for (int i = 0; i < S; ++i) v = (v << 2) | (uint64_t)(s[i] & 3);
+  return v;
+}
+
+static uint64_t seed_revcomp(uint64_t v, int S) {
+  uint64_t r = 0;
+  for (int i = 0; i < S; ++i) {
+    r = (r << 2) | (3 - (v & 3));
+    v >>= 2;
+  }
+  return r;
+}
+
+static int occ_cmp(const void *a, const void *b) {
+  const oracle_occ_t *x = (const oracle_occ_t *)a, *y = (const oracle_occ_t *)b;
+  if (x->seed != y->seed) return x->seed < y->seed ? -1 : 1;
+  if (x->ref != y->ref) return x->ref < y->ref ? -1 : 1;
+  if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+  return 0;
+}
+
+/* first index whose seed is >= v */
+static int64_t occ_lower(const oracle_occ_t *o, int64_t n, uint64_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (o[mid].seed < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+int64_t oracle_find_cals(const uint8_t *ref_codes, const int64_t *ref_off, const int64_t *ref_len, int32_t n_refs,
+                         const uint8_t *read_codes, const int64_t *read_off, const int32_t *read_len, int32_t n_reads,
+                         int32_t seed_len, int32_t stride, int32_t max_cals_per_seed, int64_t *cal_ptr,
+                         int64_t *cal_pos, int16_t *cal_ref, uint8_t *strand, int64_t capacity) {
+  const int S = seed_len;
+  int64_t n_occ = 0;
+  for (int k = 0; k < n_refs; ++k)
+    if (ref_len[k] >= S) n_occ += ref_len[k] - S + 1;
+  oracle_occ_t *occ = (oracle_occ_t *)malloc((size_t)(n_occ > 0 ? n_occ : 1) * sizeof(oracle_occ_t));
+  int64_t m = 0;
+  for (int k = 0; k < n_refs; ++k)
+    for (int64_t x = 0; x + S <= ref_len[k]; ++x) {
+      occ[m].seed = seed_at(ref_codes + ref_off[k] + x, S);
+      occ[m].ref = k;
+      occ[m].pos = x;
+      ++m;
+    }
+  qsort(occ, (size_t)n_occ, sizeof(oracle_occ_t), occ_cmp);
+  int64_t n = 0;
+  cal_ptr[0] = 0;
+  for (int64_t r = 0; r < n_reads; ++r) {
+    const int64_t L = read_len[r];
+    for (int64_t o = 0; o + S <= L; o += stride) {
+      const uint64_t s = seed_at(read_codes + read_off[r] + o, S);
+      const uint64_t rs = seed_revcomp(s, S);
+      const int64_t f0 = occ_lower(occ, n_occ, s), f1 = occ_lower(occ, n_occ, s + 1);
+      const int64_t r0 = occ_lower(occ, n_occ, rs), r1 = occ_lower(occ, n_occ, rs + 1);
+      const int64_t total = (f1 - f0) + (r1 - r0); /* a palindrome counts twice */
+      if (total == 0 || (max_cals_per_seed > 0 && total > max_cals_per_seed)) continue;
+      int64_t i = f0, j = r0;
+      while (i < f1 || j < r1) {
+        /* next match in (reference, position) order; the forward one first on a tie */
+        int take_fwd;
+        if (i >= f1) take_fwd = 0;
+        else if (j >= r1) take_fwd = 1;
+        else take_fwd = (occ[i].ref < occ[j].ref || (occ[i].ref == occ[j].ref && occ[i].pos <= occ[j].pos));
+        const oracle_occ_t *h = take_fwd ? &occ[i++] : &occ[j++];
+        int64_t p = take_fwd ? h->pos - o : h->pos - (L - o - S);
+        if (p < 0) p = 0;
+        if (p >= ref_len[h->ref]) p = ref_len[h->ref] - 1;
+        if (n < capacity) {
+          cal_pos[n] = p;
+          cal_ref[n] = (int16_t)h->ref;
+          strand[n] = take_fwd ? 1 : 2;
+        }
+        ++n;
+      }
+    }
+    cal_ptr[r + 1] = n;
+  }
+  free(occ);
+  return n;
+}

@@ -634,3 +634,107 @@ def test_cal_filter_exact_duplicates_preserve_scores():
     bs0 = o.reduce_best(b.cal_ptr, b.cal_ref, b.n_reads, b.n_refs, s0)[0]
     bs1 = o.reduce_best(op, ref, b.n_reads, b.n_refs, s1)[0]
     np.testing.assert_array_equal(bs0, bs1)
+
+
+# ------------------------------------------------------------------ seeding / CAL finder (sections 3.1, 3.2)
+
+def _brute_cals(b, S, stride, limit):
+    """Direct string comparison of every read seed with every reference seed."""
+    out = []
+    for r in range(b.n_reads):
+        q = b.read(r)
+        L = len(q)
+        cals = []
+        for o_ in range(0, L - S + 1, stride):
+            s = q[o_:o_ + S]
+            rc = (3 - s[::-1]).astype(np.uint8)
+            hits = []
+            for k in range(b.n_refs):
+                ref = b.ref_codes[b.ref_off[k]:b.ref_off[k] + b.ref_len[k]]
+                for x in range(len(ref) - S + 1):
+                    t = ref[x:x + S]
+                    n_ = len(ref)
+                    if np.array_equal(t, s):
+                        hits.append((k, int(np.clip(x - o_, 0, n_ - 1)), 1))
+                    if np.array_equal(t, rc):
+                        hits.append((k, int(np.clip(x - (L - o_ - S), 0, n_ - 1)), 2))
+            if hits and (limit == 0 or len(hits) <= limit):
+                cals.extend(hits)
+        out.append(cals)
+    return out
+
+
+def _as_lists(ptr, pos, ref, st, n_reads):
+    return [[(int(ref[c]), int(pos[c]), int(st[c])) for c in range(ptr[r], ptr[r + 1])] for r in range(n_reads)]
+
+
+@pytest.mark.parametrize("S,stride,limit", [(3, 1, 0), (4, 1, 3), (4, 2, 0), (5, 5, 0), (6, 1, 2)])
+def test_find_cals_brute_force(S, stride, limit):
+    rng = np.random.default_rng(100 + S)
+    refs = [wl.uniform_genome(rng, 120), wl.uniform_genome(rng, 70)]
+    refs[0][40:46] = [0, 1, 2, 1, 2, 3]               # contains palindromes: ACG CGT, GCGC ...
+    refs[1][10:14] = [0, 3, 0, 3]                     # ATAT (its own reverse complement)
+    reads = []
+    for i in range(25):
+        if i % 3 == 0:
+            k = int(rng.integers(0, 2))
+            p = int(rng.integers(0, len(refs[k]) - 20))
+            rd = refs[k][p:p + int(rng.integers(S, 20))].copy()
+            reads.append(rd if i % 2 else (3 - rd[::-1]).astype(np.uint8))
+        else:
+            reads.append(wl.uniform_genome(rng, int(rng.integers(1, 20))))
+    reads += [refs[0][38:50].copy(), refs[1][8:16].copy()]   # reads holding the palindromes
+    b = wl._pack_batch(refs, reads, [[] for _ in reads], wl.Scoring(), None, None, None, "seeds")
+    ptr, pos, ref, st = o.find_cals(b, seed_len=S, stride=stride, max_cals_per_seed=limit)
+    want = _brute_cals(b, S, stride, limit)
+    assert _as_lists(ptr, pos, ref, st, b.n_reads) == want
+    if S in (4, 6) and stride == 1 and limit == 0:
+        # a palindromic seed gives a forward and a reverse CAL at the same reference seed
+        assert any(a[0] == c[0] and a[2] == 1 and c[2] == 2 for cl in want for a, c in zip(cl, cl[1:]))
+
+
+def test_find_cals_planted_reads_recover_locus():
+    """Error-free 100-bp reads from a random 200 kbp genome: every 22-base seed
+    is unique, so each of the 79 overlapping seeds (or 4 non-overlapping ones)
+    reports the read's own locus and strand."""
+    rng = np.random.default_rng(101)
+    g = wl.uniform_genome(rng, 200_000)
+    pos0 = rng.integers(0, len(g) - 100, 40)
+    reads = [g[p:p + 100].copy() if i % 2 == 0 else (3 - g[p:p + 100][::-1]).astype(np.uint8)
+             for i, p in enumerate(pos0)]
+    b = wl._pack_batch([g], reads, [[] for _ in reads], wl.Scoring(), None, None, None, "planted")
+    for stride, per_read in ((1, 79), (22, 4)):
+        ptr, pos, ref, st = o.find_cals(b, seed_len=22, stride=stride)
+        assert np.all(np.diff(ptr) == per_read)
+        for i, p in enumerate(pos0):
+            sl = slice(ptr[i], ptr[i + 1])
+            assert np.all(pos[sl] == p) and np.all(ref[sl] == 0)
+            assert np.all(st[sl] == (1 if i % 2 == 0 else 2))
+
+
+def test_find_cals_fig3_seeds():
+    """Fig. 3: the first three overlapping 22-base seeds of the printed reference
+    are the printed Seed0..Seed2; looked up as reads they land at 0, 1 and 2."""
+    ref_s, *seeds = _golden_lines("fig3_reference.txt")
+    ref = o.encode(ref_s)
+    for x, s in enumerate(seeds):
+        assert ref_s[x:x + 22] == s
+    reads = [o.encode(s) for s in seeds]
+    b = wl._pack_batch([ref], reads, [[] for _ in reads], wl.Scoring(), None, None, None, "fig3")
+    ptr, pos, ref_, st = o.find_cals(b, seed_len=22)
+    assert _as_lists(ptr, pos, ref_, st, 3) == [[(0, 0, 1)], [(0, 1, 1)], [(0, 2, 1)]]
+
+
+def test_find_cals_per_seed_limit():
+    rng = np.random.default_rng(102)
+    g = wl.uniform_genome(rng, 20_000)
+    unit = g[1000:1060].copy()
+    for k in range(1, 5):                              # 5 copies of a 60-base unit
+        g[1000 + 3000 * k:1060 + 3000 * k] = unit
+    read = g[1010:1050].copy()                         # lies inside the unit: every seed hits 5 times
+    b = wl._pack_batch([g], [read], [[]], wl.Scoring(), None, None, None, "repeat")
+    ptr, pos, ref, st = o.find_cals(b, seed_len=16, stride=1, max_cals_per_seed=4)
+    assert ptr[-1] == 0
+    ptr, pos, ref, st = o.find_cals(b, seed_len=16, stride=1, max_cals_per_seed=5)
+    assert ptr[-1] == 25 * 5
+    assert sorted(set(pos.tolist())) == [1010 + 3000 * k for k in range(5)]
