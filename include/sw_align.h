@@ -188,6 +188,86 @@ int sw_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32
 int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
                   sw_stream_t stream);
 
+/* ------------------------------------------------------------------ seeding */
+/*
+ * Seed index (section 3.1) and CAL finder (section 3.2).
+ *
+ * The index holds every overlapping seed of seed_len bases of every
+ * reference, each reduced to its canonical form (the smaller of the seed and
+ * its reverse complement, with a bit saying which one the reference holds)
+ * and hashed so that the pointer table's buckets fill evenly; the CAL table
+ * lists the seeds' positions sorted by hash, and the pointer table (2^addr_bits
+ * entries) points at the first CAL-table entry of each address.  It lives in
+ * device memory (16 bytes per reference position, plus 8 per address) and
+ * keeps a pointer to the reference set's words only during the build.
+ *
+ * sw_find_cals cuts each read into seeds starting at offsets 0, stride,
+ * 2*stride, ... (stride 1: overlapping seeds; stride = seed_len: non-overlapping)
+ * and looks each one up.  A read seed matches reference position x forward
+ * when the reference seed there equals it (CAL strand 1 at x - offset), and
+ * reverse when the reference holds its reverse complement (strand 2 at
+ * x - (L - offset - seed_len), where base 0 of the read's reverse complement
+ * falls); a palindromic seed matches both ways.  Positions are clipped to the
+ * reference.  A seed with more than max_cals_per_seed matches (0: no limit)
+ * contributes nothing.  CALs are listed per read, seed by seed, each seed's
+ * matches by (reference, position), forward before reverse.  The output is
+ * the CSR input of sw_cal_filter / sw_align_batch (duplicates included).
+ *   cal_ptr   device [n_reads+1]    written in every successful or
+ *                                   SW_ERR_WORKSPACE return
+ *   cal_pos, cal_ref, strand  device [capacity]
+ *   n_cals    host: number of CALs found; SW_ERR_WORKSPACE when it exceeds
+ *             capacity (nothing else written; call again with room)
+ * The call synchronises `stream` once (to read the count).  Reads longer than
+ * max_read_len get no CALs and are counted by sw_error_count() when the CALs
+ * are written (not on a SW_ERR_WORKSPACE return).  An index is not thread-safe.
+ */
+typedef struct sw_index sw_index_t;
+typedef struct {
+  int32_t device;    /* HIP device ordinal */
+  int32_t seed_len;  /* 1..32 (the paper's V1 uses 22) */
+  int32_t addr_bits; /* pointer-table address bits, 1..min(2*seed_len, 30); 0: min(2*seed_len, 24) */
+} sw_index_opts_t;
+typedef struct {
+  int32_t stride;            /* >= 1 */
+  int32_t max_cals_per_seed; /* >= 0; 0: no limit */
+  int32_t max_read_len;      /* 1..SW_MAX_READ_LEN; 0 means SW_MAX_READ_LEN */
+} sw_find_opts_t;
+int sw_index_build(const sw_refset_t *refs, const sw_index_opts_t *opts, sw_index_t **out, sw_stream_t stream);
+int sw_index_info(const sw_index_t *ix, int64_t *n_entries, int64_t *device_bytes);
+int sw_index_destroy(sw_index_t *ix);
+int sw_find_cals(sw_index_t *ix, const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
+                 int32_t n_reads, const sw_find_opts_t *opts, int64_t *cal_ptr, int64_t *cal_pos,
+                 int16_t *cal_ref, uint8_t *strand, int64_t capacity, int64_t *n_cals, sw_stream_t stream);
+
+/* ------------------------------------------------------------------ CAL filter */
+/*
+ * CAL Filter (section 3.3): the CALs of a read that point at the same part of
+ * the reference are combined into one lookup before scoring.  Two CALs of one
+ * read are duplicates when they name the same reference and their positions
+ * fall in the same bucket of 2^bucket_bits bases (0: identical positions only).
+ * Each read keeps the first CAL of every bucket, in input order, carrying the
+ * union of the strand masks of its duplicates.
+ *   cal_ptr, cal_pos, cal_ref, strand   device: the CSR CAL lists (as for scoring)
+ *   bucket_bits  0..40
+ * Outputs, device:
+ *   out_ptr    [n_reads+1]  CSR row pointer of the kept CALs; out_ptr[n_reads]
+ *                           is their number (read it back to size the scoring call)
+ *   out_pos, out_ref, out_strand  [n_cals]  kept CALs (first out_ptr[n_reads] used)
+ *   cal_map    [n_cals]     kept CAL each input CAL was folded into (-1 for a CAL
+ *                           outside every read's range)
+ * With bucket_bits = 0, for every strand h that CAL c requests, slot
+ * 2*cal_map[c]+h of a scoring call on the kept CALs holds exactly what slot
+ * 2c+h of the unfiltered call holds (same read, reference and window).
+ * cal_ptr must be non-decreasing with cal_ptr[n_reads] <= n_cals; if it is not,
+ * the outputs are unspecified, but nothing outside the arrays is accessed.
+ * `workspace` (device) must hold sw_cal_filter_workspace_bytes(n_reads) bytes.
+ */
+size_t sw_cal_filter_workspace_bytes(int32_t n_reads);
+int sw_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand,
+                  int32_t n_reads, int64_t n_cals, int32_t bucket_bits, int64_t *out_ptr, int64_t *out_pos,
+                  int16_t *out_ref, uint8_t *out_strand, int64_t *cal_map, void *workspace,
+                  size_t workspace_bytes, sw_stream_t stream);
+
 /* ------------------------------------------------------------------ traceback */
 /*
  * Start position and CIGAR of selected slots.  The paper's hardware reports

@@ -15,7 +15,7 @@ import torch  # load torch's HIP runtime before the library so both share it
 
 __all__ = [
     "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
-    "reduce_best", "topk", "tied_flags", "classify", "error_count", "traceback", "cigar_text", "SwError", "Context", "Outputs", "Server", "Request",
+    "reduce_best", "topk", "tied_flags", "classify", "error_count", "traceback", "cigar_text", "cal_filter", "SeedIndex", "SwError", "Context", "Outputs", "Server", "Request",
     "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
     "MODE_LOCAL", "MODE_FINAL_ROW", "MAX_READ_LEN", "MAX_REFS", "MAX_TOPK",
 ]
@@ -56,6 +56,14 @@ class Scoring(ctypes.Structure):
 class _RefSetC(ctypes.Structure):
     _fields_ = [("words", ctypes.c_void_p), ("word_offset", ctypes.c_void_p), ("length", ctypes.c_void_p),
                 ("n_refs", ctypes.c_int32)]
+
+
+class _IndexOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("seed_len", ctypes.c_int32), ("addr_bits", ctypes.c_int32)]
+
+
+class _FindOpts(ctypes.Structure):
+    _fields_ = [("stride", ctypes.c_int32), ("max_cals_per_seed", ctypes.c_int32), ("max_read_len", ctypes.c_int32)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -100,6 +108,14 @@ def lib():
         L.sw_traceback.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, i64,
                                    ctypes.POINTER(Scoring), vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp,
                                    ctypes.c_size_t, vp]
+        L.sw_index_build.argtypes = [ctypes.POINTER(_RefSetC), ctypes.POINTER(_IndexOpts), ctypes.POINTER(vp), vp]
+        L.sw_index_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.sw_index_destroy.argtypes = [vp]
+        L.sw_find_cals.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(_FindOpts), vp, vp, vp, vp, i64,
+                                   ctypes.POINTER(i64), vp]
+        L.sw_cal_filter.argtypes = [vp, vp, vp, vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.sw_cal_filter_workspace_bytes.argtypes = [i32]
+        L.sw_cal_filter_workspace_bytes.restype = ctypes.c_size_t
         L.sw_traceback_workspace_bytes.argtypes = [i64, ctypes.POINTER(Scoring)]
         L.sw_traceback_workspace_bytes.restype = ctypes.c_size_t
         L.sw_tied_flags.argtypes = [vp, i32, vp, vp, vp]
@@ -282,6 +298,83 @@ def traceback(db: DeviceBatch, refs: "RefSet", sc: Scoring, out: "Outputs", slot
                               _ptr(rs), _ptr(qs), _ptr(nops), _ptr(cig), _ptr(ws), nb, _stream(stream)),
            "sw_traceback")
     return rs, qs, nops, cig[:n * cap].view(n, cap)
+
+
+def cal_filter(db: DeviceBatch, bucket_bits: int = 0, stream=None, workspace: Optional[torch.Tensor] = None):
+    """CAL Filter on device: a DeviceBatch with each read's duplicate CALs folded
+    into one (same reads), and cal_map (input CAL -> kept CAL).  Synchronises the
+    stream once to read the number of kept CALs."""
+    dev = db.cal_pos.device
+    n = db.n_cals
+    out_ptr = torch.empty(db.n_reads + 1, dtype=torch.int64, device=dev)
+    out_pos = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    out_ref = torch.empty(max(n, 1), dtype=torch.int16, device=dev)
+    out_strand = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    cal_map = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    nb = lib().sw_cal_filter_workspace_bytes(db.n_reads)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    _check(lib().sw_cal_filter(_ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref), _ptr(db.strand), db.n_reads,
+                               n, bucket_bits, _ptr(out_ptr), _ptr(out_pos), _ptr(out_ref), _ptr(out_strand),
+                               _ptr(cal_map), _ptr(workspace), nb, _stream(stream)), "sw_cal_filter")
+    if stream is not None:
+        stream.synchronize()
+    m = int(out_ptr[-1].item())
+    kept = DeviceBatch(db.reads2bit, db.read_word_off, db.read_len, out_ptr, out_pos[:m], out_ref[:m],
+                       out_strand[:m])
+    return kept, cal_map[:n]
+
+
+class SeedIndex:
+    """Seed index of a resident reference set (sw_index_*): pointer table + CAL
+    table in device memory; find() turns reads into the CSR CAL lists that
+    cal_filter and align_batch take."""
+
+    def __init__(self, refs: "RefSet", seed_len: int = 22, addr_bits: int = 0, device: int = 0, stream=None):
+        self._h = ctypes.c_void_p()
+        self.seed_len = seed_len
+        o = _IndexOpts(device, seed_len, addr_bits)
+        _check(lib().sw_index_build(refs.c, ctypes.byref(o), ctypes.byref(self._h), _stream(stream)),
+               "sw_index_build")
+
+    def info(self):
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sw_index_info(self._h, ctypes.byref(n), ctypes.byref(b)), "sw_index_info")
+        return {"entries": n.value, "device_bytes": b.value}
+
+    def find(self, db: DeviceBatch, stride: int = 1, max_cals_per_seed: int = 0, max_read_len: int = 0,
+             capacity: Optional[int] = None, stream=None) -> DeviceBatch:
+        """CALs of the reads of `db` (its own CAL arrays are ignored)."""
+        dev = db.read_len.device
+        o = _FindOpts(stride, max_cals_per_seed, max_read_len)
+        ptr = torch.empty(db.n_reads + 1, dtype=torch.int64, device=dev)
+        cap = capacity if capacity is not None else 16 * max(db.n_reads, 1)
+        for _ in range(2):
+            pos = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+            ref = torch.empty(max(cap, 1), dtype=torch.int16, device=dev)
+            st = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+            n = ctypes.c_int64()
+            rc = lib().sw_find_cals(self._h, _ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len),
+                                    db.n_reads, ctypes.byref(o), _ptr(ptr), _ptr(pos), _ptr(ref), _ptr(st), cap,
+                                    ctypes.byref(n), _stream(stream))
+            if rc == -5 and n.value > cap:
+                cap = n.value
+                continue
+            _check(rc, "sw_find_cals")
+            m = n.value
+            return DeviceBatch(db.reads2bit, db.read_word_off, db.read_len, ptr, pos[:m], ref[:m], st[:m])
+        raise SwError(-5, "sw_find_cals")
+
+    def close(self):
+        if self._h:
+            lib().sw_index_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _OP_TEXT = {1: "I", 2: "D", 4: "S", 7: "=", 8: "X"}

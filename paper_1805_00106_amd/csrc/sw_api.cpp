@@ -10,6 +10,7 @@
 
 #include "../../include/sw_align.h"
 #include "sw_api_internal.h"
+#include "sw_filter.h"
 #include "sw_launch.h"
 
 namespace swapi {
@@ -439,6 +440,26 @@ int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const 
   A.run_cap = tl.P.run_cap;
   A.planes_lds_off = (int64_t)tl.P.planes_lds_off;
   hipError_t e = swk::launch_trace(A, T, tl.P, tl.grid, (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+size_t sw_cal_filter_workspace_bytes(int32_t n_reads) {
+  if (n_reads < 0) return 0;
+  return swk::filter_workspace_bytes(n_reads);
+}
+
+int sw_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand,
+                  int32_t n_reads, int64_t n_cals, int32_t bucket_bits, int64_t *out_ptr, int64_t *out_pos,
+                  int16_t *out_ref, uint8_t *out_strand, int64_t *cal_map, void *workspace, size_t workspace_bytes,
+                  sw_stream_t stream) {
+  if (n_reads < 0 || n_cals < 0 || bucket_bits < 0 || bucket_bits > 40) return SW_ERR_INVALID_ARG;
+  if (!cal_ptr || !out_ptr) return SW_ERR_INVALID_ARG;
+  if (n_cals > 0 && (!cal_pos || !cal_ref || !strand || !out_pos || !out_ref || !out_strand || !cal_map))
+    return SW_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < swk::filter_workspace_bytes(n_reads)) return SW_ERR_WORKSPACE;
+  swk::FilterArgs A{cal_ptr, cal_pos, cal_ref, strand, n_reads, n_cals, bucket_bits,
+                    out_ptr, out_pos, out_ref, out_strand, cal_map};
+  hipError_t e = swk::launch_filter(A, workspace, workspace_bytes, (hipStream_t)stream);
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 

@@ -632,3 +632,35 @@ def with_duplicate_cals(batch: Batch, seed: int = 0, mean_copies: float = 4.0, j
     return dataclasses.replace(batch, cal_ptr=ptr, cal_pos=pos[order].astype(np.int64),
                                cal_ref=ref[order].astype(np.int16), strand=strand[order],
                                name=batch.name + "+dupcals")
+
+
+def seeding_batch(n_reads: int = 2000, ref_len: int = 2_000_000, read_len=(100, 100), n_refs: int = 1,
+                  seed: int = 0, sub_rate: float = 0.01, indel_rate: float = 0.001) -> Batch:
+    """Reads for the seeding path (no CALs: the seed index finds them).  Each
+    reference is random with 5% planted repeats (the chromosome-scale recipe);
+    reads are sampled uniformly over the references with the sequencer error
+    model, half from the reverse strand; the true locus is kept."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([ROOT_SEED, 55, seed])))
+    refs = []
+    for k in range(n_refs):
+        n = int(ref_len) - 37 * k  # lengths that are not multiples of 16
+        g = uniform_genome(rng, n)
+        plant_repeats(rng, g, 0.05)
+        refs.append(g)
+    lens = rng.integers(read_len[0], read_len[1] + 1, n_reads)
+    which = rng.integers(0, n_refs, n_reads)
+    reads = [None] * n_reads
+    true_pos = np.zeros(n_reads, np.int64)
+    true_rev = np.zeros(n_reads, bool)
+    for k in range(n_refs):
+        idx = np.nonzero(which == k)[0]
+        if len(idx) == 0:
+            continue
+        rd, pos, rev = _sample_reads(rng, rng, refs[k], lens[idx], sub_rate, indel_rate)
+        for j, r in enumerate(idx):
+            reads[r] = rd[j]
+        true_pos[idx] = pos
+        true_rev[idx] = rev
+    sc = Scoring(2, -3, 5, 2, 32)
+    return _pack_batch(refs, reads, [[] for _ in range(n_reads)], sc, which.astype(np.int16), true_pos,
+                       true_rev, f"seeding{seed}")

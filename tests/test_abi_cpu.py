@@ -140,3 +140,17 @@ def test_traceback_validation(sw):
     assert L.sw_traceback(*args(0, 4, ctypes.byref(sc))) == 0
     bad = sw.Scoring.make(max_read_len=100, match=0)
     assert L.sw_traceback(*args(1, 4, ctypes.byref(bad))) == -2
+
+
+def test_cal_filter_validation(sw):
+    L = sw.lib()
+    p = ctypes.c_void_p(16)
+    call = lambda n_reads, n_cals, bits, ws, nb: L.sw_cal_filter(p, p, p, p, n_reads, n_cals, bits, p, p, p, p, p,
+                                                                 ws, nb, None)
+    assert call(-1, 1, 0, p, 1 << 30) == -1
+    assert call(1, -1, 0, p, 1 << 30) == -1
+    assert call(1, 1, -1, p, 1 << 30) == -1
+    assert call(1, 1, 41, p, 1 << 30) == -1
+    assert call(1, 1, 0, None, 0) == -5
+    assert call(10, 1, 0, p, 8) == -5
+    assert L.sw_cal_filter_workspace_bytes(1000) >= 8 * 1001
