@@ -21,6 +21,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -220,6 +221,120 @@ class Leg:
                 "batched_gcups": g(batched_ms), "plain_equals_batched": same, "aligned_fraction": aligned,
                 "plan": self.ctx.last_plan()}
 
+    def traceback(self, reps=5, cap=64, parity_reads=200):
+        """Start + CIGAR of every read's best slot (from the last scoring step's
+        outputs), timed with HIP events on the leg's stream."""
+        torch, sw, db = self.torch, self.sw, self.db
+        slots = self.bl.view(db.n_reads, self.batch.n_refs)[:, 0].contiguous()
+        n = slots.numel()
+        dev = slots.device
+        rs = torch.empty(n, dtype=torch.int64, device=dev)
+        qs = torch.empty(n, dtype=torch.int16, device=dev)
+        nops = torch.empty(n, dtype=torch.int32, device=dev)
+        cig = torch.zeros(n * cap, dtype=torch.int32, device=dev)
+        nb = sw.lib().sw_traceback_workspace_bytes(n, ctypes.byref(self.scoring))
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        st = self.stream
+        P = sw._ptr
+
+        def call():
+            rc = sw.lib().sw_traceback(P(db.reads2bit), P(db.read_word_off), P(db.read_len), db.n_reads, self.refs.c,
+                                       P(db.cal_ptr), P(db.cal_pos), P(db.cal_ref), db.n_cals,
+                                       ctypes.byref(self.scoring), P(self.out.score), P(self.out.ref_end),
+                                       P(self.out.read_end), P(slots), n, cap, P(rs), P(qs), P(nops), P(cig),
+                                       P(ws), nb, sw._stream(st))
+            assert rc == 0, rc
+
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            call()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        # cells of the rebuilt rectangles: (read_end + 1) x (ref_end - window start + 1)
+        ok = slots >= 0
+        sl = slots.clamp(min=0)
+        ws0 = (db.cal_pos[sl >> 1] - self.batch.scoring.band).clamp(min=0)
+        rect = (self.out.read_end[sl].to(torch.int64) + 1) * (self.out.ref_end[sl] - ws0 + 1)
+        cells = int(torch.where(ok & (self.out.score[sl] > 0), rect, torch.zeros_like(rect)).sum().item())
+        res = {"reads": n, "ms": round(ms, 3), "reads_per_s": round(n / (ms * 1e-3), 1),
+               "rectangle_cells": cells, "rectangle_gcups": round(cells / (ms * 1e-3) / 1e9, 1),
+               "traced_fraction": round(float((nops > 0).float().mean().item()), 4),
+               "planes": "lds" if nb == 0 else "device"}
+        if parity_reads:
+            res["parity_sample_ok"] = self._trace_parity(slots, rs, qs, nops, cig.view(n, cap), cap, parity_reads)
+        return res
+
+    def pipeline(self, seed_len=22, stride=1, limit=16, reps=3):
+        """The whole method on the device: seed index of the resident reference
+        (built once), CALs from every overlapping seed of every read, the CAL
+        filter (exact duplicates), Smith-Waterman on the kept CALs and the
+        per-read best.  Stage times are wall-clock between device
+        synchronisations (the finder and the filter each read one count back)."""
+        torch, sw, db = self.torch, self.sw, self.db
+        sync = torch.cuda.synchronize
+        sync()
+        t0 = time.perf_counter()
+        ix = sw.SeedIndex(self.refs, seed_len=seed_len)
+        sync()
+        build_s = time.perf_counter() - t0
+        times = {"find": [], "filter": [], "score": [], "reduce": []}
+        for _ in range(reps):
+            t = time.perf_counter()
+            found = ix.find(db, stride=stride, max_cals_per_seed=limit, max_read_len=int(self.batch.read_len.max()))
+            sync()
+            times["find"].append(time.perf_counter() - t)
+            t = time.perf_counter()
+            kept, cmap = sw.cal_filter(found, 0)
+            sync()
+            times["filter"].append(time.perf_counter() - t)
+            t = time.perf_counter()
+            ws = torch.empty(sw.workspace_bytes(db.n_reads, kept.n_cals, self.scoring), dtype=torch.uint8,
+                             device=db.read_len.device)
+            out = sw.align_batch(kept, self.refs, self.scoring, None, ws)
+            sync()
+            times["score"].append(time.perf_counter() - t)
+            t = time.perf_counter()
+            bs, bl, nt = sw.reduce_best(kept, self.batch.n_refs, out.score)
+            sync()
+            times["reduce"].append(time.perf_counter() - t)
+        ms = {k: round(1e3 * float(np.median(v)), 3) for k, v in times.items()}
+        total_ms = sum(ms.values())
+        # planted locus recovered: best CAL within 8 bases of the sampled position, right strand
+        b = self.batch
+        best = bl[:, 0].cpu().numpy()
+        kpos = kept.cal_pos.cpu().numpy()
+        okb = best >= 0
+        hit = okb & (np.abs(kpos[np.maximum(best, 0) // 2] - b.true_pos) <= 8) & \
+            ((best % 2 == 1) == np.asarray(b.true_strand, bool))
+        info = ix.info()
+        ix.close()
+        return {"seed_len": seed_len, "stride": stride, "max_cals_per_seed": limit,
+                "index_build_s": round(build_s, 3), "index_entries": info["entries"],
+                "index_gb": round(info["device_bytes"] / 1e9, 3),
+                "raw_cals": found.n_cals, "kept_cals": kept.n_cals,
+                "stage_ms": ms, "total_ms": round(total_ms, 3),
+                "reads_per_s": round(db.n_reads / (total_ms * 1e-3), 1),
+                "planted_locus_recovered": round(float(hit.mean()), 4)}
+
+    def _trace_parity(self, slots, rs, qs, nops, cig, cap, n, seed=11):
+        from oracle import oracle as orc
+        b = self.batch
+        rng = np.random.default_rng(seed)
+        idx = np.sort(rng.choice(b.n_reads, min(n, b.n_reads), replace=False))
+        sub = b.subset_reads(idx)
+        s, r, e, _ = orc.align_batch(sub, n_threads=min(16, os.cpu_count() or 1))
+        _, bl, _ = orc.reduce_best(sub.cal_ptr, sub.cal_ref, sub.n_reads, sub.n_refs, s)
+        ors, oqs, onops, ocig = orc.traceback(sub, s, r, e, bl[:, 0], cap=cap)
+        g = lambda t: t.cpu().numpy()[idx]
+        gcig = cig.cpu().numpy().view(np.uint32)[idx]
+        # the sub-batch renumbers slots, so compare the traced alignments themselves
+        return bool(np.array_equal(g(rs), ors) and np.array_equal(g(qs), oqs) and np.array_equal(g(nops), onops)
+                    and np.array_equal(gcig, ocig))
+
     def free(self):
         self.ctx.close()
 
@@ -375,6 +490,7 @@ def main():
     ap.add_argument("--serve-step-cals", type=int, default=1 << 19, help="CALs per device step of the server")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pipeline", type=int, default=1, help="1: also time seeds -> CALs -> filter -> score")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run an elementwise copy of this size (counter calibration for profiles)")
@@ -395,6 +511,8 @@ def main():
     leg = Leg(batch, int(batch.read_len.max()), args.steps, args.warmup)
     r2 = leg.run()
     parity = None if args.no_parity else parity_sample(batch, leg.out)
+    trace = leg.traceback(parity_reads=0 if args.no_parity else 200)
+    pipe = leg.pipeline() if args.pipeline else None
     small = small_batch_latency(batch)
     n_reads, n_cals, cells = leg.db.n_reads, leg.db.n_cals, leg.cells
     leg.free()
@@ -452,6 +570,8 @@ def main():
                   "kernel_ms": round(r2["plain_kern_ms"], 3)},
         "plain_equals_batched": r2["plain_equals_batched"],
         "small_batch_latency": small,
+        "traceback": trace,
+        "seed_to_score": pipe,
         "aligned_fraction": round(r2["aligned_fraction"], 4), "aligned_threshold": ALIGNED_THRESHOLD,
         "wall_s_timed": round(r2["wall"], 3), "gen_s": round(t_gen, 1), "parity_sample_ok": parity,
         "roofline": roof,

@@ -278,10 +278,26 @@ __device__ __forceinline__ void fold16(const v2s (&M)[R], int r0, int tb, uint64
   }
 }
 
+// Final-row mode: fold the maximum of one row (both halves on row `row`).
+__device__ __forceinline__ void fold16_row(v2s m, int row, int tb, uint64_t &best_f, uint64_t &best_r) {
+  const uint32_t mb = bits(m);
+  const int32_t vf = (int32_t)(int16_t)(mb & 0xFFFFu), vr = (int32_t)(int16_t)(mb >> 16);
+  if ((vf >> 6) > 0) {
+    const uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), row);
+    best_f = kf > best_f ? kf : best_f;
+  }
+  if ((vr >> 6) > 0) {
+    const uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), row);
+    best_r = kr > best_r ? kr : best_r;
+  }
+}
+
 // One strip of R read rows swept over every window column.  FIRST: the strip
 // starts at read row 0 (top boundary H = 0); LAST: no strip follows (nothing
-// is written to the scratch rows).
-template <int R, bool FIRST, bool LAST>
+// is written to the scratch rows).  FR: final-row mode (only row L-1 may hold
+// the best cell); a template parameter so that the local mode keeps its
+// register budget.
+template <int R, bool FIRST, bool LAST, bool FR>
 __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
                                         int lane, int r0, int L, int W, int Wmin, int Wmax, uint64_t &best_f,
                                         uint64_t &best_r) {
@@ -365,13 +381,16 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
       }
       if (!LAST) scr[c * 64 + lane] = make_uint2(bits(Hl[R - 1]), bits(F));
     }
-    if (K.final_row) {
+    if (FR) {
       // read-end-anchored scoring: only row L-1 may hold the best cell
+      const int rr = L - 1 - r0;
+      v2s m = pair(0u);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (r0 + r != L - 1) M[r] = pair(0u);
+      for (int r = 0; r < R; ++r) m = r == rr ? M[r] : m;
+      fold16_row(m, L - 1, tb, best_f, best_r);
+    } else {
+      fold16<R>(M, r0, tb, best_f, best_r);
     }
-    fold16<R>(M, r0, tb, best_f, best_r);
     if (tend < Wmax) {
       // next tile: restart the row maxima and re-base the carried tags by +64
 #pragma unroll
@@ -403,7 +422,7 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
 // reported.  Columns past the lane's window use a table of 0x8000 (a wall).
 
 // One tile of up to 64 CALs (task positions [first, first + count)).
-template <int R>
+template <int R, bool FR>
 __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off, const int64_t *rt_len,
                                        uint32_t *win, uint32_t *rdw, uint2 *scr, int lane, int64_t first,
                                        int count) {
@@ -424,12 +443,12 @@ __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off
   uint64_t best_f = 0, best_r = 0;
   const int nstrips = (Lmax + R - 1) / R;
   if (nstrips == 1) {
-    strip16<R, true, true>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    strip16<R, true, true, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
   } else {
-    strip16<R, true, false>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    strip16<R, true, false, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
     for (int s = 1; s + 1 < nstrips; ++s)
-      strip16<R, false, false>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
-    strip16<R, false, true>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
+      strip16<R, false, false, FR>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
+    strip16<R, false, true, FR>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
   }
   if (L > 0) {
     if (t.mask & 1) write_result(A, 2 * t.c, best_f, t.ws);
@@ -438,7 +457,7 @@ __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off
 }
 
 // Plain launch: fixed 64-CAL tiles, static striding over a persistent grid.
-template <int R>
+template <int R, bool FR>
 __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
@@ -450,11 +469,12 @@ __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTabl
   TileIter it{(int64_t)blockIdx.x, (A.n_tasks + 63) / 64};
   int64_t first, ti;
   int count;
-  while (next_tile(A, it, first, count, ti)) tile16<R>(A, rt_off, rt_len, win, rdw, scr, lane, first, count);
+  while (next_tile(A, it, first, count, ti)) tile16<R, FR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count);
 }
 
 // Batched launch: tiles (each with its own strip height) popped from a device
 // work queue, longest reads first.
+template <bool FR>
 __global__ __launch_bounds__(64) void k_inter16_queue(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
@@ -468,9 +488,11 @@ __global__ __launch_bounds__(64) void k_inter16_queue(const AlignArgs A, const R
   int count;
   while (next_tile(A, it, first, count, ti)) {
     switch (A.tile_strips[ti]) {
-#define SW_Q16_CASE(RR)                                                 \
-  case RR:                                                              \
-    tile16<RR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
+  // the final-row fold needs a few more registers: its queue kernel runs the
+  // 50-row tiles with 48-row strips (any strip height gives the same results)
+#define SW_Q16_CASE(RR)                                                                         \
+  case RR:                                                                                      \
+    tile16<(FR && RR > 48 ? 48 : RR), FR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
     break;
       SW_QUEUE16_STRIPS(SW_Q16_CASE)
 #undef SW_Q16_CASE
@@ -1044,7 +1066,10 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
 template <int R>
 static hipError_t launch_inter16_r(const AlignArgs &A, const RefTable &T, int grid, size_t lds,
                                    hipStream_t st) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16<R>), dim3(grid), dim3(64), lds, st, A, T);
+  if (A.k.final_row)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16<R, true>), dim3(grid), dim3(64), lds, st, A, T);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16<R, false>), dim3(grid), dim3(64), lds, st, A, T);
   return hipGetLastError();
 }
 template <int R>
@@ -1091,8 +1116,10 @@ hipError_t launch_batch_plan(const BatchBufs &B, const int32_t *read_len, int32_
 
 hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st) {
   size_t lds = (size_t)(A.wwords + A.rwords) * 64 * sizeof(uint32_t);
-  if (int16)
-    hipLaunchKernelGGL(k_inter16_queue, dim3(grid), dim3(64), lds, st, A, T);
+  if (int16 && A.k.final_row)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16_queue<true>), dim3(grid), dim3(64), lds, st, A, T);
+  else if (int16)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16_queue<false>), dim3(grid), dim3(64), lds, st, A, T);
   else
     hipLaunchKernelGGL(k_inter32_queue, dim3(grid), dim3(64), lds, st, A, T);
   return hipGetLastError();
@@ -1100,7 +1127,7 @@ hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T,
 
 int queue_blocks_per_cu(bool int16) {
   int n = 0;
-  const void *f = int16 ? reinterpret_cast<const void *>(&k_inter16_queue)
+  const void *f = int16 ? reinterpret_cast<const void *>(&k_inter16_queue<false>)
                         : reinterpret_cast<const void *>(&k_inter32_queue);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, 8192) != hipSuccess) return 0;
   return n;
@@ -1169,7 +1196,7 @@ unsigned long long *error_counter() {
 template <int R>
 static int occ16(size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_inter16<R>), 64,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_inter16<R, false>), 64,
                                                   lds) != hipSuccess)
     return 0;
   return n;
