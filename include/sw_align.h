@@ -271,8 +271,8 @@ int sw_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t 
 /* ------------------------------------------------------------------ traceback */
 /*
  * Start position and CIGAR of selected slots.  The paper's hardware reports
- * only the score and the end (sections 3.5, 3.6); section 7 names CIGAR
- * generation as the work that follows.  For each entry t of `slots` (a slot
+ * only the score and the end (sections 3.5, 3.6); section 6.4 (Table 5) finds
+ * CIGAR string generation the next bottleneck.  For each entry t of `slots` (a slot
  * index 2c+h into the outputs of a scoring call, or -1 to skip) the task's
  * dynamic program is rebuilt up to the reported end cell and walked backwards.
  * Where several alignments reach the score, the walk takes at every cell the

@@ -364,7 +364,8 @@ void oracle_classify(const int32_t *best_score, int32_t n_reads, int32_t n_refs,
 
 /*
  * Start position and CIGAR of selected slots (the alignment behind a score;
- * section 7 names CIGAR generation as the step that follows scoring).
+ * section 6.4 finds CIGAR string generation the next bottleneck once CALs per
+ * seed are limited, Table 5).
  *
  * For slot 2c+h with a positive score, the full H, E, F matrices of the task
  * are rebuilt and walked backwards from the reported end cell.  Several
