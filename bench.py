@@ -232,7 +232,7 @@ class Leg:
         qs = torch.empty(n, dtype=torch.int16, device=dev)
         nops = torch.empty(n, dtype=torch.int32, device=dev)
         cig = torch.zeros(n * cap, dtype=torch.int32, device=dev)
-        nb = sw.lib().sw_traceback_workspace_bytes(n, ctypes.byref(self.scoring))
+        nb = sw.lib().sw_traceback_workspace_bytes(n, db.n_cals, ctypes.byref(self.scoring))
         ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
         st = self.stream
         P = sw._ptr
@@ -263,7 +263,8 @@ class Leg:
         res = {"reads": n, "ms": round(ms, 3), "reads_per_s": round(n / (ms * 1e-3), 1),
                "rectangle_cells": cells, "rectangle_gcups": round(cells / (ms * 1e-3) / 1e9, 1),
                "traced_fraction": round(float((nops > 0).float().mean().item()), 4),
-               "planes": "lds" if nb == 0 else "device"}
+               "kernel": "one slot per lane" if self.scoring.kernel != sw.KERNEL_INTRA else "one slot per wavefront",
+               "workspace_mb": round(nb / 2**20, 1)}
         if parity_reads:
             res["parity_sample_ok"] = self._trace_parity(slots, rs, qs, nops, cig.view(n, cap), cap, parity_reads)
         return res

@@ -282,8 +282,11 @@ int sw_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t 
  * a cell with H = 0 ends the alignment.
  *   reads2bit .. n_cals   the arrays of the scoring call (strands come from the slot)
  *   sc                    the scoring of that call (band, max_read_len and the
- *                         penalties must match; precision, kernel and mode are
- *                         not used)
+ *                         penalties must match; precision and mode are not used);
+ *                         kernel: SW_KERNEL_INTER traces 64 slots per wavefront,
+ *                         one per lane; SW_KERNEL_INTRA one slot per wavefront;
+ *                         SW_KERNEL_AUTO the former unless its per-block buffer
+ *                         would exceed 4 MiB (very long reads or wide bands)
  *   score, ref_end, read_end   device [2*n_cals]: the scoring call's outputs
  *   slots                 device [n_slots] int64
  *   cap                   CIGAR entries per slot (>= 1)
@@ -292,7 +295,8 @@ int sw_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t 
  *                         base; -1 when n_ops <= 0
  *   read_start [n_slots]  first aligned base of the oriented read; -1 likewise
  *   n_ops      [n_slots]  entries written; 0 for a skipped slot or a score <= 0;
- *                         -1 if more than cap entries are needed; -2 if the slot,
+ *                         -1 if more than cap entries are needed (the row is then
+ *                         cleared to 0); -2 if the slot,
  *                         its task or its end cell is invalid (the end cell's H
  *                         differs from the reported score), counted by
  *                         sw_error_count()
@@ -300,9 +304,10 @@ int sw_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t 
  *                         op codes: 1 I (read base only), 2 D (window base only),
  *                         4 S (soft clip: unaligned head and tail of the read),
  *                         7 '=' (match), 8 X (mismatch)
- * `workspace` must hold sw_traceback_workspace_bytes(n_slots, sc) bytes (0 when
- * the per-task buffers fit in on-chip memory: reads up to a few hundred bases)
- * and must not be used by an overlapping call.
+ * `workspace` must hold sw_traceback_workspace_bytes(n_slots, n_cals, sc) bytes
+ * (the one-slot-per-lane kernel keeps 4 bits per cell of each block's 64 tasks
+ * in it: tens of KB per block and read; the wavefront-per-slot kernel needs none
+ * when a task's bits fit in LDS) and must not be used by an overlapping call.
  */
 int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
                  int32_t n_reads, const sw_refset_t *refs, const int64_t *cal_ptr, const int64_t *cal_pos,
@@ -310,7 +315,7 @@ int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const 
                  const int64_t *ref_end, const int16_t *read_end, const int64_t *slots, int64_t n_slots,
                  int32_t cap, int64_t *ref_start, int16_t *read_start, int32_t *n_ops, uint32_t *cigar,
                  void *workspace, size_t workspace_bytes, sw_stream_t stream);
-size_t sw_traceback_workspace_bytes(int64_t n_slots, const sw_scoring_t *sc);
+size_t sw_traceback_workspace_bytes(int64_t n_slots, int64_t n_cals, const sw_scoring_t *sc);
 
 /*
  * Classification of reads between references by best score (section 6.2,

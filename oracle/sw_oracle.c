@@ -384,7 +384,8 @@ void oracle_classify(const int32_t *best_score, int32_t n_reads, int32_t n_refs,
  * Outputs per entry t of `slots`: ref_start (absolute forward position),
  * read_start (in the oriented read), n_ops and cigar[t*cap .. t*cap+n_ops).
  * n_ops = 0 with starts -1 when the slot is -1 or its score is not positive;
- * n_ops = -1 when more than `cap` operations are needed; n_ops = -2 when the
+ * n_ops = -1 (row cleared to 0) when more than `cap` operations are needed;
+ * n_ops = -2 when the
  * slot, its task or its reported end is invalid (the end cell's H differs from
  * the reported score).
  */
@@ -523,6 +524,7 @@ void oracle_traceback(const uint8_t *read_codes, const int64_t *read_off, const 
     }
     if (n > cap) {
       out_n_ops[t] = -1;
+      for (int64_t x = 0; x < cap; ++x) cigar[t * cap + x] = 0;
     } else {
       out_ref_start[t] = ws + j;
       out_read_start[t] = (int16_t)i;

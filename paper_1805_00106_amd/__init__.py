@@ -116,7 +116,7 @@ def lib():
         L.sw_cal_filter.argtypes = [vp, vp, vp, vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.sw_cal_filter_workspace_bytes.argtypes = [i32]
         L.sw_cal_filter_workspace_bytes.restype = ctypes.c_size_t
-        L.sw_traceback_workspace_bytes.argtypes = [i64, ctypes.POINTER(Scoring)]
+        L.sw_traceback_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Scoring)]
         L.sw_traceback_workspace_bytes.restype = ctypes.c_size_t
         L.sw_tied_flags.argtypes = [vp, i32, vp, vp, vp]
         L.sw_ctx_create.argtypes = [ctypes.POINTER(_CtxOpts), ctypes.POINTER(vp)]
@@ -290,7 +290,7 @@ def traceback(db: DeviceBatch, refs: "RefSet", sc: Scoring, out: "Outputs", slot
     qs = torch.empty(n, dtype=torch.int16, device=dev)
     nops = torch.empty(n, dtype=torch.int32, device=dev)
     cig = torch.zeros(max(n, 1) * cap, dtype=torch.int32, device=dev)
-    nb = lib().sw_traceback_workspace_bytes(n, ctypes.byref(sc))
+    nb = lib().sw_traceback_workspace_bytes(n, db.n_cals, ctypes.byref(sc))
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
     _check(lib().sw_traceback(_ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len), db.n_reads, refs.c,
                               _ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref), db.n_cals, ctypes.byref(sc),

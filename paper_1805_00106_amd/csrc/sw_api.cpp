@@ -12,6 +12,7 @@
 #include "sw_api_internal.h"
 #include "sw_filter.h"
 #include "sw_launch.h"
+#include "sw_trace.h"
 
 namespace swapi {
 
@@ -355,17 +356,37 @@ int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_rea
 
 namespace {
 
-// Grid and workspace of a traceback launch.
+// Kernel family, grid and workspace of a traceback launch.  One slot per lane
+// (64 per wavefront) unless its per-block bit buffer would exceed 4 MiB (very
+// long reads or wide bands) or the caller asks for the wavefront-per-slot kernel.
+constexpr size_t kTraceInterBlockLimit = 4u << 20;
+
 struct TraceLaunch {
-  swk::TracePlan P;
+  bool inter;
+  swk::TracePlan P;  // wavefront-per-slot kernel
   int grid;
-  size_t bytes;  // workspace: per-block plane buffers when they do not fit in LDS
+  size_t block_bytes;     // one-slot-per-lane kernel: bits + boundary rows per block
+  size_t cal_read_bytes;  // one-slot-per-lane kernel: owner read per CAL
+  size_t bytes;           // total workspace
 };
 
-int trace_launch(int64_t n_slots, const sw_scoring_t *sc, TraceLaunch *t) {
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+int trace_launch(int64_t n_slots, int64_t n_cals, const sw_scoring_t *sc, TraceLaunch *t) {
   ScoreMode m;
   int rc = validate_scoring(sc, &m);
   if (rc) return rc;
+  const size_t bb = swk::trace_inter_block_bytes(m.max_read_len, m.wcap);
+  t->inter = sc->kernel == SW_KERNEL_INTER || (sc->kernel == SW_KERNEL_AUTO && bb <= kTraceInterBlockLimit);
+  if (t->inter) {
+    const int64_t tiles = (n_slots + 63) / 64;
+    const int64_t resident = (int64_t)device_cus() * swk::trace_inter_blocks_per_cu();
+    t->grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, resident));
+    t->block_bytes = align256(bb);
+    t->cal_read_bytes = align256(sizeof(int32_t) * (size_t)std::max<int64_t>(n_cals, 1));
+    t->bytes = t->cal_read_bytes + (size_t)t->grid * t->block_bytes;
+    return SW_OK;
+  }
   t->P = swk::trace_plan(m.max_read_len, m.wcap);
   const int64_t resident = (int64_t)device_cus() * swk::trace_blocks_per_cu(t->P);
   t->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_slots, resident));
@@ -375,10 +396,10 @@ int trace_launch(int64_t n_slots, const sw_scoring_t *sc, TraceLaunch *t) {
 
 }  // namespace
 
-size_t sw_traceback_workspace_bytes(int64_t n_slots, const sw_scoring_t *sc) {
-  if (n_slots <= 0) return 0;
+size_t sw_traceback_workspace_bytes(int64_t n_slots, int64_t n_cals, const sw_scoring_t *sc) {
+  if (n_slots <= 0 || n_cals < 0) return 0;
   TraceLaunch t;
-  if (trace_launch(n_slots, sc, &t) != SW_OK) return 0;
+  if (trace_launch(n_slots, n_cals, sc, &t) != SW_OK) return 0;
   return t.bytes;
 }
 
@@ -400,7 +421,7 @@ int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const 
       !read_end || !slots || !ref_start || !read_start || !n_ops || !cigar)
     return SW_ERR_INVALID_ARG;
   TraceLaunch tl;
-  rc = trace_launch(n_slots, sc, &tl);
+  rc = trace_launch(n_slots, n_cals, sc, &tl);
   if (rc) return rc;
   if (tl.bytes > 0 && (!workspace || workspace_bytes < tl.bytes)) return SW_ERR_WORKSPACE;
   unsigned long long *err = swk::error_counter();
@@ -439,7 +460,27 @@ int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const 
   A.win_words = tl.P.win_words;
   A.run_cap = tl.P.run_cap;
   A.planes_lds_off = (int64_t)tl.P.planes_lds_off;
-  hipError_t e = swk::launch_trace(A, T, tl.P, tl.grid, (hipStream_t)stream);
+  hipError_t e;
+  if (tl.inter) {
+    swk::TraceInterArgs I{};
+    I.a = A;
+    I.a.planes_global = nullptr;
+    int32_t *cal_read = static_cast<int32_t *>(workspace);
+    I.cal_read = cal_read;
+    I.bits = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + tl.cal_read_bytes);
+    // per block, one block_bytes slice: [bits | boundary rows]
+    const size_t bits_bytes = swk::trace_inter_block_bytes(m.max_read_len, m.wcap) - (size_t)m.wcap * 64 * 8;
+    I.bits_stride = (int64_t)(tl.block_bytes / 4);
+    I.bscr = reinterpret_cast<uint2 *>(static_cast<char *>(workspace) + tl.cal_read_bytes + bits_bytes);
+    I.bscr_stride = (int64_t)(tl.block_bytes / 8);
+    I.wcap = m.wcap;
+    I.rwords = (m.max_read_len + 15) / 16;
+    I.wwords = (m.wcap + 15) / 16;
+    e = swk::launch_expand(cal_ptr, n_reads, n_cals, cal_read, (hipStream_t)stream);
+    if (e == hipSuccess) e = swk::launch_trace_inter(I, T, tl.grid, (hipStream_t)stream);
+  } else {
+    e = swk::launch_trace(A, T, tl.P, tl.grid, (hipStream_t)stream);
+  }
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 

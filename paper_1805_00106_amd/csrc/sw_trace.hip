@@ -276,6 +276,8 @@ __global__ __launch_bounds__(64) void k_trace(const TraceArgs A, const RefTable 
     ++n;
     __syncthreads();
     if (n > A.cap) {
+      uint32_t *out = A.cigar + t * (int64_t)A.cap;
+      for (int x = lane; x < A.cap; x += 64) out[x] = 0u;  // an over-capacity row is cleared
       if (lane == 0) {
         A.ref_start[t] = -1;
         A.read_start[t] = -1;
@@ -322,6 +324,299 @@ hipError_t launch_trace(const TraceArgs &A, const RefTable &T, const TracePlan &
     hipLaunchKernelGGL(k_trace<true>, dim3(grid), dim3(64), P.lds, st, A, T);
   else
     hipLaunchKernelGGL(k_trace<false>, dim3(grid), dim3(64), P.lds, st, A, T);
+  return hipGetLastError();
+}
+
+}  // namespace swk
+
+// --------------------------------------------------------------------------- one slot per lane
+//
+// The wavefront traces 64 slots at once, one per lane, with the read rows of a
+// strip in registers and the window columns swept left to right, as in the
+// scoring kernels (plain int32 values: the end cell is known).  For every
+// cell the lane records 4 bits: the source of H (0 diagonal, 1 F, 2 E, 3
+// diagonal from a zero cell or the boundary, i.e. the first aligned pair) and
+// whether the E and F leaving the cell are opened from its H.  Eight cells of
+// a column form one 32-bit word per lane, stored coalesced as
+// [strip][column][group][lane] in the block's device buffer; each lane then
+// walks its own path back through its words.
+
+#include "sw_trace.h"
+
+namespace swk {
+
+namespace {
+
+__device__ __forceinline__ uint32_t code_at(const uint32_t *bits, int cmax, int lane, int i, int j) {
+  const int s = i / kTraceRows, r = i - s * kTraceRows;
+  const uint32_t w = bits[(((int64_t)s * cmax + j) * kTraceGroups + (r >> 3)) * 64 + lane];
+  return (w >> (4 * (r & 7))) & 15u;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_trace_inter(const TraceInterArgs I, const RefTable T) {
+  extern __shared__ uint32_t tism[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const TraceArgs &A = I.a;
+  const int lane = threadIdx.x;
+  for (int i = 0; i < A.n_refs; ++i)
+    if (lane == i) {
+      rt_off[i] = T.word_off[i];
+      rt_len[i] = T.len[i];
+    }
+  __syncthreads();
+  uint32_t *rdw = tism;                  // [rwords][64] read words
+  uint32_t *win = tism + I.rwords * 64;  // [wwords][64] window words
+  uint32_t *bits = I.bits + (size_t)blockIdx.x * I.bits_stride;
+  uint2 *bscr = I.bscr + (size_t)blockIdx.x * I.bscr_stride;
+  const int32_t goe = A.goe, ge = A.ge;
+
+  for (int64_t first = (int64_t)blockIdx.x * 64; first < A.n_slots; first += (int64_t)gridDim.x * 64) {
+    const int64_t t = first + lane;
+    // ---- this lane's task; n_rows = 0 leaves the lane idle
+    int status = 0, L = 0, h = 0, k = 0, ie = -1, je = -1;
+    int64_t r = -1, ws = 0, slot = -1;
+    int32_t sc = 0;
+    bool live = false;
+    if (t < A.n_slots) {
+      slot = A.slots[t];
+      if (slot != -1) {
+        if (slot < 0 || slot >= 2 * A.n_cals) {
+          status = -2;
+        } else if ((sc = A.score[slot]) > 0) {
+          const int64_t c = slot >> 1;
+          h = (int)(slot & 1);
+          r = I.cal_read[c];
+          const int64_t p = A.cal_pos[c];
+          k = A.cal_ref[c];
+          L = r >= 0 && r < A.n_reads ? A.read_len[r] : 0;
+          if (r < 0 || L < 1 || L > A.max_read_len || k < 0 || k >= A.n_refs || p < 0 || p >= rt_len[k]) {
+            status = -2;
+          } else {
+            ws = p - A.band < 0 ? 0 : p - A.band;
+            const int64_t we = min(rt_len[k], p + L + A.band);
+            ie = A.read_end[slot];
+            const int64_t je64 = A.ref_end[slot] - ws;
+            if (ie < 0 || ie >= L || je64 < 0 || je64 >= we - ws) status = -2;
+            else {
+              je = (int)je64;
+              live = true;
+            }
+          }
+        }
+      }
+      if (!live) {
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = status;
+        if (status) atomicAdd(A.err, 1ull);
+      }
+    }
+    const int n_rows = live ? ie + 1 : 0, n_cols = live ? je + 1 : 0;
+    int rmax = n_rows, cmax = n_cols, lmax = live ? L : 0;
+    for (int m = 32; m; m >>= 1) {
+      rmax = max(rmax, __shfl_xor(rmax, m, 64));
+      cmax = max(cmax, __shfl_xor(cmax, m, 64));
+      lmax = max(lmax, __shfl_xor(lmax, m, 64));
+    }
+    if (rmax == 0) continue;
+    // ---- stage the lane's read and window words ([word][lane] in LDS); the whole
+    // read is needed: a reverse-strand row i reads original base L-1-i
+    __syncthreads();
+    {
+      const int nrw = (lmax + 15) >> 4, nww = (cmax + 15) >> 4;
+      if (live) {
+        const uint32_t *rp = A.reads + A.read_word_off[r];
+        const int lw = (L + 15) >> 4;
+        for (int q = 0; q < nrw; ++q) rdw[q * 64 + lane] = q < lw ? rp[q] : 0u;
+        const int64_t fw = rt_off[k] + (ws >> 4);
+        const int64_t last = rt_off[k] + ((rt_len[k] - 1) >> 4);
+        const uint32_t sh = 2u * (uint32_t)(ws & 15);
+        uint32_t lo = A.ref_words[fw];
+        for (int q = 0; q < nww; ++q) {
+          const uint32_t hi = fw + q + 1 <= last ? A.ref_words[fw + q + 1] : 0u;
+          win[q * 64 + lane] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+          lo = hi;
+        }
+      } else {
+        for (int q = 0; q < nrw; ++q) rdw[q * 64 + lane] = 0u;
+        for (int q = 0; q < nww; ++q) win[q * 64 + lane] = 0u;
+      }
+    }
+    __syncthreads();
+    auto qbase = [&](int i) -> int32_t {  // oriented read base of row i
+      const int src = h == 0 ? i : L - 1 - i;
+      const int32_t b = (int32_t)((rdw[(src >> 4) * 64 + lane] >> (2 * (src & 15))) & 3u);
+      return h == 0 ? b : 3 - b;
+    };
+    auto wbase = [&](int j) -> int32_t {
+      return (int32_t)((win[(j >> 4) * 64 + lane] >> (2 * (j & 15))) & 3u);
+    };
+
+    // ---- sweep: strips of kTraceRows rows, columns left to right
+    int32_t endv = -1;
+    const int nstrips = (rmax + kTraceRows - 1) / kTraceRows;
+    for (int s = 0; s < nstrips; ++s) {
+      const int r0 = s * kTraceRows;
+      int32_t q[kTraceRows], Hl[kTraceRows], E[kTraceRows];
+#pragma unroll
+      for (int x = 0; x < kTraceRows; ++x) {
+        q[x] = r0 + x < n_rows ? qbase(r0 + x) : 4;  // 4 never equals a window base
+        Hl[x] = 0;                                    // H(i, -1)
+        E[x] = -goe;                                  // E(i, 0)
+      }
+      int32_t hup_prev = 0;  // H(r0 - 1, -1)
+      if (s > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      for (int c = 0; c < cmax; ++c) {
+        const int32_t w = c < n_cols ? wbase(c) : 5;
+        int32_t hup, F;
+        if (s == 0) {
+          hup = 0;
+          F = -goe;
+        } else {
+          const uint2 b = bscr[c * 64 + lane];
+          hup = (int32_t)b.x;
+          F = (int32_t)b.y;
+        }
+        int32_t Hd = hup_prev;
+        hup_prev = hup;
+        uint32_t word[kTraceGroups];
+#pragma unroll
+        for (int x = 0; x < kTraceRows; ++x) {
+          const int32_t diag = Hd + (q[x] == w ? A.match : A.mismatch);
+          const int32_t H = max(max(diag, E[x]), max(F, 0));
+          const uint32_t code = H == diag ? (Hd == 0 ? 3u : 0u) : (H == F ? 1u : 2u);
+          const int32_t U = H - goe;
+          const int32_t e2 = E[x] - ge, f2 = F - ge;
+          const bool eo = U >= e2, fo = U >= f2;
+          E[x] = eo ? U : e2;
+          F = fo ? U : f2;
+          const uint32_t nib = code | (eo ? 4u : 0u) | (fo ? 8u : 0u);
+          if ((x & 7) == 0)
+            word[x >> 3] = nib;
+          else
+            word[x >> 3] |= nib << (4 * (x & 7));
+          Hd = Hl[x];
+          Hl[x] = H;
+        }
+#pragma unroll
+        for (int g = 0; g < kTraceGroups; ++g) bits[(((int64_t)s * cmax + c) * kTraceGroups + g) * 64 + lane] = word[g];
+        if (s + 1 < nstrips) bscr[c * 64 + lane] = make_uint2((uint32_t)Hl[kTraceRows - 1], (uint32_t)F);
+        if (c == je && ie >= r0 && ie < r0 + kTraceRows) {
+#pragma unroll
+          for (int x = 0; x < kTraceRows; ++x)
+            if (ie == r0 + x) endv = Hl[x];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __syncthreads();
+    }
+
+    // ---- walk (each lane its own path); runs go to the output row end first
+    if (live) {
+      if (endv != sc) {
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = -2;
+        atomicAdd(A.err, 1ull);
+      } else {
+        uint32_t *out = A.cigar + t * (int64_t)A.cap;
+        int n = 0;
+        uint32_t cur_op = 0, cur_len = 0;
+        auto flush = [&]() {
+          if (cur_len) {
+            if (n < A.cap) out[n] = (cur_len << 4) | cur_op;
+            ++n;
+          }
+        };
+        auto emit = [&](uint32_t op) {
+          if (op != cur_op) {
+            flush();
+            cur_op = op;
+            cur_len = 0;
+          }
+          ++cur_len;
+        };
+        if (L - 1 - ie > 0) {
+          cur_op = 4;
+          cur_len = (uint32_t)(L - 1 - ie);
+        }
+        int i = ie, j = je, state = 0, start_i = 0, start_j = 0;
+        for (;;) {
+          if (state == 0) {
+            const uint32_t code = code_at(bits, cmax, lane, i, j) & 3u;
+            if (code == 0u || code == 3u) {
+              emit(qbase(i) == wbase(j) ? 7u : 8u);
+              if (code == 3u) {
+                start_i = i;
+                start_j = j;
+                break;
+              }
+              --i;
+              --j;
+              if (i < 0 || j < 0) {  // cannot happen: a diagonal from the boundary has code 3
+                start_i = i + 1;
+                start_j = j + 1;
+                break;
+              }
+            } else {
+              state = (int)code;
+            }
+          } else if (state == 1) {
+            emit(1u);
+            if (i == 0 || (code_at(bits, cmax, lane, i - 1, j) & 8u)) state = 0;
+            --i;
+            if (i < 0) break;  // cannot happen for a consistent matrix
+          } else {
+            emit(2u);
+            if (j == 0 || (code_at(bits, cmax, lane, i, j - 1) & 4u)) state = 0;
+            --j;
+            if (j < 0) break;  // cannot happen for a consistent matrix
+          }
+        }
+        if (start_i > 0) {
+          emit(4u);
+          cur_len = (uint32_t)start_i;
+        }
+        flush();
+        if (n > A.cap) {
+          for (int x = 0; x < A.cap; ++x) out[x] = 0u;  // an over-capacity row is cleared
+          A.ref_start[t] = -1;
+          A.read_start[t] = -1;
+          A.n_ops[t] = -1;
+        } else {
+          for (int x = 0; x < n / 2; ++x) {
+            const uint32_t a = out[x];
+            out[x] = out[n - 1 - x];
+            out[n - 1 - x] = a;
+          }
+          A.ref_start[t] = ws + start_j;
+          A.read_start[t] = (int16_t)start_i;
+          A.n_ops[t] = n;
+        }
+      }
+    }
+  }
+}
+
+size_t trace_inter_block_bytes(int max_read_len, int wcap) {
+  const size_t strips = (size_t)(max_read_len + kTraceRows - 1) / kTraceRows;
+  return strips * (size_t)wcap * kTraceGroups * 64 * 4 + (size_t)wcap * 64 * 8;
+}
+
+int trace_inter_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_trace_inter), 64, 8192) !=
+      hipSuccess)
+    return 1;
+  return n < 1 ? 1 : n;
+}
+
+hipError_t launch_trace_inter(const TraceInterArgs &A, const RefTable &T, int grid, hipStream_t st) {
+  if (A.a.n_slots == 0) return hipSuccess;
+  const size_t lds = (size_t)(A.rwords + A.wwords) * 64 * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_trace_inter, dim3(grid), dim3(64), lds, st, A, T);
   return hipGetLastError();
 }
 

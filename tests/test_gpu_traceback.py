@@ -13,10 +13,11 @@ from tests.gpu_util import assert_same, oracle_align, scoring_for
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_trace(batch, slots, cap, precision=sw.PREC_AUTO, max_read_len=None, mode=sw.MODE_LOCAL):
+def _gpu_trace(batch, slots, cap, precision=sw.PREC_AUTO, max_read_len=None, mode=sw.MODE_LOCAL,
+               kernel=sw.KERNEL_AUTO):
     refs = sw.RefSet.from_codes(torch.from_numpy(batch.ref_codes).cuda(), batch.ref_off, batch.ref_len)
     db = sw.DeviceBatch.upload(batch)
-    sc = scoring_for(batch, precision, max_read_len=max_read_len, mode=mode)
+    sc = scoring_for(batch, precision, kernel=kernel, max_read_len=max_read_len, mode=mode)
     out = sw.align_batch(db, refs, sc)
     rs, qs, nops, cig = sw.traceback(db, refs, sc, out, torch.as_tensor(np.asarray(slots, np.int64)), cap=cap)
     torch.cuda.synchronize()
@@ -37,10 +38,12 @@ def _case(batch, slots=None, cap=64, max_read_len=None, mode=sw.MODE_LOCAL, **kw
     if slots is None:
         slots = np.arange(2 * batch.n_cals, dtype=np.int64)
     mrl = max_read_len or max(int(batch.read_len.max()), 1)
-    got_s, got_t = _gpu_trace(batch, slots, cap, max_read_len=mrl, mode=mode, **kw)
     exp_s, exp_t = _oracle_trace(batch, slots, cap, mrl, mode=mode)
-    assert_same(got_s, exp_s, f"{batch.name} scores")
-    assert_same(got_t, exp_t, f"{batch.name} traceback cap={cap}")
+    # both kernel families: one traced slot per lane, one per wavefront
+    for kernel in (sw.KERNEL_INTER, sw.KERNEL_INTRA):
+        got_s, got_t = _gpu_trace(batch, slots, cap, max_read_len=mrl, mode=mode, kernel=kernel, **kw)
+        assert_same(got_s, exp_s, f"{batch.name} scores kernel={kernel}")
+        assert_same(got_t, exp_t, f"{batch.name} traceback cap={cap} kernel={kernel}")
     # every traced CIGAR spans the read exactly and ends where the score says
     for t, slot in enumerate(slots):
         n = int(exp_t["n_ops"][t])
@@ -102,5 +105,5 @@ def test_trace_skip_invalid_and_capacity():
     t = _case(b, slots=slots, cap=3)
     assert t["n_ops"][0] == 0 and t["n_ops"][3] == -2 and t["n_ops"][4] == -2 and t["n_ops"][5] == -2
     assert (t["n_ops"] == -1).any() and (t["n_ops"] > 0).any()
-    assert sw.error_count() == 3
+    assert sw.error_count() == 3 * 2   # three invalid slots, traced by both kernel families
 
