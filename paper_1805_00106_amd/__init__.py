@@ -333,6 +333,7 @@ class SeedIndex:
     def __init__(self, refs: "RefSet", seed_len: int = 22, addr_bits: int = 0, device: int = 0, stream=None):
         self._h = ctypes.c_void_p()
         self.seed_len = seed_len
+        self._cap_hint = 0  # CALs found by the last call: the next call's first guess
         o = _IndexOpts(device, seed_len, addr_bits)
         _check(lib().sw_index_build(refs.c, ctypes.byref(o), ctypes.byref(self._h), _stream(stream)),
                "sw_index_build")
@@ -348,7 +349,7 @@ class SeedIndex:
         dev = db.read_len.device
         o = _FindOpts(stride, max_cals_per_seed, max_read_len)
         ptr = torch.empty(db.n_reads + 1, dtype=torch.int64, device=dev)
-        cap = capacity if capacity is not None else 16 * max(db.n_reads, 1)
+        cap = capacity if capacity is not None else max(16 * max(db.n_reads, 1), self._cap_hint)
         for _ in range(2):
             pos = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
             ref = torch.empty(max(cap, 1), dtype=torch.int16, device=dev)
@@ -362,6 +363,7 @@ class SeedIndex:
                 continue
             _check(rc, "sw_find_cals")
             m = n.value
+            self._cap_hint = max(self._cap_hint, m + m // 8)
             return DeviceBatch(db.reads2bit, db.read_word_off, db.read_len, ptr, pos[:m], ref[:m], st[:m])
         raise SwError(-5, "sw_find_cals")
 
