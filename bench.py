@@ -95,18 +95,52 @@ def cpu_baseline(batch, target_s: float = 15.0):
             "reads_per_s": round(n / dt, 1)}
 
 
-def parity_sample(batch, out, n=300, seed=7):
+def parity_sample(batch, out, n=300, seed=7, final_row=False):
     """Compare a random sample of reads against the oracle (not timed)."""
     from oracle import oracle as orc
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(batch.n_reads, min(n, batch.n_reads), replace=False))
     sub = batch.subset_reads(idx)
-    s, r, e, _ = orc.align_batch(sub, n_threads=min(16, os.cpu_count() or 1))
+    s, r, e, _ = orc.align_batch(sub, n_threads=min(16, os.cpu_count() or 1), final_row=final_row)
     sel = np.concatenate([np.arange(batch.cal_ptr[i], batch.cal_ptr[i + 1]) for i in idx])
     slots = np.stack([2 * sel, 2 * sel + 1], 1).reshape(-1)
     gs, gr, ge = (out.score.cpu().numpy()[slots], out.ref_end.cpu().numpy()[slots],
                   out.read_end.cpu().numpy()[slots])
     return bool(np.array_equal(gs, s) and np.array_equal(gr, r) and np.array_equal(ge, e))
+
+
+def config1_leg(reps=20):
+    """Config 1 exactly as stated (1000 x 76 bp reads, 2 CALs each, both strands,
+    int32): one plain call per kernel family, CALs and reads resident."""
+    import torch
+    import paper_1805_00106_amd as sw
+    from paper_1805_00106_amd import workloads as wl
+    b = wl.config1()
+    refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
+    db = sw.DeviceBatch.upload(b)
+    out = sw.Outputs(db.n_cals)
+    cells = cells_of(b)
+    res = {"reads": b.n_reads, "cals": b.n_cals, "cells": cells}
+    outs = {}
+    for name, kern in (("inter_int32", sw.KERNEL_INTER), ("intra_int32", sw.KERNEL_INTRA),
+                       ("auto_int32", sw.KERNEL_AUTO)):
+        sc = sw.Scoring.make(2, -3, 5, 2, 32, sw.PREC_INT32, kern, 76)
+        ws = torch.empty(max(1, sw.workspace_bytes(db.n_reads, db.n_cals, sc)), dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            sw.align_batch(db, refs, sc, out, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            sw.align_batch(db, refs, sc, out, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"us": round(ms * 1e3, 1), "gcups": round(cells / (ms * 1e-3) / 1e9, 1),
+                     "reads_per_s": round(b.n_reads / (ms * 1e-3), 1)}
+        outs[name] = out.score.clone()
+    res["same_outputs"] = bool(all(torch.equal(outs["inter_int32"], v) for v in outs.values()))
+    return res
 
 
 def small_batch_latency(batch, n_reads=24, reps=20):
@@ -171,6 +205,7 @@ class Leg:
         self.nt = torch.empty(db.n_reads * batch.n_refs, dtype=torch.int32, device=dev)
         self.ctx = sw.Context(db.n_reads, db.n_cals)
         self.cells = cells_of(batch)
+        self.parity_reads = True
 
     def step(self, batched, k_events=None):
         sw, db, L, st = self.sw, self.db, self.sw.lib(), self.stream
@@ -220,6 +255,38 @@ class Leg:
                 "batched_kern_ms": batched_kern, "wall": wall, "plain_gcups": g(plain_ms),
                 "batched_gcups": g(batched_ms), "plain_equals_batched": same, "aligned_fraction": aligned,
                 "plan": self.ctx.last_plan()}
+
+    def variants(self, steps=5):
+        """The same resident config-2 batch on the batched path with other
+        scorings: int32 values (one strand per lane, the precision config 1
+        states) and the final-row mode (int16).  Outputs are checked against the
+        oracle on a read sample (not timed)."""
+        torch, sw = self.torch, self.sw
+        sc = self.batch.scoring
+        res = {}
+        for name, prec, mode, peak in (("int32", sw.PREC_INT32, sw.MODE_LOCAL, PEAK_INT32_TOPS),
+                                       ("final_row_int16", sw.PREC_INT16, sw.MODE_FINAL_ROW, PEAK_INT16_TOPS)):
+            scv = sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, prec,
+                                  sw.KERNEL_INTER, self.scoring.max_read_len, mode)
+            out = sw.Outputs(self.db.n_cals, self.db.read_len.device)
+            for _ in range(2):
+                self.ctx.align(self.db, self.refs, scv, out, self.stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(self.stream)
+            for _ in range(steps):
+                self.ctx.align(self.db, self.refs, scv, out, self.stream)
+            e1.record(self.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            gcups = self.cells / (ms * 1e-3) / 1e9
+            res[name] = {"ms_per_step": round(ms, 3), "gcups": round(gcups, 1),
+                         "roofline_frac": round(OPS_PER_CELL * gcups * 1e9 / (peak * 1e12), 4),
+                         "plan": self.ctx.last_plan()}
+            if self.parity_reads:
+                res[name]["parity_sample_ok"] = parity_sample(self.batch, out, n=100,
+                                                              final_row=mode == sw.MODE_FINAL_ROW)
+        return res
 
     def traceback(self, reps=5, cap=64, parity_reads=200):
         """Start + CIGAR of every read's best slot (from the last scoring step's
@@ -492,6 +559,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pipeline", type=int, default=1, help="1: also time seeds -> CALs -> filter -> score")
+    ap.add_argument("--variants", type=int, default=1, help="1: also time int32 and final-row scoring, config 1")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run an elementwise copy of this size (counter calibration for profiles)")
@@ -512,6 +580,8 @@ def main():
     leg = Leg(batch, int(batch.read_len.max()), args.steps, args.warmup)
     r2 = leg.run()
     parity = None if args.no_parity else parity_sample(batch, leg.out)
+    leg.parity_reads = not args.no_parity
+    variants = leg.variants() if args.variants else None
     trace = leg.traceback(parity_reads=0 if args.no_parity else 200)
     pipe = leg.pipeline() if args.pipeline else None
     small = small_batch_latency(batch)
@@ -571,6 +641,8 @@ def main():
                   "kernel_ms": round(r2["plain_kern_ms"], 3)},
         "plain_equals_batched": r2["plain_equals_batched"],
         "small_batch_latency": small,
+        "variants": variants,
+        "config1": config1_leg() if args.variants else None,
         "traceback": trace,
         "seed_to_score": pipe,
         "aligned_fraction": round(r2["aligned_fraction"], 4), "aligned_threshold": ALIGNED_THRESHOLD,

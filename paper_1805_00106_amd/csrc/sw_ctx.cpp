@@ -114,7 +114,7 @@ struct CallArgs {
   int16_t *read_end;
 };
 
-swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t) {
+swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t, bool final_row) {
   swk::BinParams P{};
   P.bin_width = t.bin_width;
   P.max_read_len = m.max_read_len;
@@ -123,8 +123,12 @@ swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t) {
   P.descending = t.descending;
   const int *s = m.int16 ? kQueueStrips16 : kQueueStrips32;
   const int n = m.int16 ? (int)(sizeof(kQueueStrips16) / sizeof(int)) : (int)(sizeof(kQueueStrips32) / sizeof(int));
-  P.n_strips = n;
-  for (int i = 0; i < n; ++i) P.strips[i] = s[i];
+  P.n_strips = 0;
+  for (int i = 0; i < n; ++i) {
+    // the int16 final-row queue kernel has no 50-row variant (register budget)
+    if (m.int16 && final_row && s[i] > 48) continue;
+    P.strips[P.n_strips++] = s[i];
+  }
   return P;
 }
 
@@ -149,7 +153,7 @@ int enqueue(sw_ctx *c, const CallArgs &a, const swapi::ScoreMode &m, const swk::
   if (e != hipSuccess) return swapi::hip_fail(e);
   e = swk::launch_expand(a.cal_ptr, a.n_reads, a.n_cals, c->B.cal_read, st);
   if (e != hipSuccess) return swapi::hip_fail(e);
-  const swk::BinParams P = bin_params(m, t);
+  const swk::BinParams P = bin_params(m, t, a.sc->mode == SW_MODE_FINAL_ROW);
   e = swk::launch_batch_plan(c->B, a.read_len, a.n_reads, n_tasks, P, st);
   if (e != hipSuccess) return swapi::hip_fail(e);
   swk::AlignArgs A{};
@@ -208,7 +212,8 @@ std::string graph_key(const CallArgs &a, const swapi::ScoreMode &m, const TunedP
 
 std::string tune_key(const swapi::ScoreMode &m, const sw_scoring_t *sc, int64_t n_tasks) {
   char k[128];
-  std::snprintf(k, sizeof k, "gfx950/%s/L%d/b%d/t%d", m.int16 ? "int16" : "int32", m.max_read_len, sc->band,
+  std::snprintf(k, sizeof k, "gfx950/%s%s/L%d/b%d/t%d", m.int16 ? "int16" : "int32",
+                sc->mode == SW_MODE_FINAL_ROW ? "-final-row" : "", m.max_read_len, sc->band,
                 (int)std::floor(std::log2((double)std::max<int64_t>(n_tasks, 1))));
   return k;
 }

@@ -488,8 +488,8 @@ __global__ __launch_bounds__(64) void k_inter16_queue(const AlignArgs A, const R
   int count;
   while (next_tile(A, it, first, count, ti)) {
     switch (A.tile_strips[ti]) {
-  // the final-row fold needs a few more registers: its queue kernel runs the
-  // 50-row tiles with 48-row strips (any strip height gives the same results)
+  // the final-row fold needs a few more registers: the planner gives its tiles no
+  // 50-row strips, and a 50-row tile would still run correctly as 48-row strips
 #define SW_Q16_CASE(RR)                                                                         \
   case RR:                                                                                      \
     tile16<(FR && RR > 48 ? 48 : RR), FR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
