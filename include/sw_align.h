@@ -68,7 +68,8 @@ typedef struct ihipStream_t *sw_stream_t; /* a hipStream_t */
 #define SW_PREC_INT32 2
 
 /* kernel family */
-#define SW_KERNEL_AUTO 0  /* inter-task unless the window is too wide for it */
+#define SW_KERNEL_AUTO 0  /* one wavefront per task for small int32-capable batches (at most
+                             32 tasks per compute unit), one CAL per lane otherwise */
 #define SW_KERNEL_INTER 1 /* one CAL per lane (both strands in one lane) */
 #define SW_KERNEL_INTRA 2 /* one wavefront per CAL, lanes hold window columns */
 
