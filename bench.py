@@ -450,7 +450,7 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD):
     return out
 
 
-def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9), step_cals: int = 1 << 19):
+def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9), step_cals: int = 1 << 20):
     """Config 5: two resident references, Poisson arrivals of log-uniform request
     sizes, p50/p99 latency (scheduled arrival -> completion) at three loads
     relative to the measured saturated throughput."""
@@ -481,8 +481,19 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
         srv.wait(srv.submit_batch(b))
     rounds = 3  # the pool three times over, so ramp-up and drain are a small part
     preps = [srv.prepare_batch(b) for _ in range(rounds) for b in pool]
+    n_clients = 4  # client threads submitting at once (the library calls release the GIL)
+    hs = [None] * len(preps)
+
+    def client(k):
+        for i in range(k, len(preps), n_clients):
+            hs[i] = srv.submit_prepared(preps[i])
+
     t0 = time.monotonic()
-    hs = [srv.submit_prepared(p) for p in preps]
+    clients = [threading.Thread(target=client, args=(k,)) for k in range(n_clients)]
+    for th in clients:
+        th.start()
+    for th in clients:
+        th.join()
     for h in hs:
         srv.wait(h)
     dt = time.monotonic() - t0
@@ -555,7 +566,7 @@ def main():
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=300)
-    ap.add_argument("--serve-step-cals", type=int, default=1 << 19, help="CALs per device step of the server")
+    ap.add_argument("--serve-step-cals", type=int, default=1 << 20, help="CALs per device step of the server")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pipeline", type=int, default=1, help="1: also time seeds -> CALs -> filter -> score")

@@ -362,10 +362,14 @@ const char *sw_ctx_last_plan(sw_ctx_t *ctx);
 
 /* ------------------------------------------------------------------ served */
 /*
- * A server keeps a reference set resident, admits requests by their device
- * memory footprint and packs chunks of every admitted request into each device
- * step (continuous batching): a request that arrives while a step runs joins
- * the next step as soon as arena memory frees up.  Each step runs the batched
+ * A server keeps a reference set resident, admits requests by their footprint
+ * in a pinned staging arena that the device maps, and packs chunks of every
+ * admitted request into each device step (continuous batching): a request that
+ * arrives while a step runs joins the next step as soon as arena memory frees
+ * up.  A request is staged with its reads packed to 2 bits; each step's gather
+ * kernels read its chunks from the arena in place and its scatter kernels write
+ * the results back there, so device memory holds only the references and the
+ * step buffers.  Each step runs the batched
  * pipeline (sw_align_batch_ctx) and the Score Tracker reduction, and a request's
  * results are bit-identical to sw_align_batch + sw_reduce_best on the request
  * alone.  The paper's V2 streams reads and their CALs from host threads to the
@@ -378,8 +382,8 @@ typedef struct sw_server sw_server_t;
 typedef struct {
   int32_t device;
   sw_scoring_t scoring;     /* scoring of every request (max_read_len bounds the reads) */
-  size_t memory_budget;     /* device bytes for admitted requests (>= 1 MiB); a pinned host
-                               mirror of the same size is allocated */
+  size_t memory_budget;     /* bytes of the pinned, device-mapped staging arena for admitted
+                               requests' inputs and outputs (>= 1 MiB) */
   int32_t max_step_reads;   /* reads per device step; also the largest request in reads */
   int64_t max_step_cals;    /* CALs per device step; also the most CALs of one read */
   int32_t max_step_chunks;  /* request chunks per step, 1..4096 */
@@ -418,7 +422,7 @@ int sw_server_submit(sw_server_t *srv, const uint8_t *read_codes, int64_t n_code
                      int32_t *n_tied, int64_t *req_id);
 /* Wait up to timeout_ms (-1: forever) for a request; *done = 1 when complete. */
 int sw_server_wait(sw_server_t *srv, int64_t req_id, int32_t timeout_ms, int32_t *done);
-/* State (0 pending, 1 admitted, 2 draining, 3 done) and steady-clock times in seconds. */
+/* State (0 pending, 1 admitted, 3 done) and steady-clock times in seconds. */
 int sw_server_request_info(sw_server_t *srv, int64_t req_id, int32_t *state, double *t_submit, double *t_admit,
                            double *t_done);
 /* Forget a completed request. */

@@ -1,13 +1,16 @@
-// Served execution: resident references, admission by device-memory footprint,
+// Served execution: resident references, admission by staging-memory footprint,
 // continuous batching of admitted requests into device steps, and per-request
 // timestamps for latency.  Contracts are in include/sw_align.h.
 //
 // The paper's V2 host keeps the reference resident on the accelerator and
 // streams each read followed by its CALs to it, with separate threads feeding
-// and draining the device (sections 4.2 and 4.3).  Here one scheduler thread
-// plays those roles: it admits requests into a device arena, packs chunks of
-// every admitted request into each device step, and drains finished requests,
-// so requests that arrive while a step runs join the next one.
+// and draining the device (sections 4.2 and 4.3).  Here a request is staged
+// (reads packed to 2 bits) in a pinned arena that the device maps; one
+// scheduler thread packs chunks of every admitted request into each device
+// step, whose gather kernels read the chunks straight from the mapped arena
+// and whose scatter kernels write the results straight back, so a request
+// costs no device copy or kernel of its own and requests that arrive while a
+// step runs join the next one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,7 +85,7 @@ class Arena {
 enum ReqState { RS_PENDING = 0, RS_ADMITTED = 1, RS_DRAINING = 2, RS_DONE = 3, RS_FAILED = 4 };
 
 struct Layout {  // byte offsets of one request's arrays inside its arena block
-  size_t codes, words, word_off, len, cal_ptr, cal_pos, cal_ref, strand;
+  size_t words, word_off, len, cal_ptr, cal_pos, cal_ref, strand;
   size_t score, ref_end, read_end, best_score, best_slot, n_tied;
   size_t in_end, total;
 };
@@ -109,12 +112,11 @@ struct Request {
   int64_t next_read = 0;  // first read not yet placed in a step
   int64_t reads_done = 0;
   int state = RS_PENDING;
-  bool staged = false;  // inputs already copied into the pinned mirror at `off`
+  bool staged = false;  // inputs already staged in the pinned arena at `off`
   double t_submit = 0, t_admit = 0, t_done = 0;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
-struct StepSlot {  // device buffers of one step (two are used alternately)
+struct StepSlot {  // device buffers of one step (the slots are used in turn)
   uint32_t *words = nullptr;
   int64_t *word_off = nullptr, *cal_ptr = nullptr, *cal_pos = nullptr;
   int32_t *read_len = nullptr;
@@ -130,8 +132,11 @@ struct StepSlot {  // device buffers of one step (two are used alternately)
   swk::ServeChunk *chunks_host = nullptr;  // pinned
   void *base = nullptr;
   hipEvent_t done = nullptr;
-  hipStream_t stream = nullptr;  // each slot computes on its own stream with its own context,
-  sw_ctx_t *ctx = nullptr;       // so consecutive steps overlap on the device
+  // All slots share one stream: steps run back to back, and the scheduler can
+  // queue the next steps while one runs.  (On separate streams the small kernels
+  // of one step waited behind the persistent scoring kernel of the next.)
+  hipStream_t stream = nullptr;
+  sw_ctx_t *ctx = nullptr;  // one batched context per slot
   bool busy = false;
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> parts;  // request and reads placed
 };
@@ -148,20 +153,22 @@ struct sw_server {
   sw_refset_t refs{};
   std::vector<int64_t> ref_off, ref_len;
   bool refs_set = false;
-  void *arena_dev = nullptr;
-  uint8_t *arena_host = nullptr;  // pinned mirror of the arena
+  uint8_t *arena_host = nullptr;  // pinned staging arena (requests' inputs and outputs)
+  uint8_t *arena_map = nullptr;   // the same memory as the device addresses it
   std::unique_ptr<Arena> arena;
-  hipStream_t copy = nullptr;
   StepSlot slots[kSlots];
   int next_slot = 0;
   std::deque<std::shared_ptr<Request>> pending;
   std::deque<std::shared_ptr<Request>> admitted;  // admitted, not fully placed in steps
-  std::list<std::shared_ptr<Request>> draining;
   std::deque<StepSlot *> in_flight;
   std::map<int64_t, std::shared_ptr<Request>> all;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_fin;
   std::thread worker;
+  std::thread finisher;                            // copies results out, frees blocks
+  std::deque<std::shared_ptr<Request>> to_finish;  // all reads done, results in the arena
+  int64_t finishing = 0;                           // handed to the finisher, not yet done
+  bool worker_running = false;
   std::atomic<bool> stop{false};
   int64_t next_id = 1;
   int last_error = 0;
@@ -178,7 +185,6 @@ Layout make_layout(int32_t n_reads, int64_t n_cals, int64_t n_codes, int32_t n_r
     o = up256(o + bytes);
     return r;
   };
-  L.codes = put(n_codes);
   L.words = put(sizeof(uint32_t) * ((n_codes + 15) / 16));
   L.word_off = put(sizeof(int64_t) * n_reads);
   L.len = put(sizeof(int32_t) * n_reads);
@@ -198,18 +204,27 @@ Layout make_layout(int32_t n_reads, int64_t n_cals, int64_t n_codes, int32_t n_r
 }
 
 template <class T>
-T *dptr(sw_server *s, const Request &r, size_t field) {
-  return reinterpret_cast<T *>((char *)s->arena_dev + r.off + field);
+T *dptr(sw_server *s, const Request &r, size_t field) {  // device address of an arena field
+  return reinterpret_cast<T *>(s->arena_map + r.off + field);
 }
 template <class T>
 T *hptr(sw_server *s, const Request &r, size_t field) {
   return reinterpret_cast<T *>(s->arena_host + r.off + field);
 }
 
-// Copy a request's inputs into its block of the pinned mirror.
+// Stage a request's inputs in its block of the pinned arena, packing the reads
+// to 2 bits per base (16 bases per word, first base least significant; each
+// read starts on a word, as its code offset is a multiple of 16).
 void stage_inputs(sw_server *s, Request &r, const uint8_t *codes, const int64_t *code_off, const int32_t *len,
                   const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand) {
-  std::memcpy(hptr<uint8_t>(s, r, r.lay.codes), codes, r.n_codes);
+  uint32_t *words = hptr<uint32_t>(s, r, r.lay.words);
+  const int64_t n_words = (r.n_codes + 15) / 16;
+  for (int64_t w = 0; w < n_words; ++w) {
+    const int64_t b0 = 16 * w, nb = std::min<int64_t>(16, r.n_codes - b0);
+    uint32_t v = 0;
+    for (int64_t k = 0; k < nb; ++k) v |= (uint32_t)(codes[b0 + k] & 3u) << (2 * k);
+    words[w] = v;
+  }
   int64_t *wo = hptr<int64_t>(s, r, r.lay.word_off);
   for (int32_t i = 0; i < r.n_reads; ++i) wo[i] = code_off[i] / 16;
   std::memcpy(hptr<int32_t>(s, r, r.lay.len), len, sizeof(int32_t) * r.n_reads);
@@ -220,9 +235,9 @@ void stage_inputs(sw_server *s, Request &r, const uint8_t *codes, const int64_t 
   r.staged = true;
 }
 
-// Admission (scheduler thread, lock held): reserve the footprint if the
-// request did not get it at submit, stage the inputs, upload them and pack the
-// reads on the device.
+// Admission (scheduler thread, lock held): reserve the footprint and stage the
+// inputs if the request did not get its block at submit.  The device reads the
+// staged inputs in place, so admission needs no device work.
 bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
   Request &r = *rq;
   if (!r.staged) {
@@ -232,10 +247,6 @@ bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
     stage_inputs(s, r, r.codes.data(), r.code_off.data(), r.len.data(), r.cal_ptr.data(), r.cal_pos.data(),
                  r.cal_ref.data(), r.strand.data());
   }
-  hipMemcpyAsync((char *)s->arena_dev + r.off, s->arena_host + r.off, r.lay.in_end, hipMemcpyHostToDevice, s->copy);
-  sw_pack_2bit(dptr<uint8_t>(s, r, r.lay.codes), r.n_codes, dptr<uint32_t>(s, r, r.lay.words),
-               (sw_stream_t)s->copy);
-  hipEventRecord(r.ev_in, s->copy);
   r.t_admit = now_s();
   r.state = RS_ADMITTED;
   std::vector<uint8_t>().swap(r.codes);
@@ -292,7 +303,6 @@ bool launch_step(sw_server *s) {
     nc += r.cal_ptr[r1] - r.cal_ptr[r0];
     r.next_read = r1;
     st.parts.emplace_back(rq, r1 - r0);
-    hipStreamWaitEvent(st.stream, r.ev_in, 0);
   }
   (void)words_per_read;
   while (!s->admitted.empty() && s->admitted.front()->next_read >= s->admitted.front()->n_reads)
@@ -324,7 +334,9 @@ bool launch_step(sw_server *s) {
   return true;
 }
 
-// Retire finished steps; start the download of requests whose reads are all done.
+// Retire finished steps (lock held).  A request whose reads are all done has
+// its results in the arena already (written there by the scatter kernels); it
+// goes to the finisher thread, so the scheduler keeps launching steps.
 void retire_steps(sw_server *s) {
   // steps retire in launch order (a request's chunks complete in order)
   while (!s->in_flight.empty() && hipEventQuery(s->in_flight.front()->done) == hipSuccess) {
@@ -334,12 +346,9 @@ void retire_steps(sw_server *s) {
       Request &r = *p.first;
       r.reads_done += p.second;
       if (r.reads_done == r.n_reads) {
-        hipStreamWaitEvent(s->copy, st.done, 0);
-        hipMemcpyAsync(s->arena_host + r.off + r.lay.in_end, (char *)s->arena_dev + r.off + r.lay.in_end,
-                       r.lay.total - r.lay.in_end, hipMemcpyDeviceToHost, s->copy);
-        hipEventRecord(r.ev_out, s->copy);
-        r.state = RS_DRAINING;
-        s->draining.push_back(p.first);
+        s->to_finish.push_back(p.first);
+        s->finishing++;
+        s->cv_fin.notify_one();
       }
     }
     st.parts.clear();
@@ -347,14 +356,21 @@ void retire_steps(sw_server *s) {
   }
 }
 
-void finish_downloads(sw_server *s) {
-  bool any = false;
-  for (auto it = s->draining.begin(); it != s->draining.end();) {
-    Request &r = **it;
-    if (hipEventQuery(r.ev_out) != hipSuccess) {
-      ++it;
-      continue;
-    }
+// Finisher thread: copy the results of finished requests to the callers'
+// buffers (lock not held: the blocks stay reserved until the copies end), then
+// free the blocks and mark the requests done.  Ends once the scheduler has
+// ended and nothing is left to finish.
+void finish_loop(sw_server *s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  std::vector<std::shared_ptr<Request>> done;
+  while (true) {
+    s->cv_fin.wait(lk, [&] { return !s->to_finish.empty() || !s->worker_running; });
+    if (s->to_finish.empty()) break;
+    done.assign(s->to_finish.begin(), s->to_finish.end());
+    s->to_finish.clear();
+    lk.unlock();
+    for (auto &rq : done) {
+    Request &r = *rq;
     std::memcpy(r.o_score, hptr<int32_t>(s, r, r.lay.score), sizeof(int32_t) * 2 * r.n_cals);
     std::memcpy(r.o_ref_end, hptr<int64_t>(s, r, r.lay.ref_end), sizeof(int64_t) * 2 * r.n_cals);
     std::memcpy(r.o_read_end, hptr<int16_t>(s, r, r.lay.read_end), sizeof(int16_t) * 2 * r.n_cals);
@@ -364,13 +380,19 @@ void finish_downloads(sw_server *s) {
       std::memcpy(r.o_best_slot, hptr<int64_t>(s, r, r.lay.best_slot), sizeof(int64_t) * r.n_reads * s->n_refs);
     if (r.o_n_tied)
       std::memcpy(r.o_n_tied, hptr<int32_t>(s, r, r.lay.n_tied), sizeof(int32_t) * r.n_reads * s->n_refs);
-    s->arena->release(r.off, r.lay.total);
-    r.t_done = now_s();
-    r.state = RS_DONE;
-    it = s->draining.erase(it);
-    any = true;
+    }
+    const double t = now_s();
+    lk.lock();
+    for (auto &rq : done) {
+      s->arena->release(rq->off, rq->lay.total);
+      rq->t_done = t;
+      rq->state = RS_DONE;
+      s->finishing--;
+    }
+    done.clear();
+    s->cv_done.notify_all();
+    s->cv_work.notify_one();  // freed blocks may admit waiting requests
   }
-  if (any) s->cv_done.notify_all();
 }
 
 void serve_loop(sw_server *s) {
@@ -385,14 +407,15 @@ void serve_loop(sw_server *s) {
     while (launch_step(s)) {
     }
     retire_steps(s);
-    finish_downloads(s);
-    const bool idle = s->pending.empty() && s->admitted.empty() && s->in_flight.empty() && s->draining.empty();
+    const bool idle = s->pending.empty() && s->admitted.empty() && s->in_flight.empty() && s->finishing == 0;
     if (s->stop && idle) break;
     if (idle)
       s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
     else
       s->cv_work.wait_for(lk, std::chrono::microseconds(50));
   }
+  s->worker_running = false;  // every request is done: the finisher may end
+  s->cv_fin.notify_all();
 }
 
 }  // namespace
@@ -416,12 +439,11 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
   s->sc = opts->scoring;
   s->mode = m;
   s->arena.reset(new Arena(opts->memory_budget));
-  if (hipMalloc(&s->arena_dev, opts->memory_budget) != hipSuccess ||
-      hipHostMalloc((void **)&s->arena_host, opts->memory_budget, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void **)&s->arena_host, opts->memory_budget, hipHostMallocMapped) != hipSuccess) {
     sw_server_destroy(s);
     return SW_ERR_NOMEM;
   }
-  if ((e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking)) != hipSuccess) {
+  if ((e = hipHostGetDevicePointer((void **)&s->arena_map, s->arena_host, 0)) != hipSuccess) {
     sw_server_destroy(s);
     return swapi::hip_fail(e);
   }
@@ -443,7 +465,8 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
         hipHostMalloc((void **)&st.chunks_host, sizeof(swk::ServeChunk) * opts->max_step_chunks,
                       hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) != hipSuccess) {
+        (&st == &s->slots[0] ? hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking)
+                             : (st.stream = s->slots[0].stream, hipSuccess)) != hipSuccess) {  // shared
       sw_server_destroy(s);
       return SW_ERR_NOMEM;
     }
@@ -496,7 +519,9 @@ int sw_server_set_refs(sw_server_t *s, const sw_refset_t *refs) {
   s->refs.n_refs = refs->n_refs;
   s->n_refs = refs->n_refs;
   s->refs_set = true;
+  s->worker_running = true;
   s->worker = std::thread(serve_loop, s);
+  s->finisher = std::thread(finish_loop, s);
   return SW_OK;
 }
 
@@ -555,20 +580,10 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
   r.o_best_slot = best_slot;
   r.o_n_tied = n_tied;
   r.t_submit = t;
-  if (hipEventCreateWithFlags(&r.ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&r.ev_out, hipEventDisableTiming) != hipSuccess) {
-    if (reserved) {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->arena->release(r.off, r.lay.total);
-    }
-    return SW_ERR_NOMEM;
-  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
       if (reserved) s->arena->release(r.off, r.lay.total);
-      hipEventDestroy(r.ev_in);
-      hipEventDestroy(r.ev_out);
       return SW_ERR_STATE;
     }
     r.id = s->next_id++;
@@ -615,8 +630,6 @@ int sw_server_release(sw_server_t *s, int64_t req_id) {
   auto it = s->all.find(req_id);
   if (it == s->all.end()) return SW_ERR_INVALID_ARG;
   if (it->second->state != RS_DONE) return SW_ERR_STATE;
-  hipEventDestroy(it->second->ev_in);
-  hipEventDestroy(it->second->ev_out);
   s->all.erase(it);
   return SW_OK;
 }
@@ -628,7 +641,7 @@ int sw_server_stats(sw_server_t *s, sw_server_stats_t *out) {
   out->step_reads = s->step_reads;
   out->step_cals = s->step_cals;
   out->pending = (int64_t)s->pending.size();
-  out->in_flight_requests = (int64_t)(s->admitted.size() + s->draining.size());
+  out->in_flight_requests = (int64_t)s->admitted.size();
   out->arena_used = (int64_t)s->arena->used();
   out->arena_size = (int64_t)s->arena->size();
   return s->last_error ? s->last_error : SW_OK;
@@ -643,25 +656,19 @@ int sw_server_destroy(sw_server_t *s) {
     }
     s->cv_work.notify_all();
     s->worker.join();  // drains every submitted request first
+    if (s->finisher.joinable()) s->finisher.join();
   }
   hipSetDevice(s->opts.device);
   for (auto &st : s->slots)
     if (st.stream) hipStreamSynchronize(st.stream);
-  if (s->copy) hipStreamSynchronize(s->copy);
-  for (auto &kv : s->all) {
-    if (kv.second->ev_in) hipEventDestroy(kv.second->ev_in);
-    if (kv.second->ev_out) hipEventDestroy(kv.second->ev_out);
-  }
   for (auto &st : s->slots) {
     if (st.ctx) sw_ctx_destroy(st.ctx);
-    if (st.stream) hipStreamDestroy(st.stream);
+    if (st.stream && &st == &s->slots[0]) hipStreamDestroy(st.stream);
     if (st.base) hipFree(st.base);
     if (st.chunks_host) hipHostFree(st.chunks_host);
     if (st.done) hipEventDestroy(st.done);
   }
-  if (s->arena_dev) hipFree(s->arena_dev);
   if (s->arena_host) hipHostFree(s->arena_host);
-  if (s->copy) hipStreamDestroy(s->copy);
   delete s;
   return SW_OK;
 }
