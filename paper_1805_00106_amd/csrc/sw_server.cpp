@@ -137,6 +137,8 @@ struct StepSlot {  // device buffers of one step (the slots are used in turn)
   // of one step waited behind the persistent scoring kernel of the next.)
   hipStream_t stream = nullptr;
   sw_ctx_t *ctx = nullptr;  // one batched context per slot
+  void *small_ws = nullptr;  // workspace of the plain call that small steps use
+  size_t small_ws_bytes = 0;
   bool busy = false;
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> parts;  // request and reads placed
 };
@@ -148,6 +150,8 @@ constexpr int kSlots = 3;
 struct sw_server {
   sw_server_opts_t opts{};
   sw_scoring_t sc{};
+  sw_scoring_t sc_small{};       // the scoring of small steps (kernel choice left to AUTO)
+  int64_t small_step_cals = 0;   // steps up to this many CALs take the plain call
   swapi::ScoreMode mode{};
   int32_t n_refs = 0;
   sw_refset_t refs{};
@@ -313,7 +317,14 @@ bool launch_step(sw_server *s) {
   swk::launch_serve_gather(st.chunks_dev, nch, nr, nc, st.words, st.word_off, st.read_len, st.cal_ptr, st.cal_pos,
                            st.cal_ref, st.strand, cs);
   int rc = SW_OK;
-  if (nc > 0) {
+  if (nc > 0 && nc <= s->small_step_cals) {
+    // a small step: the plain call, whose AUTO kernel choice runs one wavefront
+    // per task (a lane working through a whole long read alone would set the
+    // latency); the outputs are the same
+    rc = sw_align_batch(st.words, st.word_off, st.read_len, (int32_t)nr, &s->refs, st.cal_ptr, st.cal_pos,
+                        st.cal_ref, st.strand, nc, &s->sc_small, st.score, st.ref_end, st.read_end, st.small_ws,
+                        st.small_ws_bytes, (sw_stream_t)cs);
+  } else if (nc > 0) {
     rc = sw_align_batch_ctx(st.ctx, st.words, st.word_off, st.read_len, (int32_t)nr, &s->refs, st.cal_ptr,
                             st.cal_pos, st.cal_ref, st.strand, nc, &s->sc, st.score, st.ref_end, st.read_end,
                             (sw_stream_t)cs);
@@ -438,6 +449,13 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
   s->opts = *opts;
   s->sc = opts->scoring;
   s->mode = m;
+  s->sc_small = opts->scoring;
+  s->sc_small.kernel = SW_KERNEL_AUTO;
+  // the AUTO rule picks one wavefront per task up to 32 tasks (16 CALs) per CU
+  // when int32 is allowed; otherwise small steps stay on the batched path
+  s->small_step_cals = (opts->scoring.precision == SW_PREC_INT16 || opts->scoring.kernel != SW_KERNEL_AUTO)
+                           ? 0
+                           : 16 * (int64_t)swapi::device_cus();
   s->arena.reset(new Arena(opts->memory_budget));
   if (hipHostMalloc((void **)&s->arena_host, opts->memory_budget, hipHostMallocMapped) != hipSuccess) {
     sw_server_destroy(s);
@@ -498,6 +516,13 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
     if (rc) {
       sw_server_destroy(s);
       return rc;
+    }
+    if (s->small_step_cals > 0) {
+      st.small_ws_bytes = sw_workspace_bytes((int32_t)R, s->small_step_cals, &s->sc_small);
+      if (hipMalloc(&st.small_ws, std::max<size_t>(st.small_ws_bytes, 256)) != hipSuccess) {
+        sw_server_destroy(s);
+        return SW_ERR_NOMEM;
+      }
     }
   }
   *out = s;
@@ -663,6 +688,7 @@ int sw_server_destroy(sw_server_t *s) {
     if (st.stream) hipStreamSynchronize(st.stream);
   for (auto &st : s->slots) {
     if (st.ctx) sw_ctx_destroy(st.ctx);
+    if (st.small_ws) hipFree(st.small_ws);
     if (st.stream && &st == &s->slots[0]) hipStreamDestroy(st.stream);
     if (st.base) hipFree(st.base);
     if (st.chunks_host) hipHostFree(st.chunks_host);
