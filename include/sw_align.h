@@ -226,7 +226,8 @@ typedef struct sw_index sw_index_t;
 typedef struct {
   int32_t device;    /* HIP device ordinal */
   int32_t seed_len;  /* 1..32 (the paper's V1 uses 22) */
-  int32_t addr_bits; /* pointer-table address bits, 1..min(2*seed_len, 30); 0: min(2*seed_len, 24) */
+  int32_t addr_bits; /* pointer-table address bits, 1..min(2*seed_len, 30); 0: about log2 of the
+                        number of reference positions (one entry per address on average) */
 } sw_index_opts_t;
 typedef struct {
   int32_t stride;            /* >= 1 */

@@ -62,9 +62,10 @@ struct FindArgs {
 size_t find_temp_bytes(int64_t n_slots);
 // Pass 1: per (read, seed) CAL counts and their exclusive scan (cnt, offs hold
 // n_slots + 1 entries); cal_ptr is filled.  The total is offs[n_slots].
-hipError_t launch_find_count(const FindArgs &A, int64_t *cnt, int64_t *offs, void *temp, size_t temp_bytes,
-                             hipStream_t st);
+// run_lo (n_slots entries) keeps each seed's first CAL-table entry for pass 2.
+hipError_t launch_find_count(const FindArgs &A, int64_t *cnt, int64_t *offs, int64_t *run_lo, void *temp,
+                             size_t temp_bytes, hipStream_t st);
 // Pass 2: writes every CAL (needs offs[n_slots] <= the output capacity).
-hipError_t launch_find_write(const FindArgs &A, const int64_t *offs, hipStream_t st);
+hipError_t launch_find_write(const FindArgs &A, const int64_t *offs, const int64_t *run_lo, hipStream_t st);
 
 }  // namespace swk

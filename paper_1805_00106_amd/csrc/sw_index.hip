@@ -141,7 +141,8 @@ __device__ __forceinline__ SeedSlot seed_slot(const FindArgs &A, int64_t t) {
   return s;
 }
 
-__global__ void k_find_count(const FindArgs A, int64_t n_slots, int64_t *__restrict__ cnt) {
+__global__ void k_find_count(const FindArgs A, int64_t n_slots, int64_t *__restrict__ cnt,
+                             int64_t *__restrict__ run_lo) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t > n_slots) return;
   if (t == n_slots) {
@@ -149,14 +150,14 @@ __global__ void k_find_count(const FindArgs A, int64_t n_slots, int64_t *__restr
     return;
   }
   const SeedSlot s = seed_slot(A, t);
-  int64_t n = 0;
+  int64_t n = 0, lo = 0, hi = 0;
   if (s.live) {
-    int64_t lo, hi;
     find_run(A.ix, s.c.hash, lo, hi);
     n = (hi - lo) * (s.c.palindrome ? 2 : 1);
     if (A.max_cals_per_seed > 0 && n > A.max_cals_per_seed) n = 0;
   }
   cnt[t] = n;
+  run_lo[t] = lo;  // the write pass starts here without searching again
 }
 
 __global__ void k_find_ptr(const FindArgs A, const int64_t *__restrict__ offs) {
@@ -174,15 +175,16 @@ __global__ void k_find_errors(const FindArgs A) {
   if (L < 1 || L > A.max_read_len) atomicAdd(A.err, 1ull);
 }
 
-__global__ void k_find_write(const FindArgs A, int64_t n_slots, const int64_t *__restrict__ offs) {
+__global__ void k_find_write(const FindArgs A, int64_t n_slots, const int64_t *__restrict__ offs,
+                             const int64_t *__restrict__ run_lo) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_slots) return;
   int64_t out = offs[t];
   const int64_t end = offs[t + 1];
   if (out == end) return;
   const SeedSlot s = seed_slot(A, t);
-  int64_t lo, hi;
-  find_run(A.ix, s.c.hash, lo, hi);
+  // the run has (end - out) / (2 if palindrome) entries starting at run_lo[t]
+  const int64_t lo = run_lo[t], hi = lo + (end - out) / (s.c.palindrome ? 2 : 1);
   const int S = A.ix.p.seed_len;
   for (int64_t e = lo; e < hi && out < end; ++e) {
     const uint64_t v = A.ix.val[e];
@@ -243,10 +245,10 @@ size_t find_temp_bytes(int64_t n_slots) {
   return t;
 }
 
-hipError_t launch_find_count(const FindArgs &A, int64_t *cnt, int64_t *offs, void *temp, size_t temp_bytes,
-                             hipStream_t st) {
+hipError_t launch_find_count(const FindArgs &A, int64_t *cnt, int64_t *offs, int64_t *run_lo, void *temp,
+                             size_t temp_bytes, hipStream_t st) {
   const int64_t n_slots = (int64_t)A.n_reads * A.max_seeds;
-  hipLaunchKernelGGL(k_find_count, dim3(blocks(n_slots + 1, 256)), dim3(256), 0, st, A, n_slots, cnt);
+  hipLaunchKernelGGL(k_find_count, dim3(blocks(n_slots + 1, 256)), dim3(256), 0, st, A, n_slots, cnt, run_lo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, cnt, offs, (int)(n_slots + 1), st);
@@ -255,9 +257,10 @@ hipError_t launch_find_count(const FindArgs &A, int64_t *cnt, int64_t *offs, voi
   return hipGetLastError();
 }
 
-hipError_t launch_find_write(const FindArgs &A, const int64_t *offs, hipStream_t st) {
+hipError_t launch_find_write(const FindArgs &A, const int64_t *offs, const int64_t *run_lo, hipStream_t st) {
   const int64_t n_slots = (int64_t)A.n_reads * A.max_seeds;
-  if (n_slots > 0) hipLaunchKernelGGL(k_find_write, dim3(blocks(n_slots, 256)), dim3(256), 0, st, A, n_slots, offs);
+  if (n_slots > 0)
+    hipLaunchKernelGGL(k_find_write, dim3(blocks(n_slots, 256)), dim3(256), 0, st, A, n_slots, offs, run_lo);
   if (A.n_reads > 0) hipLaunchKernelGGL(k_find_errors, dim3(blocks(A.n_reads, 256)), dim3(256), 0, st, A);
   return hipGetLastError();
 }

@@ -21,7 +21,7 @@ struct sw_index {
   int64_t *ref_len = nullptr;  // device [n_refs]
   size_t bytes = 0;
   // CAL finder scratch, grown on demand
-  int64_t *cnt = nullptr, *offs = nullptr;
+  int64_t *cnt = nullptr, *offs = nullptr, *run_lo = nullptr;
   void *temp = nullptr;
   size_t temp_bytes = 0;
   int64_t slots_cap = -1;
@@ -38,6 +38,7 @@ void free_index(sw_index *ix) {
   hipFree(ix->ref_len);
   hipFree(ix->cnt);
   hipFree(ix->offs);
+  hipFree(ix->run_lo);
   hipFree(ix->temp);
   delete ix;
 }
@@ -58,8 +59,8 @@ int sw_index_build(const sw_refset_t *refs, const sw_index_opts_t *opts, sw_inde
   if (!opts || opts->device < 0) return SW_ERR_INVALID_ARG;
   const int S = opts->seed_len;
   if (S < 1 || S > 32) return SW_ERR_INVALID_ARG;
-  const int A = opts->addr_bits == 0 ? std::min(2 * S, 24) : opts->addr_bits;
-  if (A < 1 || A > std::min(2 * S, 30)) return SW_ERR_INVALID_ARG;
+  if (opts->addr_bits != 0 && (opts->addr_bits < 1 || opts->addr_bits > std::min(2 * S, 30)))
+    return SW_ERR_INVALID_ARG;
   swk::RefTable T;
   int rc = swapi::validate_refs(refs, 1, &T);
   if (rc) return rc;
@@ -75,6 +76,12 @@ int sw_index_build(const sw_refset_t *refs, const sw_index_opts_t *opts, sw_inde
   }
   R.occ_off[refs->n_refs] = n;
   if (n > (int64_t)INT32_MAX) return SW_ERR_INVALID_ARG;  // radix sort item count
+  // default: about one CAL-table entry per pointer-table address
+  int A = opts->addr_bits;
+  if (A == 0) {
+    A = 1;
+    while (A < std::min(2 * S, 30) && (1ll << A) < n) ++A;
+  }
   hipError_t e = hipSetDevice(opts->device);
   if (e != hipSuccess) return swapi::hip_fail(e);
   sw_index *ix = new (std::nothrow) sw_index();
@@ -153,15 +160,17 @@ int sw_find_cals(sw_index_t *ix, const uint32_t *reads2bit, const int64_t *read_
     if ((e = hipDeviceSynchronize()) != hipSuccess) return swapi::hip_fail(e);
     hipFree(ix->cnt);
     hipFree(ix->offs);
+    hipFree(ix->run_lo);
     hipFree(ix->temp);
     ix->cnt = nullptr;
     ix->offs = nullptr;
+    ix->run_lo = nullptr;
     ix->temp = nullptr;
     ix->slots_cap = -1;
     const int64_t cap = std::max<int64_t>(n_slots, 1 << 16);
     ix->temp_bytes = swk::find_temp_bytes(cap);
     if (dev_alloc(&ix->cnt, 8 * (size_t)(cap + 1)) || dev_alloc(&ix->offs, 8 * (size_t)(cap + 1)) ||
-        dev_alloc(&ix->temp, ix->temp_bytes))
+        dev_alloc(&ix->run_lo, 8 * (size_t)(cap + 1)) || dev_alloc(&ix->temp, ix->temp_bytes))
       return SW_ERR_NOMEM;
     ix->slots_cap = cap;
   }
@@ -183,7 +192,7 @@ int sw_find_cals(sw_index_t *ix, const uint32_t *reads2bit, const int64_t *read_
   A.cal_ref = cal_ref;
   A.strand = strand;
   A.err = err;
-  e = swk::launch_find_count(A, ix->cnt, ix->offs, ix->temp, ix->temp_bytes, st);
+  e = swk::launch_find_count(A, ix->cnt, ix->offs, ix->run_lo, ix->temp, ix->temp_bytes, st);
   if (e != hipSuccess) return swapi::hip_fail(e);
   int64_t total = 0;
   if ((e = hipMemcpyAsync(&total, ix->offs + n_slots, 8, hipMemcpyDeviceToHost, st)) != hipSuccess)
@@ -191,7 +200,7 @@ int sw_find_cals(sw_index_t *ix, const uint32_t *reads2bit, const int64_t *read_
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return swapi::hip_fail(e);
   *n_cals = total;
   if (total > capacity) return SW_ERR_WORKSPACE;
-  e = swk::launch_find_write(A, ix->offs, st);
+  e = swk::launch_find_write(A, ix->offs, ix->run_lo, st);
   return e == hipSuccess ? SW_OK : swapi::hip_fail(e);
 }
 
