@@ -264,6 +264,7 @@ class Leg:
         torch, sw = self.torch, self.sw
         sc = self.batch.scoring
         res = {}
+        measured = {"int32": sw.alu_peak(32) / 1e12, "final_row_int16": sw.alu_peak(16) / 1e12}
         for name, prec, mode, peak in (("int32", sw.PREC_INT32, sw.MODE_LOCAL, PEAK_INT32_TOPS),
                                        ("final_row_int16", sw.PREC_INT16, sw.MODE_FINAL_ROW, PEAK_INT16_TOPS)):
             scv = sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, prec,
@@ -282,6 +283,8 @@ class Leg:
             gcups = self.cells / (ms * 1e-3) / 1e9
             res[name] = {"ms_per_step": round(ms, 3), "gcups": round(gcups, 1),
                          "roofline_frac": round(OPS_PER_CELL * gcups * 1e9 / (peak * 1e12), 4),
+                         "peak_measured_tops": round(measured[name], 2),
+                         "frac_of_measured": round(OPS_PER_CELL * gcups * 1e9 / (measured[name] * 1e12), 4),
                          "plan": self.ctx.last_plan()}
             if self.parity_reads:
                 res[name]["parity_sample_ok"] = parity_sample(self.batch, out, n=100,
@@ -633,8 +636,11 @@ def main():
     gcups = cells / (step_ms * 1e-3) / 1e9
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
     traffic = load_traffic("inter16_queue", "config2")
+    import paper_1805_00106_amd as sw
+    measured = sw.alu_peak(16) / 1e12  # sustained packed-int16 add/max rate on this device
     roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_INT16_TOPS, 2),
             "unit": "Tops/s (int16 lane-ops)", "frac": round(achieved / PEAK_INT16_TOPS, 4), "traffic": traffic,
+            "peak_measured": round(measured, 2), "frac_of_measured": round(achieved / measured, 4),
             "kernel": "k_inter16_queue", "kernel_ms": round(kern_ms, 3),
             "kernel_gcups": round(cells / (kern_ms * 1e-3) / 1e9, 1),
             "gcups_peak": round(PEAK_INT16_TOPS * 1e12 / OPS_PER_CELL / 1e9, 1)}

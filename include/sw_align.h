@@ -432,6 +432,16 @@ int sw_server_stats(sw_server_t *srv, sw_server_stats_t *out);
 /* Drain every submitted request, then free the server. */
 int sw_server_destroy(sw_server_t *srv);
 
+/* ------------------------------------------------------------------ calibration */
+/*
+ * Sustained integer VALU rate of the current device: every compute unit runs
+ * independent chains of add + max in packed 16-bit (bits = 16; a packed op
+ * counts as two lane-ops) or 32-bit (bits = 32) arithmetic for `iters` steps
+ * (>= 16).  *ops_per_s receives lane-ops per second.  Synchronises the stream;
+ * allocates a small device buffer.
+ */
+int sw_alu_peak(int32_t bits, int64_t iters, double *ops_per_s, sw_stream_t stream);
+
 /* ------------------------------------------------------------------ misc */
 const char *sw_strerror(int code);
 int sw_last_hip_error(void);

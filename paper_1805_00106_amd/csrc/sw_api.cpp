@@ -14,6 +14,10 @@
 #include "sw_launch.h"
 #include "sw_trace.h"
 
+namespace swk {
+hipError_t measure_alu_peak(int bits, int64_t iters, int blocks, uint32_t *out, hipStream_t st, double *ops_per_s);
+}
+
 namespace swapi {
 
 thread_local int g_last_hip = 0;
@@ -502,6 +506,16 @@ int sw_cal_filter(const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t 
   swk::FilterArgs A{cal_ptr, cal_pos, cal_ref, strand, n_reads, n_cals, bucket_bits,
                     out_ptr, out_pos, out_ref, out_strand, cal_map};
   hipError_t e = swk::launch_filter(A, workspace, workspace_bytes, (hipStream_t)stream);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+int sw_alu_peak(int32_t bits, int64_t iters, double *ops_per_s, sw_stream_t stream) {
+  if ((bits != 16 && bits != 32) || iters < 16 || !ops_per_s) return SW_ERR_INVALID_ARG;
+  const int blocks = 8 * device_cus();  // 8 waves of 64 lanes per SIMD pair: every SIMD kept issuing
+  uint32_t *out = nullptr;
+  if (hipMalloc(&out, sizeof(uint32_t) * 256 * (size_t)blocks) != hipSuccess) return SW_ERR_NOMEM;
+  hipError_t e = swk::measure_alu_peak(bits, iters, blocks, out, (hipStream_t)stream, ops_per_s);
+  hipFree(out);
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 

@@ -154,3 +154,11 @@ def test_cal_filter_validation(sw):
     assert call(1, 1, 0, None, 0) == -5
     assert call(10, 1, 0, p, 8) == -5
     assert L.sw_cal_filter_workspace_bytes(1000) >= 8 * 1001
+
+
+def test_alu_peak_validation(sw):
+    L = sw.lib()
+    v = ctypes.c_double()
+    assert L.sw_alu_peak(8, 1 << 10, ctypes.byref(v), None) == -1
+    assert L.sw_alu_peak(16, 4, ctypes.byref(v), None) == -1
+    assert L.sw_alu_peak(32, 1 << 10, None, None) == -1

@@ -86,3 +86,12 @@ def test_topk_many_ties_and_invalid_slots():
     assert errs > 0
     got = gpu_align(b, sw.PREC_INT16, topk=4)
     assert_same(got, exp, "top-4 with ties and invalid slots")
+
+
+def test_alu_peak_is_plausible():
+    """The calibration kernel's sustained rate is positive and below the
+    published peak (256 CUs x 64 lanes x 2.4 GHz, x2 for packed 16-bit)."""
+    p16 = sw.alu_peak(16, 1 << 14)
+    p32 = sw.alu_peak(32, 1 << 14)
+    assert 0.2 * 7.864e13 < p16 <= 1.02 * 7.864e13
+    assert 0.2 * 3.932e13 < p32 <= 1.02 * 3.932e13
