@@ -147,7 +147,12 @@ def _check(rc: int, where: str):
 
 
 def _ptr(t: Optional[torch.Tensor]):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    if t is None:
+        return None
+    if t.numel() == 0:  # torch reports no address for an empty tensor: use its storage's
+        p = t.untyped_storage().data_ptr()
+        return ctypes.c_void_p(p) if p else None
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream(stream=None):
@@ -215,7 +220,7 @@ class DeviceBatch:
     @classmethod
     def upload(cls, batch, device="cuda", stream=None):
         """From a workloads.Batch (host codes, each read at a 16-aligned offset)."""
-        t = lambda a, dt: torch.from_numpy(a).to(device=device, dtype=dt).contiguous()
+        t = lambda a, dt: _nonnull(torch.from_numpy(a).to(device=device, dtype=dt).contiguous())
         codes = t(batch.read_codes, torch.uint8)
         words = pack_2bit(codes, stream)
         return cls(words, t(batch.read_off // 16, torch.int64), t(batch.read_len, torch.int32),
@@ -227,11 +232,19 @@ def workspace_bytes(n_reads: int, n_cals: int, sc: Scoring) -> int:
     return int(lib().sw_workspace_bytes(n_reads, n_cals, ctypes.byref(sc)))
 
 
+def _nonnull(t: torch.Tensor) -> torch.Tensor:
+    """An empty tensor still gets a storage address: the C ABI rejects null
+    pointers, and nothing is read through the address of an empty array."""
+    if t.numel() > 0:
+        return t
+    return torch.empty(1, dtype=t.dtype, device=t.device)[:0]
+
+
 class Outputs:
     def __init__(self, n_cals, device="cuda"):
-        self.score = torch.empty(2 * n_cals, dtype=torch.int32, device=device)
-        self.ref_end = torch.empty(2 * n_cals, dtype=torch.int64, device=device)
-        self.read_end = torch.empty(2 * n_cals, dtype=torch.int16, device=device)
+        self.score = _nonnull(torch.empty(2 * n_cals, dtype=torch.int32, device=device))
+        self.ref_end = _nonnull(torch.empty(2 * n_cals, dtype=torch.int64, device=device))
+        self.read_end = _nonnull(torch.empty(2 * n_cals, dtype=torch.int16, device=device))
 
 
 def align_batch(db: DeviceBatch, refs: RefSet, sc: Scoring, out: Optional[Outputs] = None,

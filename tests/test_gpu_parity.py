@@ -133,3 +133,29 @@ def test_config3_shape_moderate():
     """Config 3 generator (L uniform 75..250, geometric CAL counts) at 1500 reads."""
     b = wl.config3(n_reads=1500, band=64)
     _case(b, sw.PREC_INT16, max_read_len=250)
+
+
+def test_maximum_read_length_and_wide_band():
+    """Reads up to the library maximum (1024 bp) with band 200 (windows up to 1424
+    columns): int32 on both kernel families; int16's bound does not hold here."""
+    b = wl.random_small_batch(18, n_reads=10, read_len=(900, 1024), ref_len=(3000, 6000), band=200, max_cals=2)
+    _case(b, sw.PREC_INT32, max_read_len=1024)
+    with pytest.raises(sw.SwError):
+        gpu_align(b, sw.PREC_INT16, max_read_len=1024)
+
+
+def test_empty_inputs():
+    """No CALs at all, and reads without CALs: calls succeed and touch nothing."""
+    b = wl.random_small_batch(19, n_reads=5, max_cals=0)
+    assert b.n_cals == 0
+    refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
+    db = sw.DeviceBatch.upload(b)
+    sc = sw.Scoring.make(2, -3, 5, 2, 8, sw.PREC_AUTO, max_read_len=60)
+    out = sw.align_batch(db, refs, sc)
+    assert out.score.numel() == 0
+    bs, bl, nt = sw.reduce_best(db, b.n_refs, out.score)
+    torch.cuda.synchronize()
+    assert (bs.cpu().numpy() == -1).all() and (bl.cpu().numpy() == -1).all() and (nt.cpu().numpy() == 0).all()
+    ctx = sw.Context(5, 1)
+    ctx.align(db, refs, sc, out)
+    ctx.close()
