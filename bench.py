@@ -256,6 +256,40 @@ class Leg:
                 "batched_gcups": g(batched_ms), "plain_equals_batched": same, "aligned_fraction": aligned,
                 "plan": self.ctx.last_plan()}
 
+    def end_to_end(self, steps=3):
+        """Whole-batch rate with the PCIe transfers in the timed region: read codes
+        and CAL arrays uploaded from pinned host memory, the batched path, and every
+        output (slots and per-read best) downloaded to pinned host memory."""
+        torch, sw, db, b = self.torch, self.sw, self.db, self.batch
+        pin = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).pin_memory()
+        ups = [(pin(b.read_codes, torch.uint8), self.read_codes), (pin(b.read_off // 16, torch.int64), db.read_word_off),
+               (pin(b.read_len, torch.int32), db.read_len), (pin(b.cal_ptr, torch.int64), db.cal_ptr),
+               (pin(b.cal_pos, torch.int64), db.cal_pos), (pin(b.cal_ref, torch.int16), db.cal_ref),
+               (pin(b.strand, torch.uint8), db.strand)]
+        downs = [(torch.empty_like(t, device="cpu").pin_memory(), t)
+                 for t in (self.out.score, self.out.ref_end, self.out.read_end, self.bs, self.bl, self.nt)]
+        nbytes = sum(h.numel() * h.element_size() for h, _ in ups + downs)
+
+        def step():
+            with torch.cuda.stream(self.stream):
+                for h, d in ups:
+                    d.copy_(h, non_blocking=True)
+            self.step(True)
+            with torch.cuda.stream(self.stream):
+                for h, d in downs:
+                    h.copy_(d, non_blocking=True)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        return {"ms_per_step": round(ms, 3), "reads_per_s": round(db.n_reads / (ms * 1e-3), 1),
+                "gcups": round(self.cells / (ms * 1e-3) / 1e9, 1), "pcie_bytes_per_step": nbytes,
+                "note": "inputs from and outputs to pinned host memory inside the timed region"}
+
     def variants(self, steps=5):
         """The same resident config-2 batch on the batched path with other
         scorings: int32 values (one strand per lane, the precision config 1
@@ -438,6 +472,16 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD):
     cls = cls_t.cpu().numpy()
     truth = b.true_ref
     frac = lambda m: round(float(np.mean(m)), 5)
+    # the threshold against the scores decoy CALs reach (uniform positions, no homology) and
+    # the scores of the planted loci: T must sit above the first and below the second
+    score = leg.out.score.cpu().numpy().reshape(-1, 2).max(axis=1)
+    r_of = np.repeat(np.arange(b.n_reads), np.diff(b.cal_ptr))
+    best_decoy = np.full(b.n_reads, -1, np.int64)
+    best_true = np.full(b.n_reads, -1, np.int64)
+    dmask = b.cal_decoy.astype(bool)
+    np.maximum.at(best_decoy, r_of[dmask], score[dmask])
+    np.maximum.at(best_true, r_of[~dmask], score[~dmask])
+    pct = lambda a, q: int(np.percentile(a, q))
     out = {"workload": f"config4: A = {int(b.ref_len[0]):,} bp random, B = A + 15% substitutions + 2%/base indels "
                        f"({int(b.ref_len[1]):,} bp); {b.n_reads:,} reads of 150 bp, 70% from B / 30% from A, "
                        "1% substitutions; homologous locus + Poisson(2) decoys per reference; band 32; both strands",
@@ -448,6 +492,10 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD):
            "tie": frac(cls == -2), "unaligned": frac(cls == -1),
            "by_source": {src: {"correct": frac(cls[truth == k] == k), "tie": frac(cls[truth == k] == -2),
                                "unaligned": frac(cls[truth == k] == -1)} for k, src in ((0, "A"), (1, "B"))},
+           "decoy_best_score": {"p50": pct(best_decoy, 50), "p99": pct(best_decoy, 99),
+                                "p99.9": pct(best_decoy, 99.9), "max": int(best_decoy.max()),
+                                "reads_at_or_above_threshold": frac(best_decoy >= threshold)},
+           "homologous_best_score": {"p0.1": pct(best_true, 0.1), "p1": pct(best_true, 1), "p50": pct(best_true, 50)},
            "gen_s": round(t_gen, 1)}
     leg.free()
     return out
@@ -595,6 +643,7 @@ def main():
     r2 = leg.run()
     parity = None if args.no_parity else parity_sample(batch, leg.out)
     leg.parity_reads = not args.no_parity
+    e2e = leg.end_to_end()
     variants = leg.variants() if args.variants else None
     trace = leg.traceback(parity_reads=0 if args.no_parity else 200)
     pipe = leg.pipeline() if args.pipeline else None
@@ -658,6 +707,7 @@ def main():
                   "kernel_ms": round(r2["plain_kern_ms"], 3)},
         "plain_equals_batched": r2["plain_equals_batched"],
         "small_batch_latency": small,
+        "end_to_end_with_pcie": e2e,
         "variants": variants,
         "config1": config1_leg() if args.variants else None,
         "traceback": trace,

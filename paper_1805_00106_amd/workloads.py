@@ -79,6 +79,8 @@ class Batch:
     true_pos: Optional[np.ndarray] = None
     true_strand: Optional[np.ndarray] = None
     name: str = ""
+    # per CAL: 1 if it was drawn as a decoy (uniform position), when the generator knows
+    cal_decoy: Optional[np.ndarray] = None
 
     @property
     def n_reads(self) -> int:
@@ -117,7 +119,8 @@ class Batch:
         pick = (lambda a: None if a is None else a[idx])
         return Batch(self.ref_codes, self.ref_off, self.ref_len, codes, offs, lens.astype(np.int32),
                      ptr, self.cal_pos[sel], self.cal_ref[sel], self.strand[sel], self.scoring,
-                     pick(self.true_ref), pick(self.true_pos), pick(self.true_strand), self.name)
+                     pick(self.true_ref), pick(self.true_pos), pick(self.true_strand), self.name,
+                     None if self.cal_decoy is None else self.cal_decoy[sel])
 
 
 def aligned_offsets(lengths: np.ndarray, align: int = 16):
@@ -485,10 +488,13 @@ def config4(n_reads: int = 4_000_000, ref_len: int = 500_000_000, read_len: int 
     lim = np.where(cal_ref == 0, ref_len, len(B))
     cal_pos[dec] = (gr["cals"].random(int(dec.sum())) * lim[dec]).astype(np.int64)
     strand = np.full(total, 3, dtype=np.int64)
-    cal_pos, cal_ref, strand = _shuffle_rows(gr["cals"], counts, cal_pos, cal_ref, strand)
+    cal_pos, cal_ref, strand, decoy = _shuffle_rows(gr["cals"], counts, cal_pos, cal_ref, strand,
+                                                    dec.astype(np.uint8))
     sc = Scoring(2, -3, 5, 2, 32)
-    return _vector_batch([A, B], mat, lens, counts, cal_pos, cal_ref, strand, sc,
-                         from_b.astype(np.int64), src_pos, rev.astype(np.int64), "config4")
+    b = _vector_batch([A, B], mat, lens, counts, cal_pos, cal_ref, strand, sc,
+                      from_b.astype(np.int64), src_pos, rev.astype(np.int64), "config4")
+    b.cal_decoy = decoy
+    return b
 
 
 def random_small_batch(seed: int, n_refs: int = 2, ref_len=(40, 400), n_reads: int = 50,
