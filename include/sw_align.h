@@ -421,12 +421,15 @@ int sw_server_submit(sw_server_t *srv, const uint8_t *read_codes, int64_t n_code
                      const int16_t *cal_ref, const uint8_t *strand, int64_t n_cals, int32_t *score,
                      int64_t *ref_end, int16_t *read_end, int32_t *best_score, int64_t *best_slot,
                      int32_t *n_tied, int64_t *req_id);
-/* Wait up to timeout_ms (-1: forever) for a request; *done = 1 when complete. */
+/* Wait up to timeout_ms (-1: forever) for a request; *done = 1 when it has
+ * finished.  Returns the error of a failed request (a library call of a step
+ * that held some of its reads failed; its output buffers are left untouched),
+ * else SW_OK. */
 int sw_server_wait(sw_server_t *srv, int64_t req_id, int32_t timeout_ms, int32_t *done);
-/* State (0 pending, 1 admitted, 3 done) and steady-clock times in seconds. */
+/* State (0 pending, 1 admitted, 3 done, 4 failed) and steady-clock times in seconds. */
 int sw_server_request_info(sw_server_t *srv, int64_t req_id, int32_t *state, double *t_submit, double *t_admit,
                            double *t_done);
-/* Forget a completed request. */
+/* Forget a finished (done or failed) request. */
 int sw_server_release(sw_server_t *srv, int64_t req_id);
 int sw_server_stats(sw_server_t *srv, sw_server_stats_t *out);
 /* Drain every submitted request, then free the server. */

@@ -82,7 +82,7 @@ class Arena {
   std::map<size_t, size_t> free_;
 };
 
-enum ReqState { RS_PENDING = 0, RS_ADMITTED = 1, RS_DRAINING = 2, RS_DONE = 3, RS_FAILED = 4 };
+enum ReqState { RS_PENDING = 0, RS_ADMITTED = 1, RS_DONE = 3, RS_FAILED = 4 };
 
 struct Layout {  // byte offsets of one request's arrays inside its arena block
   size_t words, word_off, len, cal_ptr, cal_pos, cal_ref, strand;
@@ -112,6 +112,7 @@ struct Request {
   int64_t next_read = 0;  // first read not yet placed in a step
   int64_t reads_done = 0;
   int state = RS_PENDING;
+  int error = 0;        // first error of a step holding some of its reads
   bool staged = false;  // inputs already staged in the pinned arena at `off`
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
@@ -140,6 +141,7 @@ struct StepSlot {  // device buffers of one step (the slots are used in turn)
   void *small_ws = nullptr;  // workspace of the plain call that small steps use
   size_t small_ws_bytes = 0;
   bool busy = false;
+  int error = 0;  // error of the step's library calls, passed to its requests
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> parts;  // request and reads placed
 };
 
@@ -332,6 +334,7 @@ bool launch_step(sw_server *s) {
   if (rc == SW_OK)
     rc = sw_reduce_best(st.cal_ptr, st.cal_ref, (int32_t)nr, s->n_refs, st.score, st.best_score, st.best_slot,
                         st.n_tied, (sw_stream_t)cs);
+  st.error = rc;
   if (rc != SW_OK) s->last_error = rc;
   swk::launch_serve_scatter(st.chunks_dev, nch, nr, nc, s->n_refs, st.score, st.ref_end, st.read_end, st.best_score,
                             st.best_slot, st.n_tied, cs);
@@ -356,6 +359,7 @@ void retire_steps(sw_server *s) {
     for (auto &p : st.parts) {
       Request &r = *p.first;
       r.reads_done += p.second;
+      if (st.error && !r.error) r.error = st.error;
       if (r.reads_done == r.n_reads) {
         s->to_finish.push_back(p.first);
         s->finishing++;
@@ -382,6 +386,7 @@ void finish_loop(sw_server *s) {
     lk.unlock();
     for (auto &rq : done) {
     Request &r = *rq;
+    if (r.error) continue;  // failed: the caller's buffers are left as they were
     std::memcpy(r.o_score, hptr<int32_t>(s, r, r.lay.score), sizeof(int32_t) * 2 * r.n_cals);
     std::memcpy(r.o_ref_end, hptr<int64_t>(s, r, r.lay.ref_end), sizeof(int64_t) * 2 * r.n_cals);
     std::memcpy(r.o_read_end, hptr<int16_t>(s, r, r.lay.read_end), sizeof(int16_t) * 2 * r.n_cals);
@@ -397,7 +402,7 @@ void finish_loop(sw_server *s) {
     for (auto &rq : done) {
       s->arena->release(rq->off, rq->lay.total);
       rq->t_done = t;
-      rq->state = RS_DONE;
+      rq->state = rq->error ? RS_FAILED : RS_DONE;
       s->finishing--;
     }
     done.clear();
@@ -626,13 +631,13 @@ int sw_server_wait(sw_server_t *s, int64_t req_id, int32_t timeout_ms, int32_t *
   auto it = s->all.find(req_id);
   if (it == s->all.end()) return SW_ERR_INVALID_ARG;
   auto rq = it->second;
-  auto pred = [&] { return rq->state == RS_DONE; };
+  auto pred = [&] { return rq->state == RS_DONE || rq->state == RS_FAILED; };
   if (timeout_ms < 0)
     s->cv_done.wait(lk, pred);
   else
     s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred);
-  *done = rq->state == RS_DONE;
-  return s->last_error ? s->last_error : SW_OK;
+  *done = pred() ? 1 : 0;
+  return rq->state == RS_FAILED ? rq->error : SW_OK;
 }
 
 int sw_server_request_info(sw_server_t *s, int64_t req_id, int32_t *state, double *t_submit, double *t_admit,
@@ -654,7 +659,7 @@ int sw_server_release(sw_server_t *s, int64_t req_id) {
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->all.find(req_id);
   if (it == s->all.end()) return SW_ERR_INVALID_ARG;
-  if (it->second->state != RS_DONE) return SW_ERR_STATE;
+  if (it->second->state != RS_DONE && it->second->state != RS_FAILED) return SW_ERR_STATE;
   s->all.erase(it);
   return SW_OK;
 }
