@@ -485,8 +485,9 @@ class Request:
 
 
 class Server:
-    """Served scoring (sw_server_*): resident references, admission by device
-    memory, continuous batching of admitted requests, per-request timestamps."""
+    """Served scoring (sw_server_*): resident references, admission by the
+    footprint in a pinned device-mapped staging arena, continuous batching of
+    admitted requests, per-request timestamps."""
 
     def __init__(self, scoring: Scoring, memory_budget: int = 1 << 30, max_step_reads: int = 65536,
                  max_step_cals: int = 1 << 20, max_step_chunks: int = 512, device: int = 0, autotune: bool = False):

@@ -593,7 +593,7 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
     if (s->pending.empty()) reserved = s->arena->alloc(r.lay.total, &r.off);
   }
   if (reserved) {
-    // the caller's thread stages its own inputs into the pinned mirror
+    // the caller's thread stages its own inputs (reads packed) into the pinned arena
     stage_inputs(s, r, read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref, strand);
   } else {
     r.codes.assign(read_codes, read_codes + n_codes);
