@@ -611,6 +611,11 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
             "gen_s": round(t_gen, 1)}
 
 
+def progress(msg):
+    """One line per finished leg on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -649,12 +654,16 @@ def main():
     t_gen = time.perf_counter() - t_gen
     leg = Leg(batch, int(batch.read_len.max()), args.steps, args.warmup)
     r2 = leg.run()
+    progress(f"config2: batched {r2['batched_gcups']} GCUPS, plain {r2['plain_gcups']} GCUPS")
     parity = None if args.no_parity else parity_sample(batch, leg.out)
     leg.parity_reads = not args.no_parity
     e2e = leg.end_to_end()
     variants = leg.variants() if args.variants else None
+    progress("variants done")
     trace = leg.traceback(parity_reads=0 if args.no_parity else 200)
+    progress("traceback done")
     pipe = leg.pipeline() if args.pipeline else None
+    progress("seed-to-score done")
     small = small_batch_latency(batch)
     n_reads, n_cals, cells = leg.db.n_reads, leg.db.n_cals, leg.cells
     leg.free()
@@ -679,15 +688,19 @@ def main():
               "cals": b3.n_cals, "cells": leg3.cells,
               "plain_gcups": r3["plain_gcups"], "batched_gcups": r3["batched_gcups"],
               "plain_ms_per_step": round(r3["plain_ms"], 3), "batched_ms_per_step": round(r3["batched_ms"], 3),
+              "plain_reads_per_s": round(b3.n_reads / (r3["plain_ms"] * 1e-3), 1),
               "batched_reads_per_s": round(b3.n_reads / (r3["batched_ms"] * 1e-3), 1),
               "speedup_batched_vs_plain": round(r3["plain_ms"] / r3["batched_ms"], 3),
               "plain_equals_batched": r3["plain_equals_batched"], "parity_sample_ok": p3, "plan": r3["plan"]}
         leg3.free()
         del leg3
+        progress(f"config3: batched {r3['batched_gcups']} GCUPS")
 
     c4 = classification_leg(args.config4_reads) if args.config4_reads else None
+    progress("config4 done")
     served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests,
                         step_cals=args.serve_step_cals) if args.serve_scale > 0 else None
+    progress("served done")
 
     step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
     gcups = cells / (step_ms * 1e-3) / 1e9
