@@ -367,10 +367,12 @@ const char *sw_ctx_last_plan(sw_ctx_t *ctx);
  * in a pinned staging arena that the device maps, and packs chunks of every
  * admitted request into each device step (continuous batching): a request that
  * arrives while a step runs joins the next step as soon as arena memory frees
- * up.  A request is staged with its reads packed to 2 bits; each step's gather
- * kernels read its chunks from the arena in place and its scatter kernels write
- * the results back there, so device memory holds only the references and the
- * step buffers.  Each step runs the batched
+ * up.  A request is staged with its reads packed to 2 bits in a coherent arena;
+ * each step's gather kernels read its chunks from the arena in place and its
+ * scatter kernels write the results back there, so device memory holds only the
+ * references and the step buffers.  The step's read lengths, word offsets and
+ * CAL row pointers come from the server's host copies, so no device address is
+ * ever formed from staged bytes.  Each step runs the batched
  * pipeline (sw_align_batch_ctx) and the Score Tracker reduction, and a request's
  * results are bit-identical to sw_align_batch + sw_reduce_best on the request
  * alone.  The paper's V2 streams reads and their CALs from host threads to the
@@ -404,8 +406,9 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out);
 int sw_server_set_refs(sw_server_t *srv, const sw_refset_t *refs);
 /*
  * Submit one request (host arrays, copied before the call returns):
- *   read_codes     host uint8 [n_codes], base codes; read r starts at
- *                  read_code_off[r], a multiple of 16
+ *   read_codes     host uint8 [n_codes], base codes; read r is
+ *                  read_codes[read_code_off[r] .. read_code_off[r] + read_len[r])
+ *                  (any layout: the server packs the reads back to back)
  *   read_len       host [n_reads], 0..scoring.max_read_len
  *   cal_ptr        host [n_reads+1] CSR (cal_ptr[0] = 0, cal_ptr[n_reads] = n_cals)
  *   cal_pos, cal_ref, strand: host [n_cals], as for sw_align_batch

@@ -5,12 +5,15 @@
 // The paper's V2 host keeps the reference resident on the accelerator and
 // streams each read followed by its CALs to it, with separate threads feeding
 // and draining the device (sections 4.2 and 4.3).  Here a request is staged
-// (reads packed to 2 bits) in a pinned arena that the device maps; one
-// scheduler thread packs chunks of every admitted request into each device
-// step, whose gather kernels read the chunks straight from the mapped arena
-// and whose scatter kernels write the results straight back, so a request
-// costs no device copy or kernel of its own and requests that arrive while a
-// step runs join the next one.
+// (reads packed to 2 bits, back to back) in a pinned, coherent arena that the
+// device maps; one scheduler thread packs chunks of every admitted request
+// into each device step, whose gather kernels read the chunks straight from
+// the mapped arena and whose scatter kernels write the results straight back,
+// so a request costs no device copy or kernel of its own and requests that
+// arrive while a step runs join the next one.  The step's per-read arrays
+// (lengths, word offsets, CAL row pointers) are built by the scheduler from its
+// host copies and sent with the chunk descriptors in one transfer: no device
+// address is formed from bytes read out of the arena.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,7 +88,7 @@ class Arena {
 enum ReqState { RS_PENDING = 0, RS_ADMITTED = 1, RS_DONE = 3, RS_FAILED = 4 };
 
 struct Layout {  // byte offsets of one request's arrays inside its arena block
-  size_t words, word_off, len, cal_ptr, cal_pos, cal_ref, strand;
+  size_t words, cal_pos, cal_ref, strand;
   size_t score, ref_end, read_end, best_score, best_slot, n_tied;
   size_t in_end, total;
 };
@@ -93,10 +96,12 @@ struct Layout {  // byte offsets of one request's arrays inside its arena block
 struct Request {
   int64_t id = 0;
   int32_t n_reads = 0;
-  int64_t n_cals = 0, n_codes = 0, n_words = 0;
-  // host copies of the inputs (the caller may reuse its buffers after submit)
+  int64_t n_cals = 0, n_codes = 0;
+  // host copies of the inputs (the caller may reuse its buffers after submit);
+  // codes, code_off and the CAL arrays are dropped once staged
   std::vector<uint8_t> codes;
   std::vector<int64_t> code_off, cal_ptr, cal_pos;
+  std::vector<int64_t> wptr;  // [n_reads + 1] first packed word of each read in the staged words
   std::vector<int32_t> len;
   std::vector<int16_t> cal_ref;
   std::vector<uint8_t> strand;
@@ -119,8 +124,7 @@ struct Request {
 
 struct StepSlot {  // device buffers of one step (the slots are used in turn)
   uint32_t *words = nullptr;
-  int64_t *word_off = nullptr, *cal_ptr = nullptr, *cal_pos = nullptr;
-  int32_t *read_len = nullptr;
+  int64_t *cal_pos = nullptr;
   int16_t *cal_ref = nullptr;
   uint8_t *strand = nullptr;
   int32_t *score = nullptr;
@@ -129,8 +133,10 @@ struct StepSlot {  // device buffers of one step (the slots are used in turn)
   int32_t *best_score = nullptr;
   int64_t *best_slot = nullptr;
   int32_t *n_tied = nullptr;
-  swk::ServeChunk *chunks_dev = nullptr;
-  swk::ServeChunk *chunks_host = nullptr;  // pinned
+  // per-step header (read lengths, word offsets, CAL row pointers, chunk
+  // descriptors), built on the host in pinned memory and copied in one transfer
+  char *hdr_host = nullptr;
+  char *hdr_dev = nullptr;
   void *base = nullptr;
   hipEvent_t done = nullptr;
   // All slots share one stream: steps run back to back, and the scheduler can
@@ -143,7 +149,30 @@ struct StepSlot {  // device buffers of one step (the slots are used in turn)
   bool busy = false;
   int error = 0;  // error of the step's library calls, passed to its requests
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> parts;  // request and reads placed
+  std::vector<int64_t> part_r0;                                      // first read of each part
 };
+
+// Byte offsets of one step's header: read lengths, word offsets and CAL row
+// pointers of the step's reads, then the chunk descriptors.
+struct StepHeader {
+  size_t len, word_off, cal_ptr, chunks, bytes;
+};
+
+StepHeader header_layout(int64_t n_reads, int64_t n_chunks) {
+  StepHeader h{};
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t r = o;
+    o = up256(o + bytes);
+    return r;
+  };
+  h.len = put(sizeof(int32_t) * n_reads);
+  h.word_off = put(sizeof(int64_t) * n_reads);
+  h.cal_ptr = put(sizeof(int64_t) * (n_reads + 1));
+  h.chunks = put(sizeof(swk::ServeChunk) * n_chunks);
+  h.bytes = o;
+  return h;
+}
 
 constexpr int kSlots = 3;
 
@@ -183,7 +212,7 @@ struct sw_server {
 
 namespace {
 
-Layout make_layout(int32_t n_reads, int64_t n_cals, int64_t n_codes, int32_t n_refs) {
+Layout make_layout(int32_t n_reads, int64_t n_cals, int64_t n_words, int32_t n_refs) {
   Layout L{};
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -191,10 +220,7 @@ Layout make_layout(int32_t n_reads, int64_t n_cals, int64_t n_codes, int32_t n_r
     o = up256(o + bytes);
     return r;
   };
-  L.words = put(sizeof(uint32_t) * ((n_codes + 15) / 16));
-  L.word_off = put(sizeof(int64_t) * n_reads);
-  L.len = put(sizeof(int32_t) * n_reads);
-  L.cal_ptr = put(sizeof(int64_t) * (n_reads + 1));
+  L.words = put(sizeof(uint32_t) * n_words);
   L.cal_pos = put(sizeof(int64_t) * n_cals);
   L.cal_ref = put(sizeof(int16_t) * n_cals);
   L.strand = put(n_cals);
@@ -219,25 +245,27 @@ T *hptr(sw_server *s, const Request &r, size_t field) {
 }
 
 // Stage a request's inputs in its block of the pinned arena, packing the reads
-// to 2 bits per base (16 bases per word, first base least significant; each
-// read starts on a word, as its code offset is a multiple of 16).
-void stage_inputs(sw_server *s, Request &r, const uint8_t *codes, const int64_t *code_off, const int32_t *len,
-                  const int64_t *cal_ptr, const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand) {
+// to 2 bits per base (16 bases per word, first base least significant), each
+// read from its own code offset into the words from r.wptr[i] on: back to back,
+// whatever the caller's layout.
+void stage_inputs(sw_server *s, Request &r, const uint8_t *codes, const int64_t *code_off, const int64_t *cal_pos,
+                  const int16_t *cal_ref, const uint8_t *strand) {
   uint32_t *words = hptr<uint32_t>(s, r, r.lay.words);
-  const int64_t n_words = (r.n_codes + 15) / 16;
-  for (int64_t w = 0; w < n_words; ++w) {
-    const int64_t b0 = 16 * w, nb = std::min<int64_t>(16, r.n_codes - b0);
-    uint32_t v = 0;
-    for (int64_t k = 0; k < nb; ++k) v |= (uint32_t)(codes[b0 + k] & 3u) << (2 * k);
-    words[w] = v;
+  for (int32_t i = 0; i < r.n_reads; ++i) {
+    const uint8_t *q = codes + code_off[i];
+    const int32_t L = r.len[i];
+    for (int64_t w = 0; w < r.wptr[i + 1] - r.wptr[i]; ++w) {
+      const int nb = (int)std::min<int64_t>(16, L - 16 * w);
+      uint32_t v = 0;
+      for (int k = 0; k < nb; ++k) v |= (uint32_t)(q[16 * w + k] & 3u) << (2 * k);
+      words[r.wptr[i] + w] = v;
+    }
   }
-  int64_t *wo = hptr<int64_t>(s, r, r.lay.word_off);
-  for (int32_t i = 0; i < r.n_reads; ++i) wo[i] = code_off[i] / 16;
-  std::memcpy(hptr<int32_t>(s, r, r.lay.len), len, sizeof(int32_t) * r.n_reads);
-  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_ptr), cal_ptr, sizeof(int64_t) * (r.n_reads + 1));
-  std::memcpy(hptr<int64_t>(s, r, r.lay.cal_pos), cal_pos, sizeof(int64_t) * r.n_cals);
-  std::memcpy(hptr<int16_t>(s, r, r.lay.cal_ref), cal_ref, sizeof(int16_t) * r.n_cals);
-  std::memcpy(hptr<uint8_t>(s, r, r.lay.strand), strand, r.n_cals);
+  if (r.n_cals > 0) {
+    std::memcpy(hptr<int64_t>(s, r, r.lay.cal_pos), cal_pos, sizeof(int64_t) * r.n_cals);
+    std::memcpy(hptr<int16_t>(s, r, r.lay.cal_ref), cal_ref, sizeof(int16_t) * r.n_cals);
+    std::memcpy(hptr<uint8_t>(s, r, r.lay.strand), strand, r.n_cals);
+  }
   r.staged = true;
 }
 
@@ -250,12 +278,12 @@ bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
     size_t off = 0;
     if (!s->arena->alloc(r.lay.total, &off)) return false;
     r.off = off;
-    stage_inputs(s, r, r.codes.data(), r.code_off.data(), r.len.data(), r.cal_ptr.data(), r.cal_pos.data(),
-                 r.cal_ref.data(), r.strand.data());
+    stage_inputs(s, r, r.codes.data(), r.code_off.data(), r.cal_pos.data(), r.cal_ref.data(), r.strand.data());
   }
   r.t_admit = now_s();
   r.state = RS_ADMITTED;
   std::vector<uint8_t>().swap(r.codes);
+  std::vector<int64_t>().swap(r.code_off);
   std::vector<int64_t>().swap(r.cal_pos);
   std::vector<int16_t>().swap(r.cal_ref);
   std::vector<uint8_t>().swap(r.strand);
@@ -267,77 +295,104 @@ bool launch_step(sw_server *s) {
   StepSlot &st = s->slots[s->next_slot];
   if (st.busy || s->admitted.empty()) return false;
   const int64_t max_reads = s->opts.max_step_reads, max_cals = s->opts.max_step_cals;
-  const int64_t words_per_read = (s->mode.max_read_len + 15) / 16;
+  const int64_t max_words = max_reads * ((s->mode.max_read_len + 15) / 16);
+  // pass 1: which reads of which requests go into the step
   int64_t nr = 0, nc = 0, nw = 0;
-  int nch = 0;
   st.parts.clear();
+  st.part_r0.clear();
   for (auto &rq : s->admitted) {
-    if (nch >= s->opts.max_step_chunks) break;
+    if ((int64_t)st.parts.size() >= s->opts.max_step_chunks) break;
     Request &r = *rq;
-    int64_t r0 = r.next_read, r1 = r0;
+    const int64_t r0 = r.next_read;
+    int64_t r1 = r0;
     // take whole reads while the step has room (a single read always fits an
     // empty step: submit bounds the CALs of one read by the step capacity)
     while (r1 < r.n_reads && nr + (r1 - r0) < max_reads) {
       if (nc + (r.cal_ptr[r1 + 1] - r.cal_ptr[r0]) > max_cals) break;
+      if (nw + (r.wptr[r1 + 1] - r.wptr[r0]) > max_words) break;
       ++r1;
     }
     if (r1 == r0) break;
-    swk::ServeChunk &c = st.chunks_host[nch++];
-    c.words = dptr<uint32_t>(s, r, r.lay.words);
-    c.word_off = dptr<int64_t>(s, r, r.lay.word_off);
-    c.len = dptr<int32_t>(s, r, r.lay.len);
-    c.cal_ptr = dptr<int64_t>(s, r, r.lay.cal_ptr);
-    c.cal_pos = dptr<int64_t>(s, r, r.lay.cal_pos);
-    c.cal_ref = dptr<int16_t>(s, r, r.lay.cal_ref);
-    c.strand = dptr<uint8_t>(s, r, r.lay.strand);
-    c.score = dptr<int32_t>(s, r, r.lay.score);
-    c.ref_end = dptr<int64_t>(s, r, r.lay.ref_end);
-    c.read_end = dptr<int16_t>(s, r, r.lay.read_end);
-    c.best_score = dptr<int32_t>(s, r, r.lay.best_score);
-    c.best_slot = dptr<int64_t>(s, r, r.lay.best_slot);
-    c.n_tied = dptr<int32_t>(s, r, r.lay.n_tied);
-    c.r0 = r0;
-    c.r1 = r1;
-    c.step_r0 = nr;
-    c.step_c0 = nc;
-    c.step_w0 = nw;
-    // the chunk's words are contiguous in the request (16-aligned code offsets)
-    const int64_t w_first = r.code_off[r0] / 16;
-    const int64_t w_last = r.code_off[r1 - 1] / 16 + (r.len[r1 - 1] + 15) / 16;
-    nw += w_last - w_first;
     nr += r1 - r0;
     nc += r.cal_ptr[r1] - r.cal_ptr[r0];
+    nw += r.wptr[r1] - r.wptr[r0];
     r.next_read = r1;
     st.parts.emplace_back(rq, r1 - r0);
+    st.part_r0.push_back(r0);
   }
-  (void)words_per_read;
   while (!s->admitted.empty() && s->admitted.front()->next_read >= s->admitted.front()->n_reads)
     s->admitted.pop_front();
+  const int nch = (int)st.parts.size();
   if (nch == 0) return false;
+  // pass 2: the step header, from the host copies of the requests' read lengths
+  // and CAL rows; every chunk address is offset on the host
+  const StepHeader H = header_layout(nr, nch);
+  int32_t *h_len = reinterpret_cast<int32_t *>(st.hdr_host + H.len);
+  int64_t *h_wo = reinterpret_cast<int64_t *>(st.hdr_host + H.word_off);
+  int64_t *h_cp = reinterpret_cast<int64_t *>(st.hdr_host + H.cal_ptr);
+  swk::ServeChunk *h_ch = reinterpret_cast<swk::ServeChunk *>(st.hdr_host + H.chunks);
+  int64_t sr = 0, sc = 0, sw = 0;
+  for (int k = 0; k < nch; ++k) {
+    Request &r = *st.parts[k].first;
+    const int64_t r0 = st.part_r0[k], r1 = r0 + st.parts[k].second;
+    const int64_t c0 = r.cal_ptr[r0], w0 = r.wptr[r0];
+    for (int64_t i = r0; i < r1; ++i) {
+      h_len[sr + (i - r0)] = r.len[i];
+      h_wo[sr + (i - r0)] = sw + (r.wptr[i] - w0);
+      h_cp[sr + (i - r0)] = sc + (r.cal_ptr[i] - c0);
+    }
+    swk::ServeChunk &c = h_ch[k];
+    c.words = dptr<uint32_t>(s, r, r.lay.words) + w0;
+    c.cal_pos = dptr<int64_t>(s, r, r.lay.cal_pos) + c0;
+    c.cal_ref = dptr<int16_t>(s, r, r.lay.cal_ref) + c0;
+    c.strand = dptr<uint8_t>(s, r, r.lay.strand) + c0;
+    c.score = dptr<int32_t>(s, r, r.lay.score) + 2 * c0;
+    c.ref_end = dptr<int64_t>(s, r, r.lay.ref_end) + 2 * c0;
+    c.read_end = dptr<int16_t>(s, r, r.lay.read_end) + 2 * c0;
+    c.best_score = dptr<int32_t>(s, r, r.lay.best_score) + r0 * s->n_refs;
+    c.best_slot = dptr<int64_t>(s, r, r.lay.best_slot) + r0 * s->n_refs;
+    c.n_tied = dptr<int32_t>(s, r, r.lay.n_tied) + r0 * s->n_refs;
+    c.n_reads = r1 - r0;
+    c.n_cals = r.cal_ptr[r1] - c0;
+    c.n_words = r.wptr[r1] - w0;
+    c.step_r0 = sr;
+    c.step_c0 = sc;
+    c.step_w0 = sw;
+    c.slot_shift = 2 * (c0 - sc);
+    sr += c.n_reads;
+    sc += c.n_cals;
+    sw += c.n_words;
+  }
+  h_cp[nr] = nc;
   hipStream_t cs = st.stream;
-  hipMemcpyAsync(st.chunks_dev, st.chunks_host, sizeof(swk::ServeChunk) * nch, hipMemcpyHostToDevice, cs);
-  swk::launch_serve_gather(st.chunks_dev, nch, nr, nc, st.words, st.word_off, st.read_len, st.cal_ptr, st.cal_pos,
-                           st.cal_ref, st.strand, cs);
-  int rc = SW_OK;
-  if (nc > 0 && nc <= s->small_step_cals) {
+  const int32_t *d_len = reinterpret_cast<const int32_t *>(st.hdr_dev + H.len);
+  const int64_t *d_wo = reinterpret_cast<const int64_t *>(st.hdr_dev + H.word_off);
+  const int64_t *d_cp = reinterpret_cast<const int64_t *>(st.hdr_dev + H.cal_ptr);
+  const swk::ServeChunk *d_ch = reinterpret_cast<const swk::ServeChunk *>(st.hdr_dev + H.chunks);
+  hipError_t he = hipMemcpyAsync(st.hdr_dev, st.hdr_host, H.bytes, hipMemcpyHostToDevice, cs);
+  if (he == hipSuccess) he = swk::launch_serve_gather(d_ch, nch, nw, nc, st.words, st.cal_pos, st.cal_ref, st.strand, cs);
+  int rc = he == hipSuccess ? SW_OK : swapi::hip_fail(he);
+  if (rc == SW_OK && nc > 0 && nc <= s->small_step_cals) {
     // a small step: the plain call, whose AUTO kernel choice runs one wavefront
     // per task (a lane working through a whole long read alone would set the
     // latency); the outputs are the same
-    rc = sw_align_batch(st.words, st.word_off, st.read_len, (int32_t)nr, &s->refs, st.cal_ptr, st.cal_pos,
+    rc = sw_align_batch(st.words, d_wo, d_len, (int32_t)nr, &s->refs, d_cp, st.cal_pos,
                         st.cal_ref, st.strand, nc, &s->sc_small, st.score, st.ref_end, st.read_end, st.small_ws,
                         st.small_ws_bytes, (sw_stream_t)cs);
-  } else if (nc > 0) {
-    rc = sw_align_batch_ctx(st.ctx, st.words, st.word_off, st.read_len, (int32_t)nr, &s->refs, st.cal_ptr,
+  } else if (rc == SW_OK && nc > 0) {
+    rc = sw_align_batch_ctx(st.ctx, st.words, d_wo, d_len, (int32_t)nr, &s->refs, d_cp,
                             st.cal_pos, st.cal_ref, st.strand, nc, &s->sc, st.score, st.ref_end, st.read_end,
                             (sw_stream_t)cs);
   }
   if (rc == SW_OK)
-    rc = sw_reduce_best(st.cal_ptr, st.cal_ref, (int32_t)nr, s->n_refs, st.score, st.best_score, st.best_slot,
+    rc = sw_reduce_best(d_cp, st.cal_ref, (int32_t)nr, s->n_refs, st.score, st.best_score, st.best_slot,
                         st.n_tied, (sw_stream_t)cs);
   st.error = rc;
   if (rc != SW_OK) s->last_error = rc;
-  swk::launch_serve_scatter(st.chunks_dev, nch, nr, nc, s->n_refs, st.score, st.ref_end, st.read_end, st.best_score,
-                            st.best_slot, st.n_tied, cs);
+  // no scatter without this step's descriptors on the device
+  if (he == hipSuccess)
+    swk::launch_serve_scatter(d_ch, nch, nr, nc, s->n_refs, st.score, st.ref_end, st.read_end, st.best_score,
+                              st.best_slot, st.n_tied, cs);
   hipEventRecord(st.done, cs);
   st.busy = true;
   s->in_flight.push_back(&st);
@@ -385,17 +440,19 @@ void finish_loop(sw_server *s) {
     s->to_finish.clear();
     lk.unlock();
     for (auto &rq : done) {
-    Request &r = *rq;
-    if (r.error) continue;  // failed: the caller's buffers are left as they were
-    std::memcpy(r.o_score, hptr<int32_t>(s, r, r.lay.score), sizeof(int32_t) * 2 * r.n_cals);
-    std::memcpy(r.o_ref_end, hptr<int64_t>(s, r, r.lay.ref_end), sizeof(int64_t) * 2 * r.n_cals);
-    std::memcpy(r.o_read_end, hptr<int16_t>(s, r, r.lay.read_end), sizeof(int16_t) * 2 * r.n_cals);
-    if (r.o_best_score)
-      std::memcpy(r.o_best_score, hptr<int32_t>(s, r, r.lay.best_score), sizeof(int32_t) * r.n_reads * s->n_refs);
-    if (r.o_best_slot)
-      std::memcpy(r.o_best_slot, hptr<int64_t>(s, r, r.lay.best_slot), sizeof(int64_t) * r.n_reads * s->n_refs);
-    if (r.o_n_tied)
-      std::memcpy(r.o_n_tied, hptr<int32_t>(s, r, r.lay.n_tied), sizeof(int32_t) * r.n_reads * s->n_refs);
+      Request &r = *rq;
+      if (r.error) continue;  // failed: the caller's buffers are left as they were
+      if (r.n_cals > 0) {
+        std::memcpy(r.o_score, hptr<int32_t>(s, r, r.lay.score), sizeof(int32_t) * 2 * r.n_cals);
+        std::memcpy(r.o_ref_end, hptr<int64_t>(s, r, r.lay.ref_end), sizeof(int64_t) * 2 * r.n_cals);
+        std::memcpy(r.o_read_end, hptr<int16_t>(s, r, r.lay.read_end), sizeof(int16_t) * 2 * r.n_cals);
+      }
+      if (r.o_best_score)
+        std::memcpy(r.o_best_score, hptr<int32_t>(s, r, r.lay.best_score), sizeof(int32_t) * r.n_reads * s->n_refs);
+      if (r.o_best_slot)
+        std::memcpy(r.o_best_slot, hptr<int64_t>(s, r, r.lay.best_slot), sizeof(int64_t) * r.n_reads * s->n_refs);
+      if (r.o_n_tied)
+        std::memcpy(r.o_n_tied, hptr<int32_t>(s, r, r.lay.n_tied), sizeof(int32_t) * r.n_reads * s->n_refs);
     }
     const double t = now_s();
     lk.lock();
@@ -462,7 +519,10 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
                            ? 0
                            : 16 * (int64_t)swapi::device_cus();
   s->arena.reset(new Arena(opts->memory_budget));
-  if (hipHostMalloc((void **)&s->arena_host, opts->memory_budget, hipHostMallocMapped) != hipSuccess) {
+  // coherent: blocks are rewritten by the host for each new request, and the
+  // device must never see a previous request's bytes through its caches
+  if (hipHostMalloc((void **)&s->arena_host, opts->memory_budget, hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
     sw_server_destroy(s);
     return SW_ERR_NOMEM;
   }
@@ -479,14 +539,12 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
       o = up256(o + b);
       return r;
     };
-    const size_t o_words = take(4 * W), o_wo = take(8 * R), o_len = take(4 * R), o_cp = take(8 * (R + 1)),
-                 o_pos = take(8 * C), o_ref = take(2 * C), o_str = take(C), o_sc = take(4 * 2 * C),
-                 o_re = take(8 * 2 * C), o_qe = take(2 * 2 * C), o_bs = take(4 * R * SW_MAX_REFS),
-                 o_bl = take(8 * R * SW_MAX_REFS), o_nt = take(4 * R * SW_MAX_REFS),
-                 o_ch = take(sizeof(swk::ServeChunk) * opts->max_step_chunks);
-    if (hipMalloc(&st.base, o) != hipSuccess ||
-        hipHostMalloc((void **)&st.chunks_host, sizeof(swk::ServeChunk) * opts->max_step_chunks,
-                      hipHostMallocDefault) != hipSuccess ||
+    const size_t o_words = take(4 * W), o_pos = take(8 * C), o_ref = take(2 * C), o_str = take(C),
+                 o_sc = take(4 * 2 * C), o_re = take(8 * 2 * C), o_qe = take(2 * 2 * C),
+                 o_bs = take(4 * R * SW_MAX_REFS), o_bl = take(8 * R * SW_MAX_REFS), o_nt = take(4 * R * SW_MAX_REFS);
+    const size_t hdr = header_layout(R, opts->max_step_chunks).bytes;
+    if (hipMalloc(&st.base, o) != hipSuccess || hipMalloc((void **)&st.hdr_dev, hdr) != hipSuccess ||
+        hipHostMalloc((void **)&st.hdr_host, hdr, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess ||
         (&st == &s->slots[0] ? hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking)
                              : (st.stream = s->slots[0].stream, hipSuccess)) != hipSuccess) {  // shared
@@ -495,9 +553,6 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
     }
     char *b = (char *)st.base;
     st.words = (uint32_t *)(b + o_words);
-    st.word_off = (int64_t *)(b + o_wo);
-    st.read_len = (int32_t *)(b + o_len);
-    st.cal_ptr = (int64_t *)(b + o_cp);
     st.cal_pos = (int64_t *)(b + o_pos);
     st.cal_ref = (int16_t *)(b + o_ref);
     st.strand = (uint8_t *)(b + o_str);
@@ -507,7 +562,6 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
     st.best_score = (int32_t *)(b + o_bs);
     st.best_slot = (int64_t *)(b + o_bl);
     st.n_tied = (int32_t *)(b + o_nt);
-    st.chunks_dev = (swk::ServeChunk *)(b + o_ch);
   }
   sw_ctx_opts_t co{};
   co.device = opts->device;
@@ -563,16 +617,15 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
   if (!s || !req_id) return SW_ERR_INVALID_ARG;
   if (!s->refs_set) return SW_ERR_STATE;
   if (n_reads < 1 || n_cals < 0 || n_codes < 0) return SW_ERR_INVALID_ARG;
-  if (!read_codes || !read_code_off || !read_len || !cal_ptr || !score || !ref_end || !read_end)
-    return SW_ERR_INVALID_ARG;
-  if (n_cals > 0 && (!cal_pos || !cal_ref || !strand)) return SW_ERR_INVALID_ARG;
+  if (!read_codes || !read_code_off || !read_len || !cal_ptr) return SW_ERR_INVALID_ARG;
+  if (n_cals > 0 && (!cal_pos || !cal_ref || !strand || !score || !ref_end || !read_end)) return SW_ERR_INVALID_ARG;
   if (n_reads > s->opts.max_step_reads) return SW_ERR_INVALID_ARG;
   if (cal_ptr[0] != 0 || cal_ptr[n_reads] != n_cals) return SW_ERR_INVALID_ARG;
   for (int32_t i = 0; i < n_reads; ++i) {
     if (cal_ptr[i + 1] < cal_ptr[i]) return SW_ERR_INVALID_ARG;
     if (cal_ptr[i + 1] - cal_ptr[i] > s->opts.max_step_cals) return SW_ERR_INVALID_ARG;
-    if (read_code_off[i] % 16 || read_code_off[i] < 0 || read_len[i] < 0 ||
-        read_len[i] > s->mode.max_read_len || read_code_off[i] + read_len[i] > n_codes)
+    if (read_code_off[i] < 0 || read_len[i] < 0 || read_len[i] > s->mode.max_read_len ||
+        read_code_off[i] + read_len[i] > n_codes)
       return SW_ERR_INVALID_ARG;
   }
   auto rq = std::make_shared<Request>();
@@ -580,12 +633,15 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
   r.n_reads = n_reads;
   r.n_cals = n_cals;
   r.n_codes = n_codes;
-  r.lay = make_layout(n_reads, n_cals, n_codes, s->n_refs);
-  if (r.lay.total > s->arena->size()) return SW_ERR_REJECTED;
-  // the step builder needs the read offsets, lengths and CAL rows on the host
-  r.code_off.assign(read_code_off, read_code_off + n_reads);
+  // the step builder works from host copies of the read lengths, the packed
+  // word offsets (reads back to back in the arena) and the CAL rows
   r.len.assign(read_len, read_len + n_reads);
   r.cal_ptr.assign(cal_ptr, cal_ptr + n_reads + 1);
+  r.wptr.resize((size_t)n_reads + 1);
+  r.wptr[0] = 0;
+  for (int32_t i = 0; i < n_reads; ++i) r.wptr[i + 1] = r.wptr[i] + (read_len[i] + 15) / 16;
+  r.lay = make_layout(n_reads, n_cals, r.wptr[n_reads], s->n_refs);
+  if (r.lay.total > s->arena->size()) return SW_ERR_REJECTED;
   bool reserved = false;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -594,9 +650,10 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
   }
   if (reserved) {
     // the caller's thread stages its own inputs (reads packed) into the pinned arena
-    stage_inputs(s, r, read_codes, read_code_off, read_len, cal_ptr, cal_pos, cal_ref, strand);
+    stage_inputs(s, r, read_codes, read_code_off, cal_pos, cal_ref, strand);
   } else {
     r.codes.assign(read_codes, read_codes + n_codes);
+    r.code_off.assign(read_code_off, read_code_off + n_reads);
     if (n_cals) {
       r.cal_pos.assign(cal_pos, cal_pos + n_cals);
       r.cal_ref.assign(cal_ref, cal_ref + n_cals);
@@ -696,7 +753,8 @@ int sw_server_destroy(sw_server_t *s) {
     if (st.small_ws) hipFree(st.small_ws);
     if (st.stream && &st == &s->slots[0]) hipStreamDestroy(st.stream);
     if (st.base) hipFree(st.base);
-    if (st.chunks_host) hipHostFree(st.chunks_host);
+    if (st.hdr_dev) hipFree(st.hdr_dev);
+    if (st.hdr_host) hipHostFree(st.hdr_host);
     if (st.done) hipEventDestroy(st.done);
   }
   if (s->arena_host) hipHostFree(s->arena_host);

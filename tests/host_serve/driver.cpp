@@ -1,0 +1,192 @@
+// Host test of the served path on the CPU stand-in runtime: several client
+// threads submit random requests (reads laid out with gaps and out of order,
+// reads of length 0, reads without CALs, requests split over several steps),
+// under a staging budget small enough that admission waits and arena blocks are
+// reused; every output must be the stub scoring of the request's own inputs.
+// Run under the host address and undefined-behaviour sanitizers, it also shows
+// that no gather or scatter access leaves its buffers.  TEST INFRASTRUCTURE ONLY.
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <atomic>
+#include <numeric>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "../../include/sw_align.h"
+#include "stub_score.h"
+
+extern std::atomic<long> g_plain_calls, g_ctx_calls;
+
+namespace {
+
+constexpr int kRefs = 2;
+constexpr int kMaxLen = 60;
+
+struct Req {
+  int n_reads = 0;
+  std::vector<uint8_t> codes;
+  std::vector<int64_t> code_off, cal_ptr, cal_pos;
+  std::vector<int32_t> len;
+  std::vector<int16_t> cal_ref;
+  std::vector<uint8_t> strand;
+  std::vector<int32_t> score, best_score, n_tied;
+  std::vector<int64_t> ref_end, best_slot;
+  std::vector<int16_t> read_end;
+  int64_t id = 0;
+};
+
+// layout 0: reads back to back at 16-aligned offsets, in order; 1: 16-aligned
+// offsets with gaps, in a shuffled order; 2: any offsets, gaps, shuffled.
+Req make_request(std::mt19937_64 &g, int max_reads, int max_cals_per_read, int layout) {
+  Req q;
+  q.n_reads = 1 + (int)(g() % (uint64_t)max_reads);
+  q.len.resize(q.n_reads);
+  for (auto &L : q.len) L = (g() % 8 == 0) ? 0 : 1 + (int)(g() % kMaxLen);
+  // reads placed in a shuffled order with random gaps between them
+  std::vector<int> order(q.n_reads);
+  std::iota(order.begin(), order.end(), 0);
+  if (layout > 0) std::shuffle(order.begin(), order.end(), g);
+  q.code_off.resize(q.n_reads);
+  int64_t at = layout == 2 ? (int64_t)(g() % 7) : 0;
+  for (int i : order) {
+    q.code_off[i] = at;
+    at += q.len[i] + (layout > 0 ? (int64_t)(g() % 40) : 0);
+    if (layout < 2) at = (at + 15) / 16 * 16;
+  }
+  q.codes.resize((size_t)at + 1);
+  for (auto &c : q.codes) c = (uint8_t)(g() % 4);
+  q.cal_ptr.assign(q.n_reads + 1, 0);
+  for (int i = 0; i < q.n_reads; ++i) {
+    const int n = (g() % 6 == 0) ? 0 : (int)(g() % (uint64_t)(max_cals_per_read + 1));
+    q.cal_ptr[i + 1] = q.cal_ptr[i] + n;
+  }
+  const int64_t nc = q.cal_ptr[q.n_reads];
+  q.cal_pos.resize(nc);
+  q.cal_ref.resize(nc);
+  q.strand.resize(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    q.cal_pos[c] = (int64_t)(g() % 100000);
+    q.cal_ref[c] = (int16_t)(g() % kRefs);
+    q.strand[c] = (uint8_t)(1 + g() % 3);
+  }
+  q.score.assign(2 * nc, -7);
+  q.ref_end.assign(2 * nc, -7);
+  q.read_end.assign(2 * nc, -7);
+  q.best_score.assign(q.n_reads * kRefs, -7);
+  q.best_slot.assign(q.n_reads * kRefs, -7);
+  q.n_tied.assign(q.n_reads * kRefs, -7);
+  return q;
+}
+
+// Expected outputs from the request's own inputs; returns the number of mismatches.
+long check(const Req &q) {
+  long bad = 0;
+  for (int r = 0; r < q.n_reads; ++r) {
+    const uint64_t rh = stub_read_hash(q.codes.data() + q.code_off[r], q.len[r]);
+    for (int k = 0; k < kRefs; ++k) {
+      int32_t b = -1, nt = 0;
+      int64_t sl = -1;
+      for (int64_t c = q.cal_ptr[r]; c < q.cal_ptr[r + 1]; ++c)
+        for (int h = 0; h < 2; ++h) {
+          int32_t s;
+          int64_t re;
+          int16_t qe;
+          stub_slot(rh, q.len[r], q.cal_pos[c], q.cal_ref[c], q.strand[c], h, &s, &re, &qe);
+          if (k == 0)
+            bad += s != q.score[2 * c + h] || re != q.ref_end[2 * c + h] || qe != q.read_end[2 * c + h];
+          if (q.cal_ref[c] != k || s < 0) continue;
+          if (s > b) {
+            b = s;
+            sl = 2 * c + h;
+            nt = 1;
+          } else if (s == b) {
+            ++nt;
+          }
+        }
+      const int64_t o = (int64_t)r * kRefs + k;
+      bad += b != q.best_score[o] || sl != q.best_slot[o] || nt != q.n_tied[o];
+    }
+  }
+  return bad;
+}
+
+}  // namespace
+
+int main(int argc, char **argv) {
+  const uint64_t seed = argc > 1 ? strtoull(argv[1], nullptr, 10) : 1;
+  const int n_clients = argc > 2 ? atoi(argv[2]) : 4;
+  const int per_client = argc > 3 ? atoi(argv[3]) : 60;
+  const int layout = argc > 4 ? atoi(argv[4]) : 2;
+  sw_scoring_t sc{};
+  sc.match = 2;
+  sc.mismatch = -3;
+  sc.gap_open = 5;
+  sc.gap_extend = 2;
+  sc.band = 8;
+  sc.precision = SW_PREC_AUTO;
+  sc.kernel = SW_KERNEL_AUTO;
+  sc.max_read_len = kMaxLen;
+  sw_server_opts_t o{};
+  o.device = 0;
+  o.scoring = sc;
+  o.memory_budget = 1 << 20;
+  o.max_step_reads = 48;
+  o.max_step_cals = 200;
+  o.max_step_chunks = 6;
+  sw_server_t *srv = nullptr;
+  if (sw_server_create(&o, &srv) != SW_OK) {
+    fprintf(stderr, "create failed\n");
+    return 2;
+  }
+  std::vector<uint32_t> ref_words(64, 0);
+  const int64_t woff[kRefs] = {0, 32}, rlen[kRefs] = {500, 500};
+  sw_refset_t refs{ref_words.data(), woff, rlen, kRefs};
+  if (sw_server_set_refs(srv, &refs) != SW_OK) {
+    fprintf(stderr, "set_refs failed\n");
+    return 2;
+  }
+  std::vector<std::vector<Req>> reqs(n_clients);
+  std::atomic<long> submit_errors{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < n_clients; ++t)
+    th.emplace_back([&, t] {
+      std::mt19937_64 g(seed * 1000003ull + (uint64_t)t);
+      auto &mine = reqs[t];
+      mine.reserve(per_client);
+      for (int i = 0; i < per_client; ++i) {
+        // mostly small requests, some as large as a whole step
+        const bool big = g() % 5 == 0;
+        mine.push_back(make_request(g, big ? o.max_step_reads : 12, big ? 40 : 12, layout));
+        Req &q = mine.back();
+        const int rc = sw_server_submit(srv, q.codes.data(), (int64_t)q.codes.size(), q.code_off.data(),
+                                        q.len.data(), q.n_reads, q.cal_ptr.data(), q.cal_pos.data(),
+                                        q.cal_ref.data(), q.strand.data(), q.cal_ptr[q.n_reads], q.score.data(),
+                                        q.ref_end.data(), q.read_end.data(), q.best_score.data(),
+                                        q.best_slot.data(), q.n_tied.data(), &q.id);
+        if (rc != SW_OK) {
+          submit_errors++;
+          fprintf(stderr, "submit rc %d: %d reads, %lld CALs\n", rc, q.n_reads, (long long)q.cal_ptr[q.n_reads]);
+        }
+      }
+    });
+  for (auto &x : th) x.join();
+  long bad = 0, n = 0, failed = 0;
+  for (auto &mine : reqs)
+    for (auto &q : mine) {
+      int32_t done = 0;
+      if (sw_server_wait(srv, q.id, -1, &done) != SW_OK || !done) ++failed;
+      bad += check(q);
+      if (sw_server_release(srv, q.id) != SW_OK) ++failed;
+      ++n;
+    }
+  sw_server_stats_t st{};
+  sw_server_stats(srv, &st);
+  sw_server_destroy(srv);
+  printf("requests %ld, steps %lld (plain %ld, batched %ld), submit errors %ld, failed %ld, mismatches %ld\n", n,
+         (long long)st.steps, g_plain_calls.load(), g_ctx_calls.load(), submit_errors.load(), failed, bad);
+  return (bad || failed || submit_errors || g_plain_calls == 0 || g_ctx_calls == 0) ? 1 : 0;
+}
