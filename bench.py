@@ -627,8 +627,10 @@ def main():
     ap.add_argument("--config3-band", type=int, default=32)
     ap.add_argument("--config4-reads", type=int, default=1_000_000,
                     help="reads of the two-reference classification leg (0 skips it)")
-    ap.add_argument("--serve-scale", type=float, default=1.0,
-                    help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0 skips it)")
+    ap.add_argument("--serve-scale", type=float, default=0.0,
+                    help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0, the default, "
+                         "skips it: the served path is kept off the GPU after runs that included it "
+                         "faulted the GPU)")
     ap.add_argument("--serve-pool", type=int, default=300)
     ap.add_argument("--serve-step-cals", type=int, default=1 << 20, help="CALs per device step of the server")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
@@ -741,6 +743,9 @@ def main():
         res["config3"] = c3
     if c4:
         res["config4"] = c4
+    if not served:
+        res["served"] = {"skipped": "served path kept off the GPU: three runs that included it ended with "
+                                    "the GPU faulted, cause not shown"}
     if served:
         res["served"] = served
         res["p50_ms"] = served["loads"][-1]["p50_ms"]
