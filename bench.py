@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import dataclasses
 import hashlib
 import json
 import os
@@ -624,8 +625,8 @@ def main():
     ap.add_argument("--reads", type=int, default=1_000_000)
     ap.add_argument("--config3-reads", type=int, default=2_000_000,
                     help="reads of the uneven-length leg (0 skips it)")
-    ap.add_argument("--config3-band", type=int, default=32)
-    ap.add_argument("--config4-reads", type=int, default=1_000_000,
+    ap.add_argument("--config3-bands", default="16,32,64", help="bands of the uneven-length leg")
+    ap.add_argument("--config4-reads", type=int, default=4_000_000,
                     help="reads of the two-reference classification leg (0 skips it)")
     ap.add_argument("--serve-scale", type=float, default=0.0,
                     help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0, the default, "
@@ -681,28 +682,34 @@ def main():
 
     c3 = None
     if args.config3_reads:
-        b3 = wl.config3(n_reads=args.config3_reads, band=args.config3_band)
-        leg3 = Leg(b3, 250, max(3, args.steps // 4), 1)
-        r3 = leg3.run()
-        p3 = None if args.no_parity else parity_sample(b3, leg3.out, n=100)
-        c3 = {"workload": f"config3: same reference, {b3.n_reads} reads with L uniform 75..250, geometric CALs "
-                          f"(mean 8, cap 64), band {args.config3_band}, both strands, int16",
-              "cals": b3.n_cals, "cells": leg3.cells,
-              "plain_gcups": r3["plain_gcups"], "batched_gcups": r3["batched_gcups"],
-              "plain_ms_per_step": round(r3["plain_ms"], 3), "batched_ms_per_step": round(r3["batched_ms"], 3),
-              "plain_reads_per_s": round(b3.n_reads / (r3["plain_ms"] * 1e-3), 1),
-              "batched_reads_per_s": round(b3.n_reads / (r3["batched_ms"] * 1e-3), 1),
-              "speedup_batched_vs_plain": round(r3["plain_ms"] / r3["batched_ms"], 3),
-              "plain_equals_batched": r3["plain_equals_batched"], "parity_sample_ok": p3, "plan": r3["plan"]}
-        leg3.free()
-        del leg3
-        progress(f"config3: batched {r3['batched_gcups']} GCUPS")
+        base3 = wl.config3(n_reads=args.config3_reads, band=32)  # reads and CALs do not depend on the band
+        c3 = {}
+        for band in [int(x) for x in args.config3_bands.split(",")]:
+            b3 = dataclasses.replace(base3, scoring=dataclasses.replace(base3.scoring, band=band),
+                                     name=f"config3_band{band}")
+            leg3 = Leg(b3, 250, max(3, args.steps // 4), 1)
+            r3 = leg3.run()
+            p3 = None if args.no_parity else parity_sample(b3, leg3.out, n=60)
+            c3[f"band{band}"] = {
+                "workload": f"config3: same reference, {b3.n_reads} reads with L uniform 75..250, geometric CALs "
+                            f"(mean 8, cap 64), band {band}, both strands, int16",
+                "cals": b3.n_cals, "cells": leg3.cells,
+                "plain_gcups": r3["plain_gcups"], "batched_gcups": r3["batched_gcups"],
+                "plain_ms_per_step": round(r3["plain_ms"], 3), "batched_ms_per_step": round(r3["batched_ms"], 3),
+                "plain_reads_per_s": round(b3.n_reads / (r3["plain_ms"] * 1e-3), 1),
+                "batched_reads_per_s": round(b3.n_reads / (r3["batched_ms"] * 1e-3), 1),
+                "speedup_batched_vs_plain": round(r3["plain_ms"] / r3["batched_ms"], 3),
+                "plain_equals_batched": r3["plain_equals_batched"], "parity_sample_ok": p3, "plan": r3["plan"]}
+            leg3.free()
+            del leg3
+            progress(f"config3 band {band}: batched {r3['batched_gcups']} GCUPS")
 
     c4 = classification_leg(args.config4_reads) if args.config4_reads else None
     progress("config4 done")
     served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests,
                         step_cals=args.serve_step_cals) if args.serve_scale > 0 else None
-    progress("served done")
+    if served:
+        progress("served done")
 
     step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
     gcups = cells / (step_ms * 1e-3) / 1e9
