@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <numeric>
 #include <random>
 #include <thread>
@@ -24,7 +25,7 @@ extern std::atomic<long> g_plain_calls, g_ctx_calls;
 namespace {
 
 constexpr int kRefs = 2;
-constexpr int kMaxLen = 60;
+int kMaxLen = 60;
 
 struct Req {
   int n_reads = 0;
@@ -121,6 +122,11 @@ int main(int argc, char **argv) {
   const int n_clients = argc > 2 ? atoi(argv[2]) : 4;
   const int per_client = argc > 3 ? atoi(argv[3]) : 60;
   const int layout = argc > 4 ? atoi(argv[4]) : 2;
+  // scale 1: step and request sizes of the served benchmark (1024 chunks, 65536
+  // reads and 1 M CALs per step, requests of up to 10000 reads of up to 250
+  // bases with up to 32 CALs each); scale 0: small steps that split requests
+  const int scale = argc > 5 ? atoi(argv[5]) : 0;
+  if (scale) kMaxLen = 250;
   sw_scoring_t sc{};
   sc.match = 2;
   sc.mismatch = -3;
@@ -133,10 +139,10 @@ int main(int argc, char **argv) {
   sw_server_opts_t o{};
   o.device = 0;
   o.scoring = sc;
-  o.memory_budget = 1 << 20;
-  o.max_step_reads = 48;
-  o.max_step_cals = 200;
-  o.max_step_chunks = 6;
+  o.memory_budget = scale ? (size_t)256 << 20 : (size_t)1 << 20;
+  o.max_step_reads = scale ? 65536 : 48;
+  o.max_step_cals = scale ? 1 << 20 : 200;
+  o.max_step_chunks = scale ? 1024 : 6;
   sw_server_t *srv = nullptr;
   if (sw_server_create(&o, &srv) != SW_OK) {
     fprintf(stderr, "create failed\n");
@@ -158,9 +164,15 @@ int main(int argc, char **argv) {
       auto &mine = reqs[t];
       mine.reserve(per_client);
       for (int i = 0; i < per_client; ++i) {
-        // mostly small requests, some as large as a whole step
-        const bool big = g() % 5 == 0;
-        mine.push_back(make_request(g, big ? o.max_step_reads : 12, big ? 40 : 12, layout));
+        // mostly small requests, some as large as a whole step (at scale: log-uniform
+        // 1..10000 reads with up to 32 CALs each)
+        if (scale) {
+          const int n = (int)std::exp(std::log(10000.0) * (double)(g() % 1000000) / 1e6);
+          mine.push_back(make_request(g, std::max(1, n), 32, layout));
+        } else {
+          const bool big = g() % 5 == 0;
+          mine.push_back(make_request(g, big ? o.max_step_reads : 12, big ? 40 : 12, layout));
+        }
         Req &q = mine.back();
         const int rc = sw_server_submit(srv, q.codes.data(), (int64_t)q.codes.size(), q.code_off.data(),
                                         q.len.data(), q.n_reads, q.cal_ptr.data(), q.cal_pos.data(),

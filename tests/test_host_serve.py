@@ -55,9 +55,17 @@ def test_served_routing_under_asan(asan_exe, seed, layout):
     assert "submit errors 0, failed 0" in out
 
 
+def test_served_routing_at_benchmark_scale(asan_exe):
+    """The served benchmark's step sizes (1024 chunks, 65536 reads and 1 M CALs per
+    step) and request sizes (1..10000 reads of up to 250 bases, up to 32 CALs)."""
+    out = _run(asan_exe, 11, 4, 120, 2, 1)
+    assert "submit errors 0, failed 0" in out
+
+
 def test_served_threads_under_tsan(tmp_path):
     clang = "/opt/rocm/llvm/bin/clang++"
     if not os.path.exists(clang):
         pytest.skip("ROCm clang++ not found")
     exe = _build(tmp_path, clang, ["-fsanitize=thread"])
     _run(exe, 5, 4, 40, 2)
+    _run(exe, 12, 4, 60, 0, 1)
