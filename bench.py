@@ -228,7 +228,7 @@ class Leg:
             sw.align_batch(db, self.refs, self.scoring, self.out, self.ws, st)
         if k_events is not None:
             k_events[1].record(st)
-        assert L.sw_reduce_best(sw._ptr(db.cal_ptr), sw._ptr(db.cal_ref), db.n_reads, self.batch.n_refs,
+        assert L.sw_reduce_best(sw._ptr(db.cal_ptr), sw._ptr(db.cal_ref), db.n_reads, self.batch.n_refs, db.n_cals,
                                 sw._ptr(self.out.score), sw._ptr(self.bs), sw._ptr(self.bl), sw._ptr(self.nt),
                                 sw._stream(st)) == 0
 

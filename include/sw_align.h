@@ -156,13 +156,17 @@ int sw_error_count(int64_t *n_invalid, int reset);
 
 /*
  * Score Tracker (sections 3.6 and 4.2): best slot per (read, reference).
+ *   cal_ptr     device [n_reads+1] CSR row pointer as for sw_align_batch; each
+ *               row is clamped to [0, n_cals] on the device, so a malformed row
+ *               pointer gives fewer slots, never an access outside the arrays
+ *   cal_ref     device [n_cals]; score device [2*n_cals] (sw_align_batch output)
  *   best_score  device [n_reads*n_refs] highest score among valid slots (-1 if none)
  *   best_slot   device [n_reads*n_refs] lowest slot index reaching it (-1 if none)
  *   n_tied      device [n_reads*n_refs] number of slots reaching it (0 if none)
  * Slots with negative scores (not requested, invalid) are skipped; CALs whose
  * reference id is outside [0, n_refs) are skipped.
  */
-int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
+int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs, int64_t n_cals,
                    const int32_t *score, int32_t *best_score, int64_t *best_slot, int32_t *n_tied,
                    sw_stream_t stream);
 
@@ -179,14 +183,15 @@ int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_rea
  *
  * sw_tied_flags: flags[slot] = 1 if the slot's score equals the highest
  * non-negative score of its read over all its slots, else 0.
- *   flags       device [2*n_cals]; n_cals = cal_ptr[n_reads] (read on device)
- * Both are asynchronous on `stream`; invalid host arguments return
+ *   flags       device [2*n_cals]; slots outside every (clamped) row are not written
+ * In both, cal_ptr rows are clamped to [0, n_cals] as for sw_reduce_best.  Both
+ * are asynchronous on `stream`; invalid host arguments return
  * SW_ERR_INVALID_ARG before any device work.
  */
 #define SW_MAX_TOPK 64
-int sw_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *top_score,
-            int64_t *top_slot, sw_stream_t stream);
-int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
+int sw_topk(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, const int32_t *score, int32_t k,
+            int32_t *top_score, int64_t *top_slot, sw_stream_t stream);
+int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, const int32_t *score, uint8_t *flags,
                   sw_stream_t stream);
 
 /* ------------------------------------------------------------------ seeding */

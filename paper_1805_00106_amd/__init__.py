@@ -102,9 +102,9 @@ def lib():
         L.sw_align_batch.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, vp, i64,
                                      ctypes.POINTER(Scoring), vp, vp, vp, vp, sz, vp]
         L.sw_error_count.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
-        L.sw_reduce_best.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.sw_reduce_best.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp, vp]
         L.sw_classify.argtypes = [vp, i32, i32, i32, vp, vp]
-        L.sw_topk.argtypes = [vp, i32, vp, i32, vp, vp, vp]
+        L.sw_topk.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
         L.sw_alu_peak.argtypes = [i32, i64, ctypes.POINTER(ctypes.c_double), vp]
         L.sw_traceback.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, i64,
                                    ctypes.POINTER(Scoring), vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp,
@@ -119,7 +119,7 @@ def lib():
         L.sw_cal_filter_workspace_bytes.restype = ctypes.c_size_t
         L.sw_traceback_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Scoring)]
         L.sw_traceback_workspace_bytes.restype = ctypes.c_size_t
-        L.sw_tied_flags.argtypes = [vp, i32, vp, vp, vp]
+        L.sw_tied_flags.argtypes = [vp, i32, i64, vp, vp, vp]
         L.sw_ctx_create.argtypes = [ctypes.POINTER(_CtxOpts), ctypes.POINTER(vp)]
         L.sw_ctx_destroy.argtypes = [vp]
         L.sw_align_batch_ctx.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, vp, i64,
@@ -270,7 +270,7 @@ def reduce_best(db: DeviceBatch, n_refs: int, score: torch.Tensor, stream=None):
     bs = torch.empty(n * n_refs, dtype=torch.int32, device=dev)
     bl = torch.empty(n * n_refs, dtype=torch.int64, device=dev)
     nt = torch.empty(n * n_refs, dtype=torch.int32, device=dev)
-    _check(lib().sw_reduce_best(_ptr(db.cal_ptr), _ptr(db.cal_ref), n, n_refs, _ptr(score), _ptr(bs), _ptr(bl),
+    _check(lib().sw_reduce_best(_ptr(db.cal_ptr), _ptr(db.cal_ref), n, n_refs, db.n_cals, _ptr(score), _ptr(bs), _ptr(bl),
                                 _ptr(nt), _stream(stream)), "sw_reduce_best")
     return bs.view(n, n_refs), bl.view(n, n_refs), nt.view(n, n_refs)
 
@@ -287,14 +287,15 @@ def topk(db: DeviceBatch, score: torch.Tensor, k: int, stream=None):
     n = db.n_reads
     ts = torch.empty(n * k, dtype=torch.int32, device=score.device)
     tl = torch.empty(n * k, dtype=torch.int64, device=score.device)
-    _check(lib().sw_topk(_ptr(db.cal_ptr), n, _ptr(score), k, _ptr(ts), _ptr(tl), _stream(stream)), "sw_topk")
+    _check(lib().sw_topk(_ptr(db.cal_ptr), n, db.n_cals, _ptr(score), k, _ptr(ts), _ptr(tl), _stream(stream)),
+           "sw_topk")
     return ts.view(n, k), tl.view(n, k)
 
 
 def tied_flags(db: DeviceBatch, score: torch.Tensor, stream=None) -> torch.Tensor:
     """1 for every slot whose score equals its read's best score, else 0."""
     fl = torch.empty(score.numel(), dtype=torch.uint8, device=score.device)
-    _check(lib().sw_tied_flags(_ptr(db.cal_ptr), db.n_reads, _ptr(score), _ptr(fl), _stream(stream)),
+    _check(lib().sw_tied_flags(_ptr(db.cal_ptr), db.n_reads, db.n_cals, _ptr(score), _ptr(fl), _stream(stream)),
            "sw_tied_flags")
     return fl
 

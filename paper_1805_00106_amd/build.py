@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswalign.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["sw_kernels.hip", "sw_trace.hip", "sw_filter.hip", "sw_index.hip", "sw_peak.hip", "sw_serve.hip", "sw_api.cpp", "sw_ctx.cpp", "sw_server.cpp", "sw_seed.cpp"]
+SOURCES = ["sw_kernels.hip", "sw_tracker.hip", "sw_trace.hip", "sw_filter.hip", "sw_index.hip", "sw_peak.hip", "sw_serve.hip", "sw_api.cpp", "sw_ctx.cpp", "sw_server.cpp", "sw_seed.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # No packed-fp32 instructions anywhere in device code (this code has no float math).
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

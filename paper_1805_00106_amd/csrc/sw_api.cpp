@@ -347,14 +347,15 @@ int sw_error_count(int64_t *n_invalid, int reset) {
   return SW_OK;
 }
 
-int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
+int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs, int64_t n_cals,
                    const int32_t *score, int32_t *best_score, int64_t *best_slot, int32_t *n_tied,
                    sw_stream_t stream) {
-  if (n_reads < 0 || n_refs < 1) return SW_ERR_INVALID_ARG;
+  if (n_reads < 0 || n_refs < 1 || n_cals < 0) return SW_ERR_INVALID_ARG;
   if (n_refs > SW_MAX_REFS) return SW_ERR_TOO_MANY_REFS;
   if (n_reads == 0) return SW_OK;
-  if (!cal_ptr || !cal_ref || !score || !best_score || !best_slot || !n_tied) return SW_ERR_INVALID_ARG;
-  hipError_t e = swk::launch_reduce(cal_ptr, cal_ref, n_reads, n_refs, score, best_score, best_slot, n_tied,
+  if (!cal_ptr || !best_score || !best_slot || !n_tied) return SW_ERR_INVALID_ARG;
+  if (n_cals > 0 && (!cal_ref || !score)) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_reduce(cal_ptr, cal_ref, n_reads, n_refs, n_cals, score, best_score, best_slot, n_tied,
                                     (hipStream_t)stream);
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
@@ -519,21 +520,21 @@ int sw_alu_peak(int32_t bits, int64_t iters, double *ops_per_s, sw_stream_t stre
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 
-int sw_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *top_score,
-            int64_t *top_slot, sw_stream_t stream) {
-  if (n_reads < 0 || k < 1 || k > SW_MAX_TOPK) return SW_ERR_INVALID_ARG;
+int sw_topk(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, const int32_t *score, int32_t k,
+            int32_t *top_score, int64_t *top_slot, sw_stream_t stream) {
+  if (n_reads < 0 || n_cals < 0 || k < 1 || k > SW_MAX_TOPK) return SW_ERR_INVALID_ARG;
   if (n_reads == 0) return SW_OK;
-  if (!cal_ptr || !score || !top_score || !top_slot) return SW_ERR_INVALID_ARG;
-  hipError_t e = swk::launch_topk(cal_ptr, n_reads, score, k, top_score, top_slot, (hipStream_t)stream);
+  if (!cal_ptr || !top_score || !top_slot || (n_cals > 0 && !score)) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_topk(cal_ptr, n_reads, n_cals, score, k, top_score, top_slot, (hipStream_t)stream);
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 
-int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
+int sw_tied_flags(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, const int32_t *score, uint8_t *flags,
                   sw_stream_t stream) {
-  if (n_reads < 0) return SW_ERR_INVALID_ARG;
+  if (n_reads < 0 || n_cals < 0) return SW_ERR_INVALID_ARG;
   if (n_reads == 0) return SW_OK;
-  if (!cal_ptr || !score || !flags) return SW_ERR_INVALID_ARG;
-  hipError_t e = swk::launch_tied(cal_ptr, n_reads, score, flags, (hipStream_t)stream);
+  if (!cal_ptr || (n_cals > 0 && (!score || !flags))) return SW_ERR_INVALID_ARG;
+  hipError_t e = swk::launch_tied(cal_ptr, n_reads, n_cals, score, flags, (hipStream_t)stream);
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 

@@ -785,140 +785,6 @@ __global__ __launch_bounds__(64) void k_intra32(const AlignArgs A, const RefTabl
   }
 }
 
-// --------------------------------------------------------------------------- Score Tracker
-
-// One thread per read: best slot per reference, lowest slot among ties, tie count.
-__global__ void k_reduce_best(const int64_t *__restrict__ cal_ptr, const int16_t *__restrict__ cal_ref,
-                              int32_t n_reads, int32_t n_refs, const int32_t *__restrict__ score,
-                              int32_t *__restrict__ best_score, int64_t *__restrict__ best_slot,
-                              int32_t *__restrict__ n_tied) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_reads) return;
-  int64_t o = r * n_refs;
-  if (n_refs <= 8) {
-    int32_t bs[8];
-    int64_t bl[8];
-    int32_t nt[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      bs[k] = -1;
-      bl[k] = -1;
-      nt[k] = 0;
-    }
-    for (int64_t c = cal_ptr[r]; c < cal_ptr[r + 1]; ++c) {
-      int k = cal_ref[c];
-      if (k < 0 || k >= n_refs) continue;
-      int2 s2 = *reinterpret_cast<const int2 *>(score + 2 * c);
-      int32_t sv[2] = {s2.x, s2.y};
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        int32_t s = sv[h];
-        if (s < 0) continue;
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-          if (kk == k) {
-            if (s > bs[kk]) {
-              bs[kk] = s;
-              bl[kk] = 2 * c + h;
-              nt[kk] = 1;
-            } else if (s == bs[kk]) {
-              nt[kk] += 1;
-            }
-          }
-        }
-      }
-    }
-    for (int k = 0; k < n_refs; ++k) {
-      best_score[o + k] = bs[k];
-      best_slot[o + k] = bl[k];
-      n_tied[o + k] = nt[k];
-    }
-  } else {
-    for (int k = 0; k < n_refs; ++k) {
-      best_score[o + k] = -1;
-      best_slot[o + k] = -1;
-      n_tied[o + k] = 0;
-    }
-    for (int64_t c = cal_ptr[r]; c < cal_ptr[r + 1]; ++c) {
-      int k = cal_ref[c];
-      if (k < 0 || k >= n_refs) continue;
-      for (int h = 0; h < 2; ++h) {
-        int32_t s = score[2 * c + h];
-        if (s < 0) continue;
-        if (s > best_score[o + k]) {
-          best_score[o + k] = s;
-          best_slot[o + k] = 2 * c + h;
-          n_tied[o + k] = 1;
-        } else if (s == best_score[o + k]) {
-          n_tied[o + k] += 1;
-        }
-      }
-    }
-  }
-}
-
-// One thread per read: the k best slots over all CALs and strands (highest
-// score, then lowest slot), kept sorted in the output rows by insertion.
-__global__ void k_topk(const int64_t *__restrict__ cal_ptr, int32_t n_reads, const int32_t *__restrict__ score,
-                       int32_t k, int32_t *__restrict__ top_score, int64_t *__restrict__ top_slot) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_reads) return;
-  int32_t *ts = top_score + r * k;
-  int64_t *tl = top_slot + r * k;
-  int n = 0;              // entries filled
-  int32_t last = INT32_MAX; // score of entry k-1 once the list is full
-  const int64_t s_end = 2 * cal_ptr[r + 1];
-  for (int64_t slot = 2 * cal_ptr[r]; slot < s_end; ++slot) {
-    const int32_t s = score[slot];
-    if (s < 0) continue;
-    // slots arrive in increasing order, so an equal score never displaces an entry
-    if (n == k && s <= last) continue;
-    int pos = n < k ? n : k - 1;
-    while (pos > 0 && ts[pos - 1] < s) {
-      ts[pos] = ts[pos - 1];
-      tl[pos] = tl[pos - 1];
-      --pos;
-    }
-    ts[pos] = s;
-    tl[pos] = slot;
-    if (n < k) ++n;
-    if (n == k) last = ts[k - 1];
-  }
-  for (int i = n; i < k; ++i) {
-    ts[i] = -1;
-    tl[i] = -1;
-  }
-}
-
-// One thread per read: mark every slot whose score equals the read's best.
-__global__ void k_tied(const int64_t *__restrict__ cal_ptr, int32_t n_reads, const int32_t *__restrict__ score,
-                       uint8_t *__restrict__ flags) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_reads) return;
-  const int64_t a = 2 * cal_ptr[r], b = 2 * cal_ptr[r + 1];
-  int32_t best = -1;
-  for (int64_t slot = a; slot < b; ++slot) best = max(best, score[slot]);
-  for (int64_t slot = a; slot < b; ++slot) flags[slot] = (best >= 0 && score[slot] == best) ? 1 : 0;
-}
-
-__global__ void k_classify(const int32_t *__restrict__ best_score, int32_t n_reads, int32_t n_refs,
-                           int32_t threshold, int32_t *__restrict__ cls) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_reads) return;
-  int32_t top = -1, arg = -1, cnt = 0;
-  for (int k = 0; k < n_refs; ++k) {
-    int32_t v = best_score[r * n_refs + k];
-    if (v > top) {
-      top = v;
-      arg = k;
-      cnt = 1;
-    } else if (v == top) {
-      cnt++;
-    }
-  }
-  cls[r] = top < threshold ? -1 : (cnt > 1 ? -2 : arg);
-}
-
 // --------------------------------------------------------------------------- batched planning
 //
 // Tasks are binned by read length so that the lanes of a tile share their
@@ -1147,35 +1013,6 @@ int intra_blocks_per_cu(size_t lds) {
   return n;
 }
 
-hipError_t launch_reduce(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
-                         const int32_t *score, int32_t *bs, int64_t *bl, int32_t *nt, hipStream_t st) {
-  if (n_reads == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_best, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, cal_ref,
-                     n_reads, n_refs, score, bs, bl, nt);
-  return hipGetLastError();
-}
-
-hipError_t launch_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *ts,
-                       int64_t *tl, hipStream_t st) {
-  if (n_reads == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_topk, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, n_reads, score, k, ts, tl);
-  return hipGetLastError();
-}
-
-hipError_t launch_tied(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
-                       hipStream_t st) {
-  if (n_reads == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tied, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, cal_ptr, n_reads, score, flags);
-  return hipGetLastError();
-}
-
-hipError_t launch_classify(const int32_t *bs, int32_t n_reads, int32_t n_refs, int32_t thr, int32_t *cls,
-                           hipStream_t st) {
-  if (n_reads == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_classify, dim3(blocks_for(n_reads, 256)), dim3(256), 0, st, bs, n_reads, n_refs,
-                     thr, cls);
-  return hipGetLastError();
-}
 
 // --------------------------------------------------------------------------- queries
 

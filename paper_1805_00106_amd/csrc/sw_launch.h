@@ -39,12 +39,14 @@ hipError_t launch_expand(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals
                          hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_inter(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
+// Score Tracker launchers (sw_tracker.hip); CSR rows are clamped to [0, n_cals].
 hipError_t launch_reduce(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
-                         const int32_t *score, int32_t *bs, int64_t *bl, int32_t *nt, hipStream_t st);
-hipError_t launch_topk(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, int32_t k, int32_t *ts,
-                       int64_t *tl, hipStream_t st);
-hipError_t launch_tied(const int64_t *cal_ptr, int32_t n_reads, const int32_t *score, uint8_t *flags,
-                       hipStream_t st);
+                         int64_t n_cals, const int32_t *score, int32_t *bs, int64_t *bl, int32_t *nt,
+                         hipStream_t st);
+hipError_t launch_topk(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, const int32_t *score, int32_t k,
+                       int32_t *ts, int64_t *tl, hipStream_t st);
+hipError_t launch_tied(const int64_t *cal_ptr, int32_t n_reads, int64_t n_cals, const int32_t *score,
+                       uint8_t *flags, hipStream_t st);
 hipError_t launch_classify(const int32_t *bs, int32_t n_reads, int32_t n_refs, int32_t thr, int32_t *cls,
                            hipStream_t st);
 // Resident waves of the inter kernel with R strip rows on this device (occupancy query).

@@ -385,7 +385,7 @@ bool launch_step(sw_server *s) {
                             (sw_stream_t)cs);
   }
   if (rc == SW_OK)
-    rc = sw_reduce_best(d_cp, st.cal_ref, (int32_t)nr, s->n_refs, st.score, st.best_score, st.best_slot,
+    rc = sw_reduce_best(d_cp, st.cal_ref, (int32_t)nr, s->n_refs, nc, st.score, st.best_score, st.best_slot,
                         st.n_tied, (sw_stream_t)cs);
   st.error = rc;
   if (rc != SW_OK) s->last_error = rc;

@@ -90,7 +90,7 @@ int sw_align_batch_ctx(sw_ctx_t *, const uint32_t *reads2bit, const int64_t *rea
 
 // Score Tracker: per (read, reference) the best score, its lowest slot, and the
 // number of slots holding it; -1/-1/0 without a scored slot.
-int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs,
+int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_reads, int32_t n_refs, int64_t,
                    const int32_t *score, int32_t *best_score, int64_t *best_slot, int32_t *n_tied, sw_stream_t) {
   for (int32_t r = 0; r < n_reads; ++r)
     for (int k = 0; k < n_refs; ++k) {

@@ -101,9 +101,11 @@ def test_counts_and_workspace_validation(sw):
 def test_reduce_and_classify_validation(sw):
     L = sw.lib()
     p = ctypes.c_void_p(16)
-    assert L.sw_reduce_best(p, p, -1, 1, p, p, p, p, None) == -1
-    assert L.sw_reduce_best(p, p, 1, 0, p, p, p, p, None) == -1
-    assert L.sw_reduce_best(p, p, 1, 65, p, p, p, p, None) == -8
+    assert L.sw_reduce_best(p, p, -1, 1, 1, p, p, p, p, None) == -1
+    assert L.sw_reduce_best(p, p, 1, 0, 1, p, p, p, p, None) == -1
+    assert L.sw_reduce_best(p, p, 1, 65, 1, p, p, p, p, None) == -8
+    assert L.sw_reduce_best(p, p, 1, 1, -1, p, p, p, p, None) == -1
+    assert L.sw_reduce_best(p, None, 1, 1, 1, p, p, p, p, None) == -1
     assert L.sw_classify(p, 1, 0, 0, p, None) == -1
     assert L.sw_pack_2bit(p, -1, p, None) == -1
 
@@ -111,14 +113,16 @@ def test_reduce_and_classify_validation(sw):
 def test_topk_and_tied_validation(sw):
     L = sw.lib()
     p = ctypes.c_void_p(16)
-    assert L.sw_topk(p, -1, p, 1, p, p, None) == -1
-    assert L.sw_topk(p, 1, p, 0, p, p, None) == -1
-    assert L.sw_topk(p, 1, p, sw.MAX_TOPK + 1, p, p, None) == -1
-    assert L.sw_topk(None, 1, p, 1, p, p, None) == -1
-    assert L.sw_topk(p, 0, p, 1, p, p, None) == 0
-    assert L.sw_tied_flags(p, -1, p, p, None) == -1
-    assert L.sw_tied_flags(p, 1, None, p, None) == -1
-    assert L.sw_tied_flags(p, 0, p, p, None) == 0
+    assert L.sw_topk(p, -1, 1, p, 1, p, p, None) == -1
+    assert L.sw_topk(p, 1, 1, p, 0, p, p, None) == -1
+    assert L.sw_topk(p, 1, 1, p, sw.MAX_TOPK + 1, p, p, None) == -1
+    assert L.sw_topk(None, 1, 1, p, 1, p, p, None) == -1
+    assert L.sw_topk(p, 1, -1, p, 1, p, p, None) == -1
+    assert L.sw_topk(p, 0, 1, p, 1, p, p, None) == 0
+    assert L.sw_tied_flags(p, -1, 1, p, p, None) == -1
+    assert L.sw_tied_flags(p, 1, 1, None, p, None) == -1
+    assert L.sw_tied_flags(p, 1, -1, p, p, None) == -1
+    assert L.sw_tied_flags(p, 0, 1, p, p, None) == 0
 
 
 def test_cigar_text(sw):

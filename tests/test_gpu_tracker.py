@@ -95,3 +95,52 @@ def test_alu_peak_is_plausible():
     p32 = sw.alu_peak(32, 1 << 14)
     assert 0.2 * 7.864e13 < p16 <= 1.02 * 7.864e13
     assert 0.2 * 3.932e13 < p32 <= 1.02 * 3.932e13
+
+
+def test_malformed_row_pointer_is_clamped():
+    """Rows of a malformed CSR row pointer (negative start, end past n_cals,
+    decreasing entries) are clamped to [0, n_cals]: the best, top-k and tie-flag
+    reductions equal the same reductions over the clamped rows, computed here."""
+    b = wl.random_small_batch(61, n_reads=40, max_cals=4)
+    refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
+    db = sw.DeviceBatch.upload(b)
+    sc = scoring_for(b, sw.PREC_INT16)
+    out = sw.align_batch(db, refs, sc)
+    n = db.n_cals
+    bad = b.cal_ptr.copy()
+    bad[3], bad[7], bad[8], bad[20], bad[-1] = -5, n + 100, 2, n + 3, n + 7
+    rows = []
+    for r in range(b.n_reads):
+        a = min(max(int(bad[r]), 0), n)
+        rows.append((a, min(max(int(bad[r + 1]), a), n)))
+    bad_db = sw.DeviceBatch(db.reads2bit, db.read_word_off, db.read_len, torch.from_numpy(bad).cuda(), db.cal_pos,
+                            db.cal_ref, db.strand)
+    k = 3
+    bs, bl, nt = sw.reduce_best(bad_db, b.n_refs, out.score)
+    ts, tl = sw.topk(bad_db, out.score, k)
+    fl_dev = torch.full((2 * n,), 7, dtype=torch.uint8, device="cuda")
+    sw.lib().sw_tied_flags(sw._ptr(bad_db.cal_ptr), b.n_reads, n, sw._ptr(out.score), sw._ptr(fl_dev), None)
+    torch.cuda.synchronize()
+    s = out.score.cpu().numpy()
+    ref = b.cal_ref.astype(np.int64)
+    fl = fl_dev.cpu().numpy()
+    cover = np.zeros(2 * n, dtype=np.int64)  # clamped rows may overlap: flags are checked where one row writes
+    for a, e in rows:
+        cover[2 * a:2 * e] += 1
+    for r, (a, e) in enumerate(rows):
+        slots = [(int(s[t]), t) for t in range(2 * a, 2 * e) if s[t] >= 0]
+        for kk in range(b.n_refs):
+            mine = [(v, t) for v, t in slots if ref[t // 2] == kk]
+            best = max((v for v, _ in mine), default=-1)
+            first = min((t for v, t in mine if v == best), default=-1)
+            ties = sum(1 for v, _ in mine if v == best) if mine else 0
+            assert (bs[r, kk].item(), bl[r, kk].item(), nt[r, kk].item()) == (best, first, ties), (r, kk)
+        order = sorted(slots, key=lambda x: (-x[0], x[1]))[:k]
+        want_s = [v for v, _ in order] + [-1] * (k - len(order))
+        want_l = [t for _, t in order] + [-1] * (k - len(order))
+        assert ts[r].cpu().tolist() == want_s and tl[r].cpu().tolist() == want_l, r
+        top = max((v for v, _ in slots), default=-1)
+        for t in range(2 * a, 2 * e):
+            if cover[t] == 1:
+                assert fl[t] == (1 if top >= 0 and s[t] == top else 0), (r, t)
+    assert (fl[cover == 0] == 7).all()  # slots outside every row are not written
