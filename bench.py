@@ -104,10 +104,13 @@ def cpu_baseline(batch, target_s: float = 15.0):
                          "sample": f"{n1} reads ({cells_of(one):.3e} cells) in {dt1:.1f} s"}}
 
 
-def parity_sample(batch, out, n=300, seed=7, final_row=False):
-    """Compare a random sample of reads against the oracle (not timed)."""
+def parity_sample(batch, out, n=None, seed=7, final_row=False):
+    """Compare a random sample of reads (default 1% of them, at least 300) against
+    the oracle (not timed)."""
     from oracle import oracle as orc
     rng = np.random.default_rng(seed)
+    if n is None:
+        n = max(300, batch.n_reads // 100)
     idx = np.sort(rng.choice(batch.n_reads, min(n, batch.n_reads), replace=False))
     sub = batch.subset_reads(idx)
     s, r, e, _ = orc.align_batch(sub, n_threads=min(16, os.cpu_count() or 1), final_row=final_row)
@@ -330,7 +333,7 @@ class Leg:
                          "frac_of_measured": round(OPS_PER_CELL * gcups * 1e9 / (measured[name] * 1e12), 4),
                          "plan": self.ctx.last_plan()}
             if self.parity_reads:
-                res[name]["parity_sample_ok"] = parity_sample(self.batch, out, n=100,
+                res[name]["parity_sample_ok"] = parity_sample(self.batch, out,
                                                               final_row=mode == sw.MODE_FINAL_ROW)
         return res
 
@@ -453,7 +456,7 @@ class Leg:
         self.ctx.close()
 
 
-def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD):
+def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD, parity: bool = True):
     """Config 4: two references (A random, B = A diverged by 15% substitutions and
     2%/base indels); reads 70/30 from B/A; each read goes to the reference with
     the strictly higher best score (section 6.2).  Reports the outcome fractions
@@ -483,6 +486,7 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD):
     frac = lambda m: round(float(np.mean(m)), 5)
     # the threshold against the scores decoy CALs reach (uniform positions, no homology) and
     # the scores of the planted loci: T must sit above the first and below the second
+    p4 = parity_sample(b, leg.out) if parity else None
     score = leg.out.score.cpu().numpy().reshape(-1, 2).max(axis=1)
     r_of = np.repeat(np.arange(b.n_reads), np.diff(b.cal_ptr))
     best_decoy = np.full(b.n_reads, -1, np.int64)
@@ -505,7 +509,7 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD):
                                 "p99.9": pct(best_decoy, 99.9), "max": int(best_decoy.max()),
                                 "reads_at_or_above_threshold": frac(best_decoy >= threshold)},
            "homologous_best_score": {"p0.1": pct(best_true, 0.1), "p1": pct(best_true, 1), "p50": pct(best_true, 50)},
-           "gen_s": round(t_gen, 1)}
+           "parity_sample_ok": p4, "gen_s": round(t_gen, 1)}
     leg.free()
     return out
 
@@ -689,7 +693,7 @@ def main():
                                      name=f"config3_band{band}")
             leg3 = Leg(b3, 250, max(3, args.steps // 4), 1)
             r3 = leg3.run()
-            p3 = None if args.no_parity else parity_sample(b3, leg3.out, n=60)
+            p3 = None if args.no_parity else parity_sample(b3, leg3.out)
             c3[f"band{band}"] = {
                 "workload": f"config3: same reference, {b3.n_reads} reads with L uniform 75..250, geometric CALs "
                             f"(mean 8, cap 64), band {band}, both strands, int16",
@@ -704,7 +708,7 @@ def main():
             del leg3
             progress(f"config3 band {band}: batched {r3['batched_gcups']} GCUPS")
 
-    c4 = classification_leg(args.config4_reads) if args.config4_reads else None
+    c4 = classification_leg(args.config4_reads, parity=not args.no_parity) if args.config4_reads else None
     progress("config4 done")
     served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests,
                         step_cals=args.serve_step_cals) if args.serve_scale > 0 else None
