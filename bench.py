@@ -121,13 +121,13 @@ def parity_sample(batch, out, n=None, seed=7, final_row=False):
     return bool(np.array_equal(gs, s) and np.array_equal(gr, r) and np.array_equal(ge, e))
 
 
-def config1_leg(reps=20):
-    """Config 1 exactly as stated (1000 x 76 bp reads, 2 CALs each, both strands,
+def small_reference_leg(reps=20):
+    """The small-reference workload (1000 x 76 bp reads, 2 CALs each, both strands,
     int32): one plain call per kernel family, CALs and reads resident."""
     import torch
     import paper_1805_00106_amd as sw
     from paper_1805_00106_amd import workloads as wl
-    b = wl.config1()
+    b = wl.small_reference()
     refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
     db = sw.DeviceBatch.upload(b)
     out = sw.Outputs(db.n_cals)
@@ -303,9 +303,9 @@ class Leg:
                 "note": "inputs from and outputs to pinned host memory inside the timed region"}
 
     def variants(self, steps=5):
-        """The same resident config-2 batch on the batched path with other
-        scorings: int32 values (one strand per lane, the precision config 1
-        states) and the final-row mode (int16).  Outputs are checked against the
+        """The same resident chromosome-scale batch on the batched path with other
+        scorings: int32 values (one strand per lane, the precision of the
+        small-reference workload) and the final-row mode (int16).  Outputs are checked against the
         oracle on a read sample (not timed)."""
         torch, sw = self.torch, self.sw
         sc = self.batch.scoring
@@ -381,6 +381,33 @@ class Leg:
                "traced_fraction": round(float((nops > 0).float().mean().item()), 4),
                "kernel": "one slot per lane" if self.scoring.kernel != sw.KERNEL_INTRA else "one slot per wavefront",
                "workspace_mb": round(nb / 2**20, 1)}
+        # the other kernel family (one traced slot per wavefront) on the same slots: time and agreement
+        sc = self.scoring
+        scw = sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, sc.precision,
+                              sw.KERNEL_INTRA, sc.max_read_len)
+        nbw = sw.lib().sw_traceback_workspace_bytes(n, db.n_cals, ctypes.byref(scw))
+        wsw = torch.empty(max(nbw, 1), dtype=torch.uint8, device=dev)
+        rs2, qs2, nops2 = torch.empty_like(rs), torch.empty_like(qs), torch.empty_like(nops)
+        cig2 = torch.zeros_like(cig)
+
+        def call_wave():
+            rc = sw.lib().sw_traceback(P(db.reads2bit), P(db.read_word_off), P(db.read_len), db.n_reads, self.refs.c,
+                                       P(db.cal_ptr), P(db.cal_pos), P(db.cal_ref), db.n_cals, ctypes.byref(scw),
+                                       P(self.out.score), P(self.out.ref_end), P(self.out.read_end), P(slots), n, cap,
+                                       P(rs2), P(qs2), P(nops2), P(cig2), P(wsw), nbw, sw._stream(st))
+            assert rc == 0, rc
+
+        call_wave()
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(2):
+            call_wave()
+        e1.record(st)
+        torch.cuda.synchronize()
+        res["wavefront_per_slot_ms"] = round(e0.elapsed_time(e1) / 2, 3)
+        res["kernels_agree"] = bool(torch.equal(rs, rs2) and torch.equal(qs, qs2) and torch.equal(nops, nops2)
+                                    and torch.equal(cig, cig2))
+        del wsw
         if parity_reads:
             res["parity_sample_ok"] = self._trace_parity(slots, rs, qs, nops, cig.view(n, cap), cap, parity_reads)
         return res
@@ -457,7 +484,7 @@ class Leg:
 
 
 def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD, parity: bool = True):
-    """Config 4: two references (A random, B = A diverged by 15% substitutions and
+    """Two references (A random, B = A diverged by 15% substitutions and
     2%/base indels); reads 70/30 from B/A; each read goes to the reference with
     the strictly higher best score (section 6.2).  Reports the outcome fractions
     against the planted source and the scoring throughput."""
@@ -466,7 +493,7 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD, parity:
     from paper_1805_00106_amd import workloads as wl
 
     t_gen = time.perf_counter()
-    b = wl.config4(n_reads=n_reads)
+    b = wl.two_references(n_reads=n_reads)
     t_gen = time.perf_counter() - t_gen
     leg = Leg(b, 150, 3, 1)
     cls_t = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
@@ -495,7 +522,7 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD, parity:
     np.maximum.at(best_decoy, r_of[dmask], score[dmask])
     np.maximum.at(best_true, r_of[~dmask], score[~dmask])
     pct = lambda a, q: int(np.percentile(a, q))
-    out = {"workload": f"config4: A = {int(b.ref_len[0]):,} bp random, B = A + 15% substitutions + 2%/base indels "
+    out = {"workload": f"two references: A = {int(b.ref_len[0]):,} bp random, B = A + 15% substitutions + 2%/base indels "
                        f"({int(b.ref_len[1]):,} bp); {b.n_reads:,} reads of 150 bp, 70% from B / 30% from A, "
                        "1% substitutions; homologous locus + Poisson(2) decoys per reference; band 32; both strands",
            "threshold": threshold, "cals": b.n_cals, "cells": leg.cells,
@@ -515,7 +542,7 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD, parity:
 
 
 def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9), step_cals: int = 1 << 20):
-    """Config 5: two resident references, Poisson arrivals of log-uniform request
+    """Served requests: two resident references, Poisson arrivals of log-uniform request
     sizes, p50/p99 latency (scheduled arrival -> completion) at three loads
     relative to the measured saturated throughput."""
     import threading
@@ -524,7 +551,7 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
     from paper_1805_00106_amd import workloads as wl
 
     t_gen = time.perf_counter()
-    refs = wl.config5_references(scale=scale)
+    refs = wl.served_references(scale=scale)
     pack = wl.concat_aligned(refs)
     refs = [pack[0][int(o):int(o) + int(n)] for o, n in zip(pack[1], pack[2])]  # views, no second copy
     codes = torch.from_numpy(pack[0]).cuda()
@@ -532,8 +559,8 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
     torch.cuda.synchronize()
     del codes
     torch.cuda.empty_cache()
-    _, sizes = wl.config5_arrivals(1.0, pool_size, seed=0)
-    pool = [wl.config5_request(refs, int(n), 10_000 + k, ref_pack=pack) for k, n in enumerate(sizes)]
+    _, sizes = wl.served_arrivals(1.0, pool_size, seed=0)
+    pool = [wl.served_request(refs, int(n), 10_000 + k, ref_pack=pack) for k, n in enumerate(sizes)]
     pool_cells = [cells_of(b) for b in pool]
     t_gen = time.perf_counter() - t_gen
     sc = sw.Scoring.make(2, -3, 5, 2, 32, sw.PREC_AUTO, max_read_len=250)
@@ -605,7 +632,7 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
                         "achieved_gcups": round(sum(pool_cells[k] for k in picks) / span / 1e9, 1)})
     stats = srv.stats()
     srv.close()
-    return {"workload": f"config5: resident references of {int(pack[2][0]):,} and {int(pack[2][1]):,} bp "
+    return {"workload": f"served requests: resident references of {int(pack[2][0]):,} and {int(pack[2][1]):,} bp "
                         f"(random + 5% planted repeats, {sum(int(x) for x in pack[2]) / 4e9:.2f} GB 2-bit), "
                         f"Poisson arrivals, requests log-uniform 1..10000 reads (pool of {pool_size}), "
                         "L U{75..250}, CALs U{1..32} per read, band 32, both strands",
@@ -627,10 +654,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--reads", type=int, default=1_000_000)
-    ap.add_argument("--config3-reads", type=int, default=2_000_000,
+    ap.add_argument("--uneven-reads", type=int, default=2_000_000,
                     help="reads of the uneven-length leg (0 skips it)")
-    ap.add_argument("--config3-bands", default="16,32,64", help="bands of the uneven-length leg")
-    ap.add_argument("--config4-reads", type=int, default=4_000_000,
+    ap.add_argument("--uneven-bands", default="16,32,64", help="bands of the uneven-length leg")
+    ap.add_argument("--two-ref-reads", type=int, default=4_000_000,
                     help="reads of the two-reference classification leg (0 skips it)")
     ap.add_argument("--serve-scale", type=float, default=0.0,
                     help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0, the default, "
@@ -641,7 +668,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pipeline", type=int, default=1, help="1: also time seeds -> CALs -> filter -> score")
-    ap.add_argument("--variants", type=int, default=1, help="1: also time int32 and final-row scoring, config 1")
+    ap.add_argument("--variants", type=int, default=1, help="1: also time int32 and final-row scoring and the small-reference workload")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run an elementwise copy of this size (counter calibration for profiles)")
@@ -657,11 +684,11 @@ def main():
 
     torch.cuda.set_device(0)
     t_gen = time.perf_counter()
-    batch = wl.config2(n_reads=args.reads)
+    batch = wl.chromosome_scale(n_reads=args.reads)
     t_gen = time.perf_counter() - t_gen
     leg = Leg(batch, int(batch.read_len.max()), args.steps, args.warmup)
     r2 = leg.run()
-    progress(f"config2: batched {r2['batched_gcups']} GCUPS, plain {r2['plain_gcups']} GCUPS")
+    progress(f"chromosome scale: batched {r2['batched_gcups']} GCUPS, plain {r2['plain_gcups']} GCUPS")
     parity = None if args.no_parity else parity_sample(batch, leg.out)
     leg.parity_reads = not args.no_parity
     e2e = leg.end_to_end()
@@ -685,17 +712,17 @@ def main():
         del src, dst
 
     c3 = None
-    if args.config3_reads:
-        base3 = wl.config3(n_reads=args.config3_reads, band=32)  # reads and CALs do not depend on the band
+    if args.uneven_reads:
+        base3 = wl.uneven_lengths(n_reads=args.uneven_reads, band=32)  # reads and CALs do not depend on the band
         c3 = {}
-        for band in [int(x) for x in args.config3_bands.split(",")]:
+        for band in [int(x) for x in args.uneven_bands.split(",")]:
             b3 = dataclasses.replace(base3, scoring=dataclasses.replace(base3.scoring, band=band),
-                                     name=f"config3_band{band}")
+                                     name=f"uneven_lengths_band{band}")
             leg3 = Leg(b3, 250, max(3, args.steps // 4), 1)
             r3 = leg3.run()
             p3 = None if args.no_parity else parity_sample(b3, leg3.out)
             c3[f"band{band}"] = {
-                "workload": f"config3: same reference, {b3.n_reads} reads with L uniform 75..250, geometric CALs "
+                "workload": f"uneven lengths: same 100 Mbp reference, {b3.n_reads} reads with L uniform 75..250, geometric CALs "
                             f"(mean 8, cap 64), band {band}, both strands, int16",
                 "cals": b3.n_cals, "cells": leg3.cells,
                 "plain_gcups": r3["plain_gcups"], "batched_gcups": r3["batched_gcups"],
@@ -706,10 +733,10 @@ def main():
                 "plain_equals_batched": r3["plain_equals_batched"], "parity_sample_ok": p3, "plan": r3["plan"]}
             leg3.free()
             del leg3
-            progress(f"config3 band {band}: batched {r3['batched_gcups']} GCUPS")
+            progress(f"uneven lengths band {band}: batched {r3['batched_gcups']} GCUPS")
 
-    c4 = classification_leg(args.config4_reads, parity=not args.no_parity) if args.config4_reads else None
-    progress("config4 done")
+    c4 = classification_leg(args.two_ref_reads, parity=not args.no_parity) if args.two_ref_reads else None
+    progress("two references done")
     served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests,
                         step_cals=args.serve_step_cals) if args.serve_scale > 0 else None
     if served:
@@ -718,7 +745,7 @@ def main():
     step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
     gcups = cells / (step_ms * 1e-3) / 1e9
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
-    traffic = load_traffic("inter16_queue", "config2")
+    traffic = load_traffic("inter16_queue", "chromosome_scale")
     import paper_1805_00106_amd as sw
     measured = sw.alu_peak(16) / 1e12  # sustained packed-int16 add/max rate on this device
     roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_INT16_TOPS, 2),
@@ -731,7 +758,7 @@ def main():
         "metric": METRIC, "value": round(gcups, 1), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int16", "data": "synthetic",
-        "config": {"workload": "config2: 100 Mbp reference (5% planted repeats), 1M x 100 bp reads, "
+        "config": {"workload": "chromosome scale: 100 Mbp reference (5% planted repeats), 1M x 100 bp reads, "
                                "Poisson(6)+1 CALs/read, band 32, both strands, int16",
                    "reads": n_reads, "cals": n_cals, "tasks": 2 * n_cals, "cells": cells,
                    "path": "batched (length bins, persistent queue, HIP graph)", "plan": r2["plan"]},
@@ -743,7 +770,7 @@ def main():
         "small_batch_latency": small,
         "end_to_end_with_pcie": e2e,
         "variants": variants,
-        "config1": config1_leg() if args.variants else None,
+        "small_reference": small_reference_leg() if args.variants else None,
         "traceback": trace,
         "seed_to_score": pipe,
         "aligned_fraction": round(r2["aligned_fraction"], 4), "aligned_threshold": ALIGNED_THRESHOLD,
@@ -751,9 +778,9 @@ def main():
         "roofline": roof,
     }
     if c3:
-        res["config3"] = c3
+        res["uneven_lengths"] = c3
     if c4:
-        res["config4"] = c4
+        res["two_references"] = c4
     if not served:
         res["served"] = {"skipped": "served path kept off the GPU: three runs that included it ended with "
                                     "the GPU faulted, cause not shown"}

@@ -338,7 +338,7 @@ def _shuffle_rows(rng, counts, *arrays):
 
 # --------------------------------------------------------------------------- configs
 
-def config1(n_reads: int = 1000, ref_len: int = 10_000, read_len: int = 76) -> Batch:
+def small_reference(n_reads: int = 1000, ref_len: int = 10_000, read_len: int = 76) -> Batch:
     """Plain, small: 10 kbp uniform reference, 76 bp reads, true locus + 1 decoy CAL."""
     g = seed_streams(1)
     genome = uniform_genome(g["reference"], ref_len)
@@ -352,7 +352,7 @@ def config1(n_reads: int = 1000, ref_len: int = 10_000, read_len: int = 76) -> B
     cal_pos, cal_ref, strand = _shuffle_rows(g["cals"], counts, cal_pos, cal_ref, strand)
     sc = Scoring(2, -3, 5, 2, 32)
     return _vector_batch([genome], mat, lens, counts, cal_pos, cal_ref, strand,
-                         sc, np.zeros(n_reads, np.int64), pos, rev.astype(np.int64), "config1")
+                         sc, np.zeros(n_reads, np.int64), pos, rev.astype(np.int64), "small_reference")
 
 
 def _repeat_genome(config_index: int, ref_len: int, repeat_fraction: float = 0.05):
@@ -421,7 +421,7 @@ def _multi_cal_batch(g, genome, copies, n_reads, lens, counts, band, name, sc_in
                          sc, np.zeros(n_reads, np.int64), pos, rev.astype(np.int64), name)
 
 
-def config2(n_reads: int = 1_000_000, ref_len: int = 100_000_000, read_len: int = 100,
+def chromosome_scale(n_reads: int = 1_000_000, ref_len: int = 100_000_000, read_len: int = 100,
             reads_seed: int = 0) -> Batch:
     """Plain, chromosome scale: 100 Mbp with 5% planted repeats, 100 bp reads,
     Poisson(6)+1 CALs (true locus, repeat homologs, uniform decoys), band 32."""
@@ -429,10 +429,10 @@ def config2(n_reads: int = 1_000_000, ref_len: int = 100_000_000, read_len: int 
     g = seed_streams(2, 1 + reads_seed)
     lens = np.full(n_reads, read_len, dtype=np.int64)
     counts = g["cals"].poisson(6.0, n_reads).astype(np.int64) + 1
-    return _multi_cal_batch(g, genome, copies, n_reads, lens, counts, 32, "config2")
+    return _multi_cal_batch(g, genome, copies, n_reads, lens, counts, 32, "chromosome_scale")
 
 
-def config3(n_reads: int = 2_000_000, ref_len: int = 100_000_000, band: int = 32,
+def uneven_lengths(n_reads: int = 2_000_000, ref_len: int = 100_000_000, band: int = 32,
             reads_seed: int = 0) -> Batch:
     """Batched, uneven: same reference, L uniform in [75, 250], CAL count
     geometric with mean 8 capped at 64, band in {16, 32, 64}."""
@@ -440,10 +440,10 @@ def config3(n_reads: int = 2_000_000, ref_len: int = 100_000_000, band: int = 32
     g = seed_streams(3, 1 + reads_seed)
     lens = g["reads"].integers(75, 251, n_reads).astype(np.int64)
     counts = np.minimum(g["cals"].geometric(1.0 / 8.0, n_reads), 64).astype(np.int64)
-    return _multi_cal_batch(g, genome, copies, n_reads, lens, counts, band, f"config3_band{band}")
+    return _multi_cal_batch(g, genome, copies, n_reads, lens, counts, band, f"uneven_lengths_band{band}")
 
 
-def config4(n_reads: int = 4_000_000, ref_len: int = 500_000_000, read_len: int = 150,
+def two_references(n_reads: int = 4_000_000, ref_len: int = 500_000_000, read_len: int = 150,
             reads_seed: int = 0) -> Batch:
     """Two-reference classification: A uniform, B = A + 15% substitutions + 2%/base
     indel events; reads 70% from B, 30% from A; per reference the homologous locus
@@ -492,7 +492,7 @@ def config4(n_reads: int = 4_000_000, ref_len: int = 500_000_000, read_len: int 
                                                     dec.astype(np.uint8))
     sc = Scoring(2, -3, 5, 2, 32)
     b = _vector_batch([A, B], mat, lens, counts, cal_pos, cal_ref, strand, sc,
-                      from_b.astype(np.int64), src_pos, rev.astype(np.int64), "config4")
+                      from_b.astype(np.int64), src_pos, rev.astype(np.int64), "two_references")
     b.cal_decoy = decoy
     return b
 
@@ -544,7 +544,7 @@ def random_small_batch(seed: int, n_refs: int = 2, ref_len=(40, 400), n_reads: i
 
 # --------------------------------------------------------------------------- serving
 
-def config5_references(scale: float = 1.0):
+def served_references(scale: float = 1.0):
     """Two resident references (3.2 Gbp and 2.7 Gbp at scale 1), random with 5%
     planted repeats."""
     g = seed_streams(5)
@@ -556,7 +556,7 @@ def config5_references(scale: float = 1.0):
     return out
 
 
-def config5_arrivals(rate_per_s: float, n_requests: int, seed: int = 0):
+def served_arrivals(rate_per_s: float, n_requests: int, seed: int = 0):
     """Poisson arrival times (seconds) and request sizes, log-uniform on [1, 10000] reads."""
     g = seed_streams(5, 100 + seed)
     gaps = g["arrivals"].exponential(1.0 / rate_per_s, n_requests)
@@ -566,7 +566,7 @@ def config5_arrivals(rate_per_s: float, n_requests: int, seed: int = 0):
     return t, sizes
 
 
-def config5_request(refs, n_reads: int, seed: int, band: int = 32, ref_pack=None) -> Batch:
+def served_request(refs, n_reads: int, seed: int, band: int = 32, ref_pack=None) -> Batch:
     """One served request: reads of length U{75..250} with U{1..32} CALs on random
     references (the first CAL is the true locus).  ``ref_pack`` = (codes, offsets,
     lengths) of the concatenated references, shared instead of copied."""

@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE, run by hand (pytest does not collect it):
 
-    python tests/full_size_parity.py config3 --band 16
-    python tests/full_size_parity.py config4 --reads 4000000
+    python tests/full_size_parity.py uneven_lengths --band 16
+    python tests/full_size_parity.py two_references --reads 4000000
 
 The whole batch is scored once on the GPU (batched context, per-read best);
 the oracle then scores it in chunks of reads on the host cores, and every slot
@@ -27,22 +27,22 @@ from paper_1805_00106_amd import workloads as wl  # noqa: E402
 
 
 def make_batch(name, reads, band):
-    if name == "config1":
-        return wl.config1(), sw.PREC_INT32, 76
-    if name == "config2":
-        return wl.config2(n_reads=reads or 1_000_000), sw.PREC_INT16, 100
-    if name == "config3":
-        return wl.config3(n_reads=reads or 2_000_000, band=band), sw.PREC_INT16, 250
-    if name == "config4":
-        return wl.config4(n_reads=reads or 4_000_000), sw.PREC_INT16, 150
+    if name == "small_reference":
+        return wl.small_reference(), sw.PREC_INT32, 76
+    if name == "chromosome_scale":
+        return wl.chromosome_scale(n_reads=reads or 1_000_000), sw.PREC_INT16, 100
+    if name == "uneven_lengths":
+        return wl.uneven_lengths(n_reads=reads or 2_000_000, band=band), sw.PREC_INT16, 250
+    if name == "two_references":
+        return wl.two_references(n_reads=reads or 4_000_000), sw.PREC_INT16, 150
     raise SystemExit(f"unknown workload {name}")
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["config1", "config2", "config3", "config4"])
+    ap.add_argument("workload", choices=["small_reference", "chromosome_scale", "uneven_lengths", "two_references"])
     ap.add_argument("--reads", type=int, default=0, help="reads (0: the workload's full size)")
-    ap.add_argument("--band", type=int, default=32, help="band of config3")
+    ap.add_argument("--band", type=int, default=32, help="band of uneven_lengths")
     ap.add_argument("--chunk", type=int, default=100_000, help="reads per oracle chunk")
     args = ap.parse_args()
     threads = min(16, os.cpu_count() or 1)

@@ -50,18 +50,18 @@ def test_ctx_random_ragged(seed, precision):
 
 
 @pytest.mark.parametrize("band", [16, 32, 64])
-def test_ctx_config3_shape(band):
-    """Config 3 generator (L uniform 75..250, geometric CAL counts capped at 64)."""
-    b = wl.config3(n_reads=1200, band=band)
+def test_ctx_uneven_lengths_shape(band):
+    """Uneven-lengths generator (L uniform 75..250, geometric CAL counts capped at 64)."""
+    b = wl.uneven_lengths(n_reads=1200, band=band)
     exp, _ = oracle_align(b)
     res, plan = _ctx_run(b, sw.PREC_INT16, max_read_len=250, repeats=2)
     for r in res:
-        assert_same(r, exp, f"config3 band {band} ({plan})")
+        assert_same(r, exp, f"uneven_lengths band {band} ({plan})")
     assert "longest first" in plan or "shortest first" in plan
 
 
-def test_ctx_equals_plain_on_config2_shape():
-    b = wl.config2(n_reads=20000)
+def test_ctx_equals_plain_on_chromosome_scale_shape():
+    b = wl.chromosome_scale(n_reads=20000)
     plain = gpu_align(b, sw.PREC_INT16, reduce=False)
     res, plan = _ctx_run(b, sw.PREC_INT16, repeats=2)
     for r in res:

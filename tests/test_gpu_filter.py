@@ -51,8 +51,8 @@ def test_filter_many_cals_one_read_and_empty_reads():
         _compare(b, bits)
 
 
-def test_filter_config2_scores_through_map():
-    base = wl.config2(n_reads=2000)
+def test_filter_chromosome_scale_scores_through_map():
+    base = wl.chromosome_scale(n_reads=2000)
     b = wl.with_duplicate_cals(base, 5, jitter_frac=0.0)
     db, kept, cmap = _compare(b, 0)
     refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)

@@ -31,20 +31,20 @@ def _case(batch, precision, **kw):
     assert_same(got, exp, f"{batch.name} prec={precision} {kw}")
 
 
-def test_config1_int32_full():
-    """Config 1 exactly as stated: 1000 x 76 bp reads, 2 CALs, both strands, int32."""
-    _case(wl.config1(), sw.PREC_INT32)
+def test_small_reference_int32_full():
+    """Small-reference workload: 1000 x 76 bp reads, 2 CALs, both strands, int32."""
+    _case(wl.small_reference(), sw.PREC_INT32)
 
 
-def test_config1_int16():
-    _case(wl.config1(), sw.PREC_INT16)
+def test_small_reference_int16():
+    _case(wl.small_reference(), sw.PREC_INT16)
 
 
 def test_auto_kernel_choice_small_and_large():
     """AUTO picks the wavefront-per-task kernel for tiny batches, one CAL per lane otherwise."""
     small = wl.random_small_batch(50, n_reads=20, read_len=(30, 150), band=20)
     _case(small, sw.PREC_AUTO, kernel=sw.KERNEL_AUTO)
-    _case(wl.config1(n_reads=2000), sw.PREC_AUTO, kernel=sw.KERNEL_AUTO)
+    _case(wl.small_reference(n_reads=2000), sw.PREC_AUTO, kernel=sw.KERNEL_AUTO)
 
 
 @pytest.mark.parametrize("seed", range(3))
@@ -123,15 +123,15 @@ def test_three_references_reduce_and_classify():
         np.testing.assert_array_equal(cls, orc.classify(exp["best_score"], thr))
 
 
-def test_config2_shape_moderate():
-    """Config 2 generator (100 Mbp reference with repeats, 100 bp reads, Poisson(6)+1
+def test_chromosome_scale_shape_moderate():
+    """Chromosome-scale generator (100 Mbp reference with repeats, 100 bp reads, Poisson(6)+1
     CALs, band 32, int16) at 5000 reads: full oracle parity."""
-    _case(wl.config2(n_reads=5000), sw.PREC_INT16)
+    _case(wl.chromosome_scale(n_reads=5000), sw.PREC_INT16)
 
 
-def test_config3_shape_moderate():
-    """Config 3 generator (L uniform 75..250, geometric CAL counts) at 1500 reads."""
-    b = wl.config3(n_reads=1500, band=64)
+def test_uneven_lengths_shape_moderate():
+    """Uneven-lengths generator (L uniform 75..250, geometric CAL counts) at 1500 reads."""
+    b = wl.uneven_lengths(n_reads=1500, band=64)
     _case(b, sw.PREC_INT16, max_read_len=250)
 
 

@@ -27,7 +27,7 @@ _REFS = None
 def refs_and_pack():
     global _REFS
     if _REFS is None:
-        refs = wl.config5_references(scale=0.002)        # 6.4 + 5.4 Mbp stand-ins
+        refs = wl.served_references(scale=0.002)        # 6.4 + 5.4 Mbp stand-ins
         pack = wl.concat_aligned(refs)
         _REFS = (refs, pack)
     return _REFS
@@ -37,7 +37,7 @@ def requests(n, seed0, sizes=None):
     refs, pack = refs_and_pack()
     rng = np.random.default_rng(seed0)
     sizes = sizes or [int(x) for x in np.clip(np.exp(rng.uniform(0, np.log(400), n)), 1, 400)]
-    return [wl.config5_request(refs, s, seed0 * 1000 + k, ref_pack=pack) for k, s in enumerate(sizes)]
+    return [wl.served_request(refs, s, seed0 * 1000 + k, ref_pack=pack) for k, s in enumerate(sizes)]
 
 
 def make_server(budget=256 << 20, max_step_reads=4096, max_step_cals=60000):

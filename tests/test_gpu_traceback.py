@@ -80,9 +80,9 @@ def test_trace_very_long_reads():
     _case(b, max_read_len=1000, cap=256)
 
 
-def test_trace_config2_best_slots():
-    """Config 2 generator: trace each read's best slot (the usual caller)."""
-    b = wl.config2(n_reads=3000)
+def test_trace_chromosome_scale_best_slots():
+    """Chromosome-scale generator: trace each read's best slot (the usual caller)."""
+    b = wl.chromosome_scale(n_reads=3000)
     exp, _ = oracle_align(b)
     slots = exp["best_slot"][:, 0].astype(np.int64)
     assert (slots >= 0).all()

@@ -38,8 +38,8 @@ def test_final_row_long_reads_many_tiles():
     _fr_case(b, max_read_len=250)
 
 
-def test_final_row_config2_shape():
-    _fr_case(wl.config2(n_reads=2000))
+def test_final_row_chromosome_scale_shape():
+    _fr_case(wl.chromosome_scale(n_reads=2000))
 
 
 def test_final_row_single_base_and_homopolymers():
@@ -48,7 +48,7 @@ def test_final_row_single_base_and_homopolymers():
 
 
 def test_final_row_batched_context_replays():
-    b = wl.config3(n_reads=600, band=32)
+    b = wl.uneven_lengths(n_reads=600, band=32)
     exp, _ = oracle_align(b, mode=FR)
     refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
     db = sw.DeviceBatch.upload(b)

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 
 def test_usage_example_flow():
-    b = wl.config2(n_reads=2000)
+    b = wl.chromosome_scale(n_reads=2000)
     refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
     db = sw.DeviceBatch.upload(b)
     sc = sw.Scoring.make(2, -3, 5, 2, band=32, max_read_len=100)
