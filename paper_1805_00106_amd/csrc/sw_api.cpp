@@ -96,7 +96,7 @@ static int strip_candidates32[] = {
 #undef SW_LIST
 };
 
-int choose_strip_rows(bool int16, int rows) {
+int choose_strip_rows(bool int16, int rows, bool final_row) {
   const int *cand = int16 ? strip_candidates16 : strip_candidates32;
   const int n = int16 ? (int)(sizeof(strip_candidates16) / sizeof(int))
                       : (int)(sizeof(strip_candidates32) / sizeof(int));
@@ -104,6 +104,8 @@ int choose_strip_rows(bool int16, int rows) {
   int64_t best_cost = INT64_MAX;
   for (int i = 0; i < n; ++i) {
     const int R = cand[i];
+    // int16 final-row strips above 44 rows exceed the 256-register budget of two waves per SIMD
+    if (int16 && final_row && R > 44) continue;
     const int64_t cost = (int64_t)((rows + R - 1) / R) * R;
     if (cost < best_cost || (cost == best_cost && R > best)) {
       best_cost = cost;
@@ -184,7 +186,8 @@ int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainP
     p->bytes = p->scratch_off;
     return SW_OK;
   }
-  p->strip_rows = strip_override > 0 ? strip_override : choose_strip_rows(m.int16, m.max_read_len);
+  p->strip_rows = strip_override > 0 ? strip_override
+                                     : choose_strip_rows(m.int16, m.max_read_len, sc->mode == SW_MODE_FINAL_ROW);
   if (!strip_rows_supported(m.int16, p->strip_rows)) return SW_ERR_INVALID_ARG;
   p->n_tasks = m.int16 ? n_cals : 2 * n_cals;
   const int64_t n_tiles = (p->n_tasks + 63) / 64;

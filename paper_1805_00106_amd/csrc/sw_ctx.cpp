@@ -125,8 +125,8 @@ swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t, bool fi
   const int n = m.int16 ? (int)(sizeof(kQueueStrips16) / sizeof(int)) : (int)(sizeof(kQueueStrips32) / sizeof(int));
   P.n_strips = 0;
   for (int i = 0; i < n; ++i) {
-    // the int16 final-row queue kernel has no 50-row variant (register budget)
-    if (m.int16 && final_row && s[i] > 48) continue;
+    // the int16 final-row queue kernel has no strips above 44 rows (register budget)
+    if (m.int16 && final_row && s[i] > 44) continue;
     P.strips[P.n_strips++] = s[i];
   }
   return P;

@@ -296,8 +296,9 @@ __device__ __forceinline__ void fold16_row(v2s m, int row, int tb, uint64_t &bes
 // starts at read row 0 (top boundary H = 0); LAST: no strip follows (nothing
 // is written to the scratch rows).  FR: final-row mode (only row L-1 may hold
 // the best cell); a template parameter so that the local mode keeps its
-// register budget.
-template <int R, bool FIRST, bool LAST, bool FR>
+// register budget.  TRACK: keep the per-row maxima; a final-row strip that holds
+// no lane's last row skips them (one packed op per cell of twelve).
+template <int R, bool FIRST, bool LAST, bool FR, bool TRACK = true>
 __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
                                         int lane, int r0, int L, int W, int Wmin, int Wmax, uint64_t &best_f,
                                         uint64_t &best_r) {
@@ -376,19 +377,19 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
         F = vmax(f2, v);
         E[r] = vmax(e2, u);
         if (r + 1 < R) p = vmax(t, ZT);
-        M[r] = vmax(M[r], H);
+        if (!FR || TRACK) M[r] = vmax(M[r], H);
         Hl[r] = H;
       }
       if (!LAST) scr[c * 64 + lane] = make_uint2(bits(Hl[R - 1]), bits(F));
     }
-    if (FR) {
+    if (FR && TRACK) {
       // read-end-anchored scoring: only row L-1 may hold the best cell
       const int rr = L - 1 - r0;
       v2s m = pair(0u);
 #pragma unroll
       for (int r = 0; r < R; ++r) m = r == rr ? M[r] : m;
       fold16_row(m, L - 1, tb, best_f, best_r);
-    } else {
+    } else if (!FR) {
       fold16<R>(M, r0, tb, best_f, best_r);
     }
     if (tend < Wmax) {
@@ -421,6 +422,19 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
 // every substitution is -256, so those rows only decrease and are never
 // reported.  Columns past the lane's window use a table of 0x8000 (a wall).
 
+// One strip of a tile: in final-row mode the row maxima are kept only if some
+// lane's last read row lies in the strip (a wave-uniform choice).
+template <int R, bool FIRST, bool LAST, bool FR>
+__device__ __forceinline__ void strip16_sel(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
+                                            int lane, int r0, int L, int W, int Wmin, int Wmax, uint64_t &best_f,
+                                            uint64_t &best_r) {
+  if (FR && __ballot(L > 0 && L - 1 >= r0 && L - 1 < r0 + R) == 0ull) {
+    strip16<R, FIRST, LAST, FR, false>(K, win, rdw, scr, lane, r0, L, W, Wmin, Wmax, best_f, best_r);
+    return;
+  }
+  strip16<R, FIRST, LAST, FR, true>(K, win, rdw, scr, lane, r0, L, W, Wmin, Wmax, best_f, best_r);
+}
+
 // One tile of up to 64 CALs (task positions [first, first + count)).
 template <int R, bool FR>
 __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off, const int64_t *rt_len,
@@ -443,12 +457,12 @@ __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off
   uint64_t best_f = 0, best_r = 0;
   const int nstrips = (Lmax + R - 1) / R;
   if (nstrips == 1) {
-    strip16<R, true, true, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    strip16_sel<R, true, true, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
   } else {
-    strip16<R, true, false, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    strip16_sel<R, true, false, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
     for (int s = 1; s + 1 < nstrips; ++s)
-      strip16<R, false, false, FR>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
-    strip16<R, false, true, FR>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
+      strip16_sel<R, false, false, FR>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
+    strip16_sel<R, false, true, FR>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
   }
   if (L > 0) {
     if (t.mask & 1) write_result(A, 2 * t.c, best_f, t.ws);
@@ -488,11 +502,11 @@ __global__ __launch_bounds__(64) void k_inter16_queue(const AlignArgs A, const R
   int count;
   while (next_tile(A, it, first, count, ti)) {
     switch (A.tile_strips[ti]) {
-  // the final-row fold needs a few more registers: the planner gives its tiles no
-  // 50-row strips, and a 50-row tile would still run correctly as 48-row strips
+  // the final-row strips need a few more registers: the planner gives its tiles no
+  // strips above 44 rows, and such a tile would still run correctly as 44-row strips
 #define SW_Q16_CASE(RR)                                                                         \
   case RR:                                                                                      \
-    tile16<(FR && RR > 48 ? 48 : RR), FR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
+    tile16<(FR && RR > 44 ? 44 : RR), FR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
     break;
       SW_QUEUE16_STRIPS(SW_Q16_CASE)
 #undef SW_Q16_CASE
