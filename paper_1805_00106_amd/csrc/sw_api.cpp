@@ -42,7 +42,8 @@ int validate_scoring(const sw_scoring_t *sc, ScoreMode *mode) {
   const int64_t top = (int64_t)sc->match * mrl;
   if (top > (1 << 19) - 2 || -(int64_t)sc->mismatch > (1 << 18) || goe2 > (1 << 18)) return SW_ERR_SCORING;
   // int16 path: values are V * 64 + tag in int16; the bound needs V <= 510 everywhere
-  const bool fits16 = top <= 510 && sc->mismatch >= -511 && goe2 <= 511;
+  int32_t kb = 0, beta = 0;
+  const bool fits16 = top <= 510 && sc->mismatch >= -511 && goe2 <= 511 && int16_layout(sc, &kb, &beta);
   bool int16;
   if (sc->precision == SW_PREC_INT16) {
     if (!fits16) return SW_ERR_BOUND;
@@ -58,22 +59,48 @@ int validate_scoring(const sw_scoring_t *sc, ScoreMode *mode) {
   return SW_OK;
 }
 
+int int16_layout(const sw_scoring_t *sc, int32_t *kbits, int32_t *beta) {
+  const int64_t mrl = sc->max_read_len == 0 ? SW_MAX_READ_LEN : sc->max_read_len;
+  const int64_t top = (int64_t)sc->match * mrl;
+  const int64_t goe = (int64_t)sc->gap_open + sc->gap_extend;
+  for (int K = 6; K >= 4; --K) {
+    const int64_t U = (int64_t)1 << K;
+    // beta covers the largest single penalty (gap opening plus one, as the gap
+    // terms of the last column of a tile carry the tag -1) and the -256 of the
+    // padding rows
+    const int64_t b = std::max<int64_t>(std::max<int64_t>(-(int64_t)sc->mismatch, goe + 1), (256 + U - 1) / U);
+    if (b <= 0x7BFF && (b + top + 1) * U <= 0x7BFF) {
+      *kbits = K;
+      *beta = (int32_t)b;
+      return 1;
+    }
+  }
+  return 0;
+}
+
 DpConstHost make_consts(const sw_scoring_t *sc) {
   swk::DpConst k{};
   const int32_t goe = sc->gap_open + sc->gap_extend, ge = sc->gap_extend;
   auto pk = [](int32_t v) { return ((uint32_t)(uint16_t)(int16_t)v) * 0x00010001u; };
-  k.goe_e16 = pk(goe * 64 + 1);
-  k.ge_e16 = pk(ge * 64 + 1);
-  k.goe_f16 = pk(goe * 64);
-  k.ge_f16 = pk(ge * 64);
-  const uint16_t sm = (uint16_t)(int16_t)(sc->match * 64 - 1);
-  const uint16_t sx = (uint16_t)(int16_t)(sc->mismatch * 64 - 1);
+  // int16 pairs: the widest tag (K) whose biased values stay below 0x7C00
+  int32_t kbits = 4, beta = 0;
+  int16_layout(sc, &kbits, &beta);
+  const int32_t U = 1 << kbits;
+  k.goe_e16 = pk(goe * U + 1);
+  k.ge_e16 = pk(ge * U + 1);
+  k.goe_f16 = pk(goe * U);
+  k.ge_f16 = pk(ge * U);
+  k.tag16 = pk(U);
+  k.bias16 = pk(beta * U);
+  k.kbits16 = kbits;
+  k.beta16 = beta;
+  const uint16_t sm = (uint16_t)(int16_t)(sc->match * U - 1);
+  const uint16_t sx = (uint16_t)(int16_t)(sc->mismatch * U - 1);
   const uint32_t lo_m = sm & 0xFF, hi_m = sm >> 8, lo_x = sx & 0xFF, hi_x = sx >> 8;
   k.xlo = lo_x * 0x01010101u;
   k.dlo = lo_x ^ lo_m;
   k.xhi = hi_x * 0x01010101u;
   k.dhi = hi_x ^ hi_m;
-  k.e0_16 = 0;
   k.goe_e32 = goe * 4096 + 1;
   k.ge_e32 = ge * 4096 + 1;
   k.goe_f32 = goe * 4096;
@@ -96,7 +123,7 @@ static int strip_candidates32[] = {
 #undef SW_LIST
 };
 
-int choose_strip_rows(bool int16, int rows, bool final_row) {
+int choose_strip_rows(bool int16, int rows) {
   const int *cand = int16 ? strip_candidates16 : strip_candidates32;
   const int n = int16 ? (int)(sizeof(strip_candidates16) / sizeof(int))
                       : (int)(sizeof(strip_candidates32) / sizeof(int));
@@ -104,8 +131,6 @@ int choose_strip_rows(bool int16, int rows, bool final_row) {
   int64_t best_cost = INT64_MAX;
   for (int i = 0; i < n; ++i) {
     const int R = cand[i];
-    // int16 final-row strips above 44 rows exceed the 256-register budget of two waves per SIMD
-    if (int16 && final_row && R > 44) continue;
     const int64_t cost = (int64_t)((rows + R - 1) / R) * R;
     if (cost < best_cost || (cost == best_cost && R > best)) {
       best_cost = cost;
@@ -187,7 +212,7 @@ int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainP
     return SW_OK;
   }
   p->strip_rows = strip_override > 0 ? strip_override
-                                     : choose_strip_rows(m.int16, m.max_read_len, sc->mode == SW_MODE_FINAL_ROW);
+                                     : choose_strip_rows(m.int16, m.max_read_len);
   if (!strip_rows_supported(m.int16, p->strip_rows)) return SW_ERR_INVALID_ARG;
   p->n_tasks = m.int16 ? n_cals : 2 * n_cals;
   const int64_t n_tiles = (p->n_tasks + 63) / 64;

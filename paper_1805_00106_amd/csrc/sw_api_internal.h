@@ -38,7 +38,9 @@ int validate_batch(const uint32_t *reads2bit, const int64_t *read_word_off, cons
                    const uint8_t *strand, int64_t n_cals, int32_t *score, int64_t *ref_end,
                    int16_t *read_end);
 DpConstHost make_consts(const sw_scoring_t *sc);
-int choose_strip_rows(bool int16, int rows, bool final_row);
+// int16 pairs: tag bits K (6, 5 or 4) and bias beta of the scoring; 0 if none fits
+int int16_layout(const sw_scoring_t *sc, int32_t *kbits, int32_t *beta);
+int choose_strip_rows(bool int16, int rows);
 int strip_rows_supported(bool int16, int R);
 int device_cus();
 int blocks_per_cu(bool int16, int R);

@@ -114,7 +114,7 @@ struct CallArgs {
   int16_t *read_end;
 };
 
-swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t, bool final_row) {
+swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t) {
   swk::BinParams P{};
   P.bin_width = t.bin_width;
   P.max_read_len = m.max_read_len;
@@ -124,11 +124,7 @@ swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t, bool fi
   const int *s = m.int16 ? kQueueStrips16 : kQueueStrips32;
   const int n = m.int16 ? (int)(sizeof(kQueueStrips16) / sizeof(int)) : (int)(sizeof(kQueueStrips32) / sizeof(int));
   P.n_strips = 0;
-  for (int i = 0; i < n; ++i) {
-    // the int16 final-row queue kernel has no strips above 44 rows (register budget)
-    if (m.int16 && final_row && s[i] > 44) continue;
-    P.strips[P.n_strips++] = s[i];
-  }
+  for (int i = 0; i < n; ++i) P.strips[P.n_strips++] = s[i];
   return P;
 }
 
@@ -153,7 +149,7 @@ int enqueue(sw_ctx *c, const CallArgs &a, const swapi::ScoreMode &m, const swk::
   if (e != hipSuccess) return swapi::hip_fail(e);
   e = swk::launch_expand(a.cal_ptr, a.n_reads, a.n_cals, c->B.cal_read, st);
   if (e != hipSuccess) return swapi::hip_fail(e);
-  const swk::BinParams P = bin_params(m, t, a.sc->mode == SW_MODE_FINAL_ROW);
+  const swk::BinParams P = bin_params(m, t);
   e = swk::launch_batch_plan(c->B, a.read_len, a.n_reads, n_tasks, P, st);
   if (e != hipSuccess) return swapi::hip_fail(e);
   swk::AlignArgs A{};

@@ -24,9 +24,25 @@ struct RefTable {
 // a window base (diagonal, horizontal gap) carries an extra -1; vertical gap
 // moves carry none.  With these constants every term reaching a cell carries
 // that cell's tag, and the maximum needs no separate position bookkeeping.
+//
+// The int16 pairs also carry a bias: N = (V + beta) * 2^K + tag(c), with beta
+// at least the largest single penalty (|mismatch|, gap_open + gap_extend + 1
+// for the gap terms of a tile's last column, whose tag is -1, and the 256 of
+// the padding rows), so that every operand of the three-way maxima of the
+// sweep is a non-negative int16 below 0x7C00.  On those bit patterns the packed
+// half-precision maximum orders exactly as the integer one (they are the finite
+// non-negative halves, in increasing order), so H = max(diagonal, E, F) and the
+// clamped gap term E = max(E - ge, H - go - ge, 0) are one v_pk_maximum3_f16
+// each; a wall column (substitution 0x8000) makes the diagonal operand a
+// negative half, below every other operand.  K is the largest of 6, 5, 4 for
+// which (beta + match * max_read_len + 1) * 2^K stays below 0x7C00.
 struct DpConst {
-  // int16 pairs (K = 6), both halves hold the same constant
-  uint32_t goe_e16, ge_e16, goe_f16, ge_f16, e0_16;
+  // int16 pairs, both halves hold the same constant
+  uint32_t goe_e16, ge_e16, goe_f16, ge_f16;
+  uint32_t tag16;    // 2^K
+  uint32_t bias16;   // beta * 2^K
+  int32_t kbits16;   // K
+  int32_t beta16;    // beta
   uint32_t xlo, dlo, xhi, dhi;  // substitution table bytes (see the kernel)
   // int32 (K = 12)
   int32_t goe_e32, ge_e32, goe_f32, ge_f32, sm32, sx32, e0_32;

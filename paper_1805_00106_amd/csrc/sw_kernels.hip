@@ -26,6 +26,18 @@ __device__ __forceinline__ uint32_t bits(v2s a) { return __builtin_bit_cast(uint
 __device__ __forceinline__ v2s pair(uint32_t a) { return __builtin_bit_cast(v2s, a); }
 __device__ __forceinline__ v2s vmax(v2s a, v2s b) { return __builtin_elementwise_max(a, b); }
 
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+// max(a, b, c) per half for int16 patterns in [0, 0x7BFF] (patterns of
+// [0x8000, 0xFBFF] rank below all of them): one v_pk_maximum3_f16, exact on
+// these patterns since they are the finite non-negative halves in increasing
+// order (and the negative ones below zero).
+__device__ __forceinline__ v2s vmax3h(v2s a, v2s b, v2s c) {
+  const v2h m = __builtin_elementwise_maximum(
+      __builtin_elementwise_maximum(__builtin_bit_cast(v2h, a), __builtin_bit_cast(v2h, b)),
+      __builtin_bit_cast(v2h, c));
+  return __builtin_bit_cast(v2s, m);
+}
+
 __device__ __forceinline__ int wave_max(int v) {
   for (int m = 32; m; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
   return v;
@@ -242,22 +254,28 @@ __device__ __forceinline__ void load_ref_table(const RefTable &T, int n_refs, in
 // (q, q|4) per half, so v_perm_b32 yields both halves' scores in one
 // instruction.  Rows past the read end use selector bytes 12/13 (0x00, 0xFF):
 // every substitution is -256, so those rows only decrease and are never
-// reported.  Columns past the lane's window use a table of 0x8000 (a wall).
+// reported.  Columns past the lane's window use a table of 0x8000 (a wall: the
+// diagonal operand becomes a negative half and never wins).
+//
+// Values are biased (N = (V + beta) * 2^K + tag, see DpConst), so the running
+// maxima start at 0 (below every cell) and V = (N >> K) - beta.
 
-// Fold the per-row maxima of one 64-column tile (tile base tb) into the
+// Fold the per-row maxima of one tile of 2^K columns (tile base tb) into the
 // lexicographic best keys of both halves.  The packed maximum over the rows
 // gives, per half, the best value and (through its tag) the smallest column;
 // the smallest row holding exactly that value is then found with a packed
 // equality scan.  Rows past the read end need no check: every value there
 // derives from the rows above minus a positive penalty (their substitutions
-// are -4), so it stays strictly below the best real cell and never wins.
+// are -256), so it stays strictly below the best real cell and never wins.
 template <int R>
-__device__ __forceinline__ void fold16(const v2s (&M)[R], int r0, int tb, uint64_t &best_f, uint64_t &best_r) {
+__device__ __forceinline__ void fold16(const DpConst &K, const v2s (&M)[R], int r0, int tb, volatile uint64_t *best) {
   v2s mx = M[0];
 #pragma unroll
   for (int r = 1; r < R; ++r) mx = vmax(mx, M[r]);
   const uint32_t mxb = bits(mx);
-  if ((mxb & 0xFFC0FFC0u) == 0) return;  // both halves at value 0 (V <= 0)
+  const int kb = K.kbits16, tmask = (1 << kb) - 1;
+  const int32_t vf = ((int32_t)(mxb & 0xFFFFu) >> kb) - K.beta16, vr = ((int32_t)(mxb >> 16) >> kb) - K.beta16;
+  if (vf <= 0 && vr <= 0) return;
   uint32_t rows = 0xFFFFFFFFu;
   const v2u ONE = __builtin_bit_cast(v2u, 0x00010001u);
 #pragma unroll
@@ -267,28 +285,28 @@ __device__ __forceinline__ void fold16(const v2s (&M)[R], int r0, int tb, uint64
     const uint32_t eq = __builtin_bit_cast(uint32_t, (v2u)(d - ONE));
     rows = (rows & ~eq) | ((uint32_t)r * 0x00010001u & eq);
   }
-  const int32_t vf = (int32_t)(int16_t)(mxb & 0xFFFFu), vr = (int32_t)(int16_t)(mxb >> 16);
-  if ((vf >> 6) > 0) {
-    const uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), r0 + (int32_t)(rows & 0xFFFFu));
-    best_f = kf > best_f ? kf : best_f;
+  if (vf > 0) {
+    const uint64_t kf = cell_key(vf, tb + tmask - (int32_t)(mxb & tmask), r0 + (int32_t)(rows & 0xFFFFu));
+    if (kf > best[0]) best[0] = kf;
   }
-  if ((vr >> 6) > 0) {
-    const uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), r0 + (int32_t)(rows >> 16));
-    best_r = kr > best_r ? kr : best_r;
+  if (vr > 0) {
+    const uint64_t kr = cell_key(vr, tb + tmask - (int32_t)((mxb >> 16) & tmask), r0 + (int32_t)(rows >> 16));
+    if (kr > best[64]) best[64] = kr;
   }
 }
 
 // Final-row mode: fold the maximum of one row (both halves on row `row`).
-__device__ __forceinline__ void fold16_row(v2s m, int row, int tb, uint64_t &best_f, uint64_t &best_r) {
+__device__ __forceinline__ void fold16_row(const DpConst &K, v2s m, int row, int tb, volatile uint64_t *best) {
   const uint32_t mb = bits(m);
-  const int32_t vf = (int32_t)(int16_t)(mb & 0xFFFFu), vr = (int32_t)(int16_t)(mb >> 16);
-  if ((vf >> 6) > 0) {
-    const uint64_t kf = cell_key(vf >> 6, tb + 63 - (vf & 63), row);
-    best_f = kf > best_f ? kf : best_f;
+  const int kb = K.kbits16, tmask = (1 << kb) - 1;
+  const int32_t vf = ((int32_t)(mb & 0xFFFFu) >> kb) - K.beta16, vr = ((int32_t)(mb >> 16) >> kb) - K.beta16;
+  if (vf > 0) {
+    const uint64_t kf = cell_key(vf, tb + tmask - (int32_t)(mb & tmask), row);
+    if (kf > best[0]) best[0] = kf;
   }
-  if ((vr >> 6) > 0) {
-    const uint64_t kr = cell_key(vr >> 6, tb + 63 - (vr & 63), row);
-    best_r = kr > best_r ? kr : best_r;
+  if (vr > 0) {
+    const uint64_t kr = cell_key(vr, tb + tmask - (int32_t)((mb >> 16) & tmask), row);
+    if (kr > best[64]) best[64] = kr;
   }
 }
 
@@ -300,11 +318,12 @@ __device__ __forceinline__ void fold16_row(v2s m, int row, int tb, uint64_t &bes
 // no lane's last row skips them (one packed op per cell of twelve).
 template <int R, bool FIRST, bool LAST, bool FR, bool TRACK = true>
 __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
-                                        int lane, int r0, int L, int W, int Wmin, int Wmax, uint64_t &best_f,
-                                        uint64_t &best_r) {
+                                        int lane, int r0, int L, int W, int Wmin, int Wmax,
+                                        volatile uint64_t *best) {
   const v2s GOE_E = pair(K.goe_e16), GE_E = pair(K.ge_e16);
   const v2s GOE_F = pair(K.goe_f16), GE_F = pair(K.ge_f16);
-  const v2s TAG64 = pair(0x00400040u);
+  const v2s TAGU = pair(K.tag16), BIAS = pair(K.bias16);
+  const int U = 1 << K.kbits16;
   uint32_t sel[R];
   v2s Hl[R], E[R], M[R];
 #pragma unroll
@@ -317,23 +336,25 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
     } else {
       sel[r] = 0x0D0C0D0Cu;
     }
-    Hl[r] = TAG64;
-    E[r] = TAG64 - GOE_E;
+    Hl[r] = TAGU + BIAS;
+    // E is kept clamped at zero (see below): column 0 starts at its zero
+    E[r] = TAGU + BIAS - pair(0x00010001u);
     M[r] = pair(0u);
   }
-  v2s hup_prev = TAG64;
+  v2s hup_prev = TAGU + BIAS;
   uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
   if (!FIRST) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     pf0 = scr[lane];
     if (Wmax > 1) pf1 = scr[64 + lane];
   }
-  for (int tb = 0; tb < Wmax; tb += 64) {
-    const int tend = min(tb + 64, Wmax);
+  for (int tb = 0; tb < Wmax; tb += U) {
+    const int tend = min(tb + U, Wmax);
     uint32_t wd = 0;
     for (int c = tb; c < tend; ++c) {
       const int cc = c - tb;
-      const uint32_t zt = (uint32_t)(63 - cc) * 0x00010001u;
+      // the zero of column c: V = 0 with the column's tag
+      const uint32_t zt = (uint32_t)(U - 1 - cc) * 0x00010001u + K.bias16;
       if ((c & 15) == 0) wd = win[(c >> 4) * 64 + lane];
       const uint32_t sh8 = ((wd >> (2 * (c & 15))) & 3u) << 3;
       uint32_t tlo = K.xlo ^ (K.dlo << sh8);
@@ -355,28 +376,29 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
         hup = pair(cur.x);
         F = pair(cur.y);
       }
-      const v2s ZT = pair(zt);
-      // Row r needs p_r = max(H(i-1,j-1) + s, E(i,j), 0) (independent of F) and
-      // then the serial F chain.  The partial of row r+1 is computed while row
-      // r's chain resolves so that no packed op waits on its predecessor.
-      v2s Hd = hup_prev;
+      // the zero of the next column (the tag one lower), where E is clamped
+      const v2s ZTN = pair(zt - 0x00010001u);
+      // E is carried as max(E, 0): then H = max(diagonal, E, F) needs no zero
+      // operand, and the clamped E obeys the same recurrence clamped at zero
+      // (max(max(E, 0) - ge, H - go - ge, 0) = max(E - ge, H - go - ge, 0)).
+      // Per row: H in one three-way maximum, F and E in three ops each, the
+      // diagonal operand of the next row in two, the running maximum in one.
+      v2s t = hup_prev + pair(__builtin_amdgcn_perm(thi, tlo, sel[0]));
       hup_prev = hup;
-      v2s p = vmax(vmax(Hd + pair(__builtin_amdgcn_perm(thi, tlo, sel[0])), E[0]), ZT);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         // the diagonal of row r+1 is row r's previous H: consume it before row r's
         // new H takes its register
-        v2s t;
-        if (r + 1 < R) t = Hl[r] + pair(__builtin_amdgcn_perm(thi, tlo, sel[r + 1]));
-        const v2s H = vmax(p, F);
+        v2s tn;
+        if (r + 1 < R) tn = Hl[r] + pair(__builtin_amdgcn_perm(thi, tlo, sel[r + 1]));
+        const v2s H = vmax3h(t, E[r], F);
+        if (r + 1 < R) t = tn;
         const v2s f2 = F - GE_F;
         const v2s e2 = E[r] - GE_E;
         const v2s v = H - GOE_F;
         const v2s u = H - GOE_E;
-        if (r + 1 < R) t = vmax(t, E[r + 1]);
         F = vmax(f2, v);
-        E[r] = vmax(e2, u);
-        if (r + 1 < R) p = vmax(t, ZT);
+        E[r] = vmax3h(e2, u, ZTN);
         if (!FR || TRACK) M[r] = vmax(M[r], H);
         Hl[r] = H;
       }
@@ -388,58 +410,42 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
       v2s m = pair(0u);
 #pragma unroll
       for (int r = 0; r < R; ++r) m = r == rr ? M[r] : m;
-      fold16_row(m, L - 1, tb, best_f, best_r);
+      fold16_row(K, m, L - 1, tb, best);
     } else if (!FR) {
-      fold16<R>(M, r0, tb, best_f, best_r);
+      fold16<R>(K, M, r0, tb, best);
     }
     if (tend < Wmax) {
-      // next tile: restart the row maxima and re-base the carried tags by +64
+      // next tile: restart the row maxima and re-base the carried tags by +2^K
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         M[r] = pair(0u);
-        Hl[r] = Hl[r] + TAG64;
-        E[r] = E[r] + TAG64;
+        Hl[r] = Hl[r] + TAGU;
+        E[r] = E[r] + TAGU;
       }
-      hup_prev = hup_prev + TAG64;
+      hup_prev = hup_prev + TAGU;
     }
   }
   if (!LAST) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
 
-// --------------------------------------------------------------------------- int16-pair kernel
-//
-// One lane holds one CAL; the low int16 half of every register is the forward
-// strand task and the high half the reverse strand task (reverse complement of
-// the read against the same window), so both halves always share the window.
-// A lane keeps a strip of R read rows in registers and sweeps the window
-// columns; between strips the strip's bottom row (H and the F entering the next
-// row) goes through a per-wave scratch buffer.
-//
-// Substitution: for column j the lane builds an 8-byte table (lo bytes and hi
-// bytes of s~(b, w_j) for b = 0..3) and each row holds a byte selector
-// (q, q|4) per half, so v_perm_b32 yields both halves' scores in one
-// instruction.  Rows past the read end use selector bytes 12/13 (0x00, 0xFF):
-// every substitution is -256, so those rows only decrease and are never
-// reported.  Columns past the lane's window use a table of 0x8000 (a wall).
-
 // One strip of a tile: in final-row mode the row maxima are kept only if some
 // lane's last read row lies in the strip (a wave-uniform choice).
 template <int R, bool FIRST, bool LAST, bool FR>
 __device__ __forceinline__ void strip16_sel(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
-                                            int lane, int r0, int L, int W, int Wmin, int Wmax, uint64_t &best_f,
-                                            uint64_t &best_r) {
+                                            int lane, int r0, int L, int W, int Wmin, int Wmax,
+                                            volatile uint64_t *best) {
   if (FR && __ballot(L > 0 && L - 1 >= r0 && L - 1 < r0 + R) == 0ull) {
-    strip16<R, FIRST, LAST, FR, false>(K, win, rdw, scr, lane, r0, L, W, Wmin, Wmax, best_f, best_r);
+    strip16<R, FIRST, LAST, FR, false>(K, win, rdw, scr, lane, r0, L, W, Wmin, Wmax, best);
     return;
   }
-  strip16<R, FIRST, LAST, FR, true>(K, win, rdw, scr, lane, r0, L, W, Wmin, Wmax, best_f, best_r);
+  strip16<R, FIRST, LAST, FR, true>(K, win, rdw, scr, lane, r0, L, W, Wmin, Wmax, best);
 }
 
 // One tile of up to 64 CALs (task positions [first, first + count)).
 template <int R, bool FR>
 __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off, const int64_t *rt_len,
-                                       uint32_t *win, uint32_t *rdw, uint2 *scr, int lane, int64_t first,
-                                       int count) {
+                                       uint32_t *win, uint32_t *rdw, uint2 *scr, uint64_t *lrec, int lane,
+                                       int64_t first, int count) {
   LaneTask t{};
   if (lane < count) {
     const int64_t pos = first + lane;
@@ -454,27 +460,38 @@ __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off
   stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
 
   const DpConst &K = A.k;
-  uint64_t best_f = 0, best_r = 0;
+  // The lane's record stays in LDS during the sweep, which needs every register
+  // it can get: best keys (forward at [0], reverse at [64]), the CAL index at
+  // [128] and the window start with the strand mask at [192].
+  volatile uint64_t *best = lrec + lane;
+  best[0] = 0;
+  best[64] = 0;
+  best[128] = (uint64_t)t.c;
+  best[192] = ((uint64_t)t.ws << 2) | (uint64_t)(t.mask & 3);
   const int nstrips = (Lmax + R - 1) / R;
   if (nstrips == 1) {
-    strip16_sel<R, true, true, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    strip16_sel<R, true, true, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best);
   } else {
-    strip16_sel<R, true, false, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best_f, best_r);
+    strip16_sel<R, true, false, FR>(K, win, rdw, scr, lane, 0, L, W, Wmin, Wmax, best);
     for (int s = 1; s + 1 < nstrips; ++s)
-      strip16_sel<R, false, false, FR>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best_f, best_r);
-    strip16_sel<R, false, true, FR>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best_f, best_r);
+      strip16_sel<R, false, false, FR>(K, win, rdw, scr, lane, s * R, L, W, Wmin, Wmax, best);
+    strip16_sel<R, false, true, FR>(K, win, rdw, scr, lane, (nstrips - 1) * R, L, W, Wmin, Wmax, best);
   }
   if (L > 0) {
-    if (t.mask & 1) write_result(A, 2 * t.c, best_f, t.ws);
-    if (t.mask & 2) write_result(A, 2 * t.c + 1, best_r, t.ws);
+    const int64_t c = (int64_t)best[128];
+    const uint64_t wm = best[192];
+    const int64_t ws = (int64_t)(wm >> 2);
+    if (wm & 1) write_result(A, 2 * c, best[0], ws);
+    if (wm & 2) write_result(A, 2 * c + 1, best[64], ws);
   }
 }
 
 // Plain launch: fixed 64-CAL tiles, static striding over a persistent grid.
 template <int R, bool FR>
-__global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTable T) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_inter16(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  __shared__ uint64_t lrec[256];
   const int lane = threadIdx.x;
   load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
   uint32_t *win = smem;
@@ -483,15 +500,17 @@ __global__ __launch_bounds__(64) void k_inter16(const AlignArgs A, const RefTabl
   TileIter it{(int64_t)blockIdx.x, (A.n_tasks + 63) / 64};
   int64_t first, ti;
   int count;
-  while (next_tile(A, it, first, count, ti)) tile16<R, FR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count);
+  while (next_tile(A, it, first, count, ti))
+    tile16<R, FR>(A, rt_off, rt_len, win, rdw, scr, lrec, lane, first, count);
 }
 
 // Batched launch: tiles (each with its own strip height) popped from a device
 // work queue, longest reads first.
 template <bool FR>
-__global__ __launch_bounds__(64) void k_inter16_queue(const AlignArgs A, const RefTable T) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_inter16_queue(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  __shared__ uint64_t lrec[256];
   const int lane = threadIdx.x;
   load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
   uint32_t *win = smem;
@@ -502,11 +521,9 @@ __global__ __launch_bounds__(64) void k_inter16_queue(const AlignArgs A, const R
   int count;
   while (next_tile(A, it, first, count, ti)) {
     switch (A.tile_strips[ti]) {
-  // the final-row strips need a few more registers: the planner gives its tiles no
-  // strips above 44 rows, and such a tile would still run correctly as 44-row strips
-#define SW_Q16_CASE(RR)                                                                         \
-  case RR:                                                                                      \
-    tile16<(FR && RR > 44 ? 44 : RR), FR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
+#define SW_Q16_CASE(RR)                                                     \
+  case RR:                                                                  \
+    tile16<RR, FR>(A, rt_off, rt_len, win, rdw, scr, lrec, lane, first, count); \
     break;
       SW_QUEUE16_STRIPS(SW_Q16_CASE)
 #undef SW_Q16_CASE

@@ -124,3 +124,23 @@ def test_ctx_shapes_change_and_graph_cache(tmp_path):
     assert "tuned=cached" in ctx2.last_plan()
     assert_same(_host(out), exps[0], "cached plan")
     ctx2.close()
+
+
+@pytest.mark.parametrize("scoring,mrl", [((2, -3, 5, 2), 243), ((2, -500, 5, 2), 250), ((1, -1, 300, 100), 80)],
+                         ids=["K6-top", "K4", "K6-gap-terms"])
+def test_ctx_int16_tag_width_and_bias_edges(scoring, mrl):
+    """The batched path at the edges of the int16 layout (tag width 6 at the top of
+    its range, tag width 4, the largest gap terms) on homopolymers with full windows
+    (the largest values) and on mixed reads."""
+    import dataclasses
+    for seed, homo in ((23, True), (24, False)):
+        b = wl.random_small_batch(seed, n_reads=150, read_len=(1, mrl), ref_len=(400, 1500), band=12,
+                                  homopolymer=homo)
+        b = dataclasses.replace(b, scoring=wl.Scoring(*scoring, 12))
+        if homo:
+            b = dataclasses.replace(b, cal_pos=np.full_like(b.cal_pos, 12), strand=np.full_like(b.strand, 3))
+        exp, _ = oracle_align(b)
+        res, plan = _ctx_run(b, sw.PREC_INT16, max_read_len=mrl, repeats=2)
+        for r in res:
+            assert_same(r, exp, f"{scoring} mrl {mrl} homopolymer={homo} ({plan})")
+        assert plan.startswith("int16-pairs")

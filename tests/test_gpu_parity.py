@@ -144,6 +144,46 @@ def test_maximum_read_length_and_wide_band():
         gpu_align(b, sw.PREC_INT16, max_read_len=1024)
 
 
+# The int16 sweep keeps (V + beta) * 2^K + tag in each half, beta covering the
+# largest single penalty (|mismatch|, gap_open + gap_extend + 1, 256 / 2^K) and K
+# the widest of 6, 5, 4 with (beta + match * max_read_len + 1) * 2^K <= 0x7BFF.
+# Each case sits at an edge of that layout: values at the top of the range,
+# each term setting beta, and each tag width.
+TAG_EDGES = [
+    # (match, mismatch, gap_open, gap_extend, max_read_len, read lengths): K, beta
+    ((2, -3, 5, 2), 243, (200, 243)),     # K 6, beta 8: (8 + 486 + 1) * 64 = 31680, just inside
+    ((2, -3, 5, 2), 244, (200, 244)),     # K 5 from one base more
+    ((2, -500, 5, 2), 250, (150, 250)),   # K 4, beta from the mismatch
+    ((1, -1, 300, 100), 80, (1, 80)),     # K 6, beta 401 from the gap terms
+    ((1, -400, 0, 1), 100, (1, 100)),     # K 5, beta 400 from the mismatch, no gap opening
+    ((3, -1, 1, 1), 150, (100, 150)),     # K 6, beta 4 from the padding rows
+]
+
+
+@pytest.mark.parametrize("mode", [sw.MODE_LOCAL, sw.MODE_FINAL_ROW])
+@pytest.mark.parametrize("edge", TAG_EDGES, ids=[f"{e[0]}-L{e[1]}" for e in TAG_EDGES])
+def test_int16_tag_width_and_bias_edges(edge, mode):
+    (m, x, go, ge), mrl, lens = edge
+    sc = wl.Scoring(m, x, go, ge, 12)
+    for seed, homo in ((21, True), (22, False)):
+        # homopolymer reads on homopolymer references reach the largest values the
+        # layout must hold (every cell of the top rows scores match * row)
+        b = wl.random_small_batch(seed, n_reads=30, read_len=lens, ref_len=(400, 1500), band=12,
+                                  homopolymer=homo)
+        b = dataclasses.replace(b, scoring=sc)
+        if homo:
+            # full windows and both strands for every CAL (the other seed keeps CALs
+            # near the reference ends, with mixed strand masks)
+            b = dataclasses.replace(b, cal_pos=np.full_like(b.cal_pos, 12), strand=np.full_like(b.strand, 3))
+        exp, _ = oracle_align(b, mode=mode)
+        got = gpu_align(b, sw.PREC_INT16, kernel=sw.KERNEL_INTER, max_read_len=mrl, mode=mode)
+        assert_same(got, exp, f"{edge} homopolymer={homo} mode={mode}")
+        if homo:
+            # the top of the range is reached: the longest read with a CAL scores match * L
+            has_cal = np.diff(b.cal_ptr) > 0
+            assert int(exp["score"].max()) == m * int(b.read_len[has_cal].max())
+
+
 def test_empty_inputs():
     """No CALs at all, and reads without CALs: calls succeed and touch nothing."""
     b = wl.random_small_batch(19, n_reads=5, max_cals=0)
