@@ -45,7 +45,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("sw_kernels.hip", "sw_device.h", "sw_launch.h"):
+    for name in ("sw_kernels.hip", "sw_device.h", "sw_halfmax.h", "sw_launch.h"):
         with open(os.path.join(ROOT, "paper_1805_00106_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -62,6 +62,19 @@ def load_traffic(kernel: str, workload: str):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def load_issue(kernel: str, workload: str):
+    """VALU instructions per cell pair and VALU busy fraction from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(PROFILE_DIR, f"valu_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec
 
 
 def cells_of(batch) -> int:
@@ -753,7 +766,18 @@ def main():
             "peak_measured": round(measured, 2), "frac_of_measured": round(achieved / measured, 4),
             "kernel": "k_inter16_queue", "kernel_ms": round(kern_ms, 3),
             "kernel_gcups": round(cells / (kern_ms * 1e-3) / 1e9, 1),
-            "gcups_peak": round(PEAK_INT16_TOPS * 1e12 / OPS_PER_CELL / 1e9, 1)}
+            "gcups_peak": round(PEAK_INT16_TOPS * 1e12 / OPS_PER_CELL / 1e9, 1),
+            "note": "achieved counts 12 algorithmic lane-ops per cell; the kernel issues about 10.7 packed "
+                    "instructions per pair of cells (two cells per lane), so frac can exceed 1: issue.frac "
+                    "is the share of the VALU issue peak the kernel's instructions fill"}
+    valu = load_issue("inter16_queue", "chromosome_scale")
+    if valu:
+        # packed instructions issued per second over all lanes, against 256 CUs x 64 lanes x 2.4 GHz
+        issued = valu["insts_per_cell_pair"] * (cells / 2) / (kern_ms * 1e-3)
+        peak_issue = 256 * 64 * 2.4e9
+        roof["issue"] = {"insts_per_cell_pair": valu["insts_per_cell_pair"], "achieved": round(issued / 1e12, 2),
+                         "peak": round(peak_issue / 1e12, 2), "unit": "T packed instructions/s",
+                         "frac": round(issued / peak_issue, 4), "valu_busy_profiled": valu["valu_busy"]}
     res = {
         "metric": METRIC, "value": round(gcups, 1), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",

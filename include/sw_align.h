@@ -453,6 +453,18 @@ int sw_server_destroy(sw_server_t *srv);
  */
 int sw_alu_peak(int32_t bits, int64_t iters, double *ops_per_s, sw_stream_t stream);
 
+/*
+ * Check of the one device property the int16 scoring kernels take from the
+ * hardware rather than from integer arithmetic: per 16-bit half, the packed
+ * half-precision maximum of three operands must return the operand of highest
+ * rank when the bit patterns [0, 0x7BFF] rank in integer order and the
+ * patterns [0x8000, 0xFBFF] rank below all of them.  Every pair of patterns is
+ * tested (6.0e9 halves).  *n_bad receives the number of halves that break the
+ * order (0 on a conforming device).  Synchronises the stream; allocates a small
+ * device buffer.
+ */
+int sw_check_half_max(int64_t *n_bad, sw_stream_t stream);
+
 /* ------------------------------------------------------------------ misc */
 const char *sw_strerror(int code);
 int sw_last_hip_error(void);

@@ -15,7 +15,7 @@ import torch  # load torch's HIP runtime before the library so both share it
 
 __all__ = [
     "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
-    "reduce_best", "topk", "tied_flags", "classify", "error_count", "traceback", "cigar_text", "cal_filter", "SeedIndex", "alu_peak", "SwError", "Context", "Outputs", "Server", "Request",
+    "reduce_best", "topk", "tied_flags", "classify", "error_count", "traceback", "cigar_text", "cal_filter", "SeedIndex", "alu_peak", "check_half_max", "SwError", "Context", "Outputs", "Server", "Request",
     "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
     "MODE_LOCAL", "MODE_FINAL_ROW", "MAX_READ_LEN", "MAX_REFS", "MAX_TOPK",
 ]
@@ -106,6 +106,7 @@ def lib():
         L.sw_classify.argtypes = [vp, i32, i32, i32, vp, vp]
         L.sw_topk.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
         L.sw_alu_peak.argtypes = [i32, i64, ctypes.POINTER(ctypes.c_double), vp]
+        L.sw_check_half_max.argtypes = [ctypes.POINTER(ctypes.c_int64), vp]
         L.sw_traceback.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, i64,
                                    ctypes.POINTER(Scoring), vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp,
                                    ctypes.c_size_t, vp]
@@ -279,6 +280,14 @@ def alu_peak(bits: int = 16, iters: int = 1 << 19, stream=None) -> float:
     """Measured sustained integer lane-ops per second of the current device (sw_alu_peak)."""
     v = ctypes.c_double(0.0)
     _check(lib().sw_alu_peak(bits, iters, ctypes.byref(v), _stream(stream)), "sw_alu_peak")
+    return v.value
+
+
+def check_half_max(stream=None) -> int:
+    """Halves where the packed half-precision maximum breaks the order the int16
+    kernels rely on, over every pair of operands (sw_check_half_max); 0 expected."""
+    v = ctypes.c_int64(-1)
+    _check(lib().sw_check_half_max(ctypes.byref(v), _stream(stream)), "sw_check_half_max")
     return v.value
 
 

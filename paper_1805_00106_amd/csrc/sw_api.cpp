@@ -16,6 +16,7 @@
 
 namespace swk {
 hipError_t measure_alu_peak(int bits, int64_t iters, int blocks, uint32_t *out, hipStream_t st, double *ops_per_s);
+hipError_t check_half_max(int64_t *n_bad, hipStream_t st);
 }
 
 namespace swapi {
@@ -546,6 +547,13 @@ int sw_alu_peak(int32_t bits, int64_t iters, double *ops_per_s, sw_stream_t stre
   if (hipMalloc(&out, sizeof(uint32_t) * 256 * (size_t)blocks) != hipSuccess) return SW_ERR_NOMEM;
   hipError_t e = swk::measure_alu_peak(bits, iters, blocks, out, (hipStream_t)stream, ops_per_s);
   hipFree(out);
+  return e == hipSuccess ? SW_OK : hip_fail(e);
+}
+
+int sw_check_half_max(int64_t *n_bad, sw_stream_t stream) {
+  if (!n_bad) return SW_ERR_INVALID_ARG;
+  *n_bad = -1;
+  hipError_t e = swk::check_half_max(n_bad, (hipStream_t)stream);
   return e == hipSuccess ? SW_OK : hip_fail(e);
 }
 

@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "sw_device.h"
+#include "sw_halfmax.h"
 #include "sw_launch.h"
 
 namespace swk {
@@ -26,16 +27,8 @@ __device__ __forceinline__ uint32_t bits(v2s a) { return __builtin_bit_cast(uint
 __device__ __forceinline__ v2s pair(uint32_t a) { return __builtin_bit_cast(v2s, a); }
 __device__ __forceinline__ v2s vmax(v2s a, v2s b) { return __builtin_elementwise_max(a, b); }
 
-typedef _Float16 v2h __attribute__((ext_vector_type(2)));
-// max(a, b, c) per half for int16 patterns in [0, 0x7BFF] (patterns of
-// [0x8000, 0xFBFF] rank below all of them): one v_pk_maximum3_f16, exact on
-// these patterns since they are the finite non-negative halves in increasing
-// order (and the negative ones below zero).
 __device__ __forceinline__ v2s vmax3h(v2s a, v2s b, v2s c) {
-  const v2h m = __builtin_elementwise_maximum(
-      __builtin_elementwise_maximum(__builtin_bit_cast(v2h, a), __builtin_bit_cast(v2h, b)),
-      __builtin_bit_cast(v2h, c));
-  return __builtin_bit_cast(v2s, m);
+  return __builtin_bit_cast(v2s, half_max3(bits(a), bits(b), bits(c)));
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -572,7 +565,7 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
         q[r] = 4;  // never equal to a window code: a mismatch-only row
       }
       Hl[r] = 4096;
-      E[r] = 4096 - K.goe_e32;
+      E[r] = 4095;  // E is kept clamped at zero: column 0 starts at its zero
       M[r] = 0;
     }
     int32_t hup_prev = 4096;
@@ -605,17 +598,22 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
         hup = (int32_t)cur.x;
         F = (int32_t)cur.y;
       }
-      int32_t Hd = hup_prev;
+      // E is carried as max(E, 0), so H = max(diagonal, E, F) is one v_max3_i32
+      // and the clamp moves into E's own three-way maximum (with the next
+      // column's zero, tag one lower)
+      int32_t t = hup_prev + (q[0] == w ? K.sm32 : sx);
       hup_prev = hup;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int32_t sub = q[r] == w ? K.sm32 : sx;
-        int32_t H = max(max(Hd + sub, E[r]), F);
-        H = max(H, zt);
+        // the diagonal of row r+1 is row r's previous H: consume it before row r's
+        // new H takes its register
+        int32_t tn = 0;
+        if (r + 1 < R) tn = Hl[r] + (q[r + 1] == w ? K.sm32 : sx);
+        const int32_t H = max(max(t, E[r]), F);
+        t = tn;
         M[r] = max(M[r], H);
-        E[r] = max(E[r] - K.ge_e32, H - K.goe_e32);
+        E[r] = max(max(E[r] - K.ge_e32, H - K.goe_e32), zt - 1);
         F = max(F - K.ge_f32, H - K.goe_f32);
-        Hd = Hl[r];
         Hl[r] = H;
       }
       if (s + 1 < nstrips) scr[c * 64 + lane] = make_uint2((uint32_t)Hl[R - 1], (uint32_t)F);

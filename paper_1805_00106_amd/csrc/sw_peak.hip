@@ -1,8 +1,13 @@
 // Calibration kernels: the sustained integer VALU rate of the device, from
 // every compute unit running independent chains of packed 16-bit (or 32-bit)
-// add + max, the two operations the dynamic program is made of.
+// add + max, the two operations the dynamic program is made of; and the check
+// of the ordering the int16 sweep takes from the packed half-precision maximum.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <new>
+
+#include "sw_halfmax.h"
 
 namespace swk {
 
@@ -50,7 +55,65 @@ __global__ __launch_bounds__(256) void k_alu_peak32(int64_t iters, uint32_t seed
   out[tid] = x;
 }
 
+// Rank of a pattern in the order the int16 sweep needs: [0x8000, 0xFBFF]
+// below everything, then [0, 0x7BFF] in integer order.
+__device__ __forceinline__ uint32_t sweep_rank(uint32_t v) { return v >= 0x8000u ? 0u : v + 1u; }
+
+// One thread per first operand x (the sweep's range and the wall patterns),
+// against every second operand y of the sweep's range, with zero as the third:
+// out[t] = number of halves where the packed half maximum is not an operand
+// of the highest rank.
+__global__ __launch_bounds__(256) void k_half_max_check(const uint32_t *zero, uint32_t nx, uint32_t *out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nx) return;
+  const uint32_t x = t < 0x7C00u ? t : 0x8000u + (t - 0x7C00u);
+  const uint32_t z = zero[0];
+  const uint32_t X = x * 0x00010001u;
+  uint32_t bad = 0;
+  for (uint32_t y = 0; y < 0x7C00u; y += 2) {
+    const uint32_t Y = y | ((y + 1) << 16);
+    const uint32_t r = half_max3(X, Y, z);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t yy = y + h, got = (r >> (16 * h)) & 0xFFFFu;
+      const uint32_t want = max(max(sweep_rank(x), sweep_rank(yy)), sweep_rank(0u));
+      if (sweep_rank(got) != want || (got != x && got != yy && got != 0u)) ++bad;
+    }
+  }
+  out[t] = bad;
+}
+
 }  // namespace
+
+// Number of first operands checked by k_half_max_check.
+constexpr uint32_t kHalfCheckN = 2u * 0x7C00u;
+
+hipError_t check_half_max(int64_t *n_bad, hipStream_t st) {
+  uint32_t *buf = nullptr;
+  hipError_t e = hipMalloc(&buf, sizeof(uint32_t) * (kHalfCheckN + 1));
+  if (e != hipSuccess) return e;
+  uint32_t *zero = buf + kHalfCheckN;
+  e = hipMemsetAsync(zero, 0, sizeof(uint32_t), st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_half_max_check, dim3((kHalfCheckN + 255) / 256), dim3(256), 0, st, zero, kHalfCheckN, buf);
+    e = hipGetLastError();
+  }
+  uint32_t *host = nullptr;
+  if (e == hipSuccess) {
+    host = new (std::nothrow) uint32_t[kHalfCheckN];
+    if (!host) e = hipErrorOutOfMemory;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(host, buf, sizeof(uint32_t) * kHalfCheckN, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    int64_t n = 0;
+    for (uint32_t i = 0; i < kHalfCheckN; ++i) n += host[i];
+    *n_bad = n;
+  }
+  delete[] host;
+  hipFree(buf);
+  return e;
+}
 
 // Runs the chain kernel on `blocks` blocks of 256 threads and returns the rate
 // in integer lane-ops per second (a packed 16-bit op counts as two).

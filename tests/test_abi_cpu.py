@@ -28,7 +28,8 @@ def test_header_declares_entry_points():
     names = _declared_functions()
     for n in ("sw_align_batch", "sw_workspace_bytes", "sw_reduce_best", "sw_classify", "sw_pack_2bit",
               "sw_topk", "sw_tied_flags", "sw_traceback", "sw_traceback_workspace_bytes",
-              "sw_ctx_create", "sw_align_batch_ctx", "sw_strerror"):
+              "sw_ctx_create", "sw_align_batch_ctx", "sw_strerror", "sw_alu_peak", "sw_check_half_max",
+              "sw_cal_filter", "sw_index_build", "sw_find_cals", "sw_server_create", "sw_server_submit"):
         assert n in names
 
 
@@ -166,3 +167,4 @@ def test_alu_peak_validation(sw):
     assert L.sw_alu_peak(8, 1 << 10, ctypes.byref(v), None) == -1
     assert L.sw_alu_peak(16, 4, ctypes.byref(v), None) == -1
     assert L.sw_alu_peak(32, 1 << 10, None, None) == -1
+    assert L.sw_check_half_max(None, None) == -1

@@ -144,6 +144,12 @@ def test_maximum_read_length_and_wide_band():
         gpu_align(b, sw.PREC_INT16, max_read_len=1024)
 
 
+def test_half_max_order_on_device():
+    """The int16 sweep takes its three-way maxima from the packed half-precision
+    maximum; every pair of operand patterns must keep the integer order."""
+    assert sw.check_half_max() == 0
+
+
 # The int16 sweep keeps (V + beta) * 2^K + tag in each half, beta covering the
 # largest single penalty (|mismatch|, gap_open + gap_extend + 1, 256 / 2^K) and K
 # the widest of 6, 5, 4 with (beta + match * max_read_len + 1) * 2^K <= 0x7BFF.
