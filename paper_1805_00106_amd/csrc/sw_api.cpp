@@ -60,48 +60,30 @@ int validate_scoring(const sw_scoring_t *sc, ScoreMode *mode) {
   return SW_OK;
 }
 
-int int16_layout(const sw_scoring_t *sc, int32_t *kbits, int32_t *beta) {
+// The int16 layout of the scoring for its read-length bound (see DpConst).
+static int int16_layout_for(const sw_scoring_t *sc, swk::DpConst *k) {
+  k->match = sc->match;
+  k->mismatch = sc->mismatch;
+  k->goe = sc->gap_open + sc->gap_extend;
+  k->ge = sc->gap_extend;
   const int64_t mrl = sc->max_read_len == 0 ? SW_MAX_READ_LEN : sc->max_read_len;
-  const int64_t top = (int64_t)sc->match * mrl;
-  const int64_t goe = (int64_t)sc->gap_open + sc->gap_extend;
-  for (int K = 6; K >= 4; --K) {
-    const int64_t U = (int64_t)1 << K;
-    // beta covers the largest single penalty (gap opening plus one, as the gap
-    // terms of the last column of a tile carry the tag -1) and the -256 of the
-    // padding rows
-    const int64_t b = std::max<int64_t>(std::max<int64_t>(-(int64_t)sc->mismatch, goe + 1), (256 + U - 1) / U);
-    if (b <= 0x7BFF && (b + top + 1) * U <= 0x7BFF) {
-      *kbits = K;
-      *beta = (int32_t)b;
-      return 1;
-    }
-  }
-  return 0;
+  return swk::set_int16_layout(*k, (int64_t)sc->match * mrl);
+}
+
+int int16_layout(const sw_scoring_t *sc, int32_t *kbits, int32_t *beta) {
+  swk::DpConst k{};
+  if (!int16_layout_for(sc, &k)) return 0;
+  *kbits = k.kbits16;
+  *beta = k.beta16;
+  return 1;
 }
 
 DpConstHost make_consts(const sw_scoring_t *sc) {
   swk::DpConst k{};
   const int32_t goe = sc->gap_open + sc->gap_extend, ge = sc->gap_extend;
-  auto pk = [](int32_t v) { return ((uint32_t)(uint16_t)(int16_t)v) * 0x00010001u; };
-  // int16 pairs: the widest tag (K) whose biased values stay below 0x7C00
-  int32_t kbits = 4, beta = 0;
-  int16_layout(sc, &kbits, &beta);
-  const int32_t U = 1 << kbits;
-  k.goe_e16 = pk(goe * U + 1);
-  k.ge_e16 = pk(ge * U + 1);
-  k.goe_f16 = pk(goe * U);
-  k.ge_f16 = pk(ge * U);
-  k.tag16 = pk(U);
-  k.bias16 = pk(beta * U);
-  k.kbits16 = kbits;
-  k.beta16 = beta;
-  const uint16_t sm = (uint16_t)(int16_t)(sc->match * U - 1);
-  const uint16_t sx = (uint16_t)(int16_t)(sc->mismatch * U - 1);
-  const uint32_t lo_m = sm & 0xFF, hi_m = sm >> 8, lo_x = sx & 0xFF, hi_x = sx >> 8;
-  k.xlo = lo_x * 0x01010101u;
-  k.dlo = lo_x ^ lo_m;
-  k.xhi = hi_x * 0x01010101u;
-  k.dhi = hi_x ^ hi_m;
+  // int16 pairs: the widest tag (K) whose biased values stay below 0x7C00 (the
+  // scoring kernels may widen it per tile)
+  int16_layout_for(sc, &k);
   k.goe_e32 = goe * 4096 + 1;
   k.ge_e32 = ge * 4096 + 1;
   k.goe_f32 = goe * 4096;

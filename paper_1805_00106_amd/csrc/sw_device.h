@@ -35,7 +35,9 @@ struct RefTable {
 // clamped gap term E = max(E - ge, H - go - ge, 0) are one v_pk_maximum3_f16
 // each; a wall column (substitution 0x8000) makes the diagonal operand a
 // negative half, below every other operand.  K is the largest of 6, 5, 4 for
-// which (beta + match * max_read_len + 1) * 2^K stays below 0x7C00.
+// which (beta + top + 1) * 2^K stays below 0x7C00, top = match * (longest read):
+// chosen for the call's read-length bound, and again per tile of 64 CALs for
+// the tile's longest read (shorter reads allow the wider tag).
 struct DpConst {
   // int16 pairs, both halves hold the same constant
   uint32_t goe_e16, ge_e16, goe_f16, ge_f16;
@@ -44,11 +46,42 @@ struct DpConst {
   int32_t kbits16;   // K
   int32_t beta16;    // beta
   uint32_t xlo, dlo, xhi, dhi;  // substitution table bytes (see the kernel)
+  int32_t match, mismatch, goe, ge;  // the scoring (goe = gap_open + gap_extend)
   // int32 (K = 12)
   int32_t goe_e32, ge_e32, goe_f32, ge_f32, sm32, sx32, e0_32;
   // 1: only the last read row may hold the best cell (read-end-anchored scoring)
   int32_t final_row;
 };
+
+// Sets the int16 fields of K for the widest tag whose biased values hold scores
+// up to `top`; returns 0 (leaving K unchanged) if no width does.
+__host__ __device__ inline int set_int16_layout(DpConst &K, int64_t top) {
+  for (int kb = 6; kb >= 4; --kb) {
+    const int32_t U = 1 << kb;
+    int32_t b = -K.mismatch;
+    if (K.goe + 1 > b) b = K.goe + 1;
+    if ((256 + U - 1) / U > b) b = (256 + U - 1) / U;
+    if (b > 0x7BFF || ((int64_t)b + top + 1) * U > 0x7BFF) continue;
+    const uint32_t pair1 = 0x00010001u;
+    K.goe_e16 = (uint32_t)(uint16_t)(K.goe * U + 1) * pair1;
+    K.ge_e16 = (uint32_t)(uint16_t)(K.ge * U + 1) * pair1;
+    K.goe_f16 = (uint32_t)(uint16_t)(K.goe * U) * pair1;
+    K.ge_f16 = (uint32_t)(uint16_t)(K.ge * U) * pair1;
+    K.tag16 = (uint32_t)U * pair1;
+    K.bias16 = (uint32_t)(b * U) * pair1;
+    K.kbits16 = kb;
+    K.beta16 = b;
+    // substitution s * 2^K - 1 (the tag step of a diagonal move), as bytes
+    const uint32_t sm = (uint16_t)(K.match * U - 1), sx = (uint16_t)(K.mismatch * U - 1);
+    const uint32_t lo_m = sm & 0xFFu, hi_m = sm >> 8, lo_x = sx & 0xFFu, hi_x = sx >> 8;
+    K.xlo = lo_x * 0x01010101u;
+    K.dlo = lo_x ^ lo_m;
+    K.xhi = hi_x * 0x01010101u;
+    K.dhi = hi_x ^ hi_m;
+    return 1;
+  }
+  return 0;
+}
 
 struct AlignArgs {
   const uint32_t *reads;

@@ -31,13 +31,15 @@ __device__ __forceinline__ v2s vmax3h(v2s a, v2s b, v2s c) {
   return __builtin_bit_cast(v2s, half_max3(bits(a), bits(b), bits(c)));
 }
 
+// Wave-wide maximum and minimum; every lane holds the result, which is read
+// from lane 0 so that the compiler keeps it in a scalar register.
 __device__ __forceinline__ int wave_max(int v) {
   for (int m = 32; m; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
-  return v;
+  return __builtin_amdgcn_readfirstlane(v);
 }
 __device__ __forceinline__ int wave_min(int v) {
   for (int m = 32; m; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
-  return v;
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 // --------------------------------------------------------------------------- packing
@@ -452,7 +454,9 @@ __device__ __forceinline__ void tile16(const AlignArgs &A, const int64_t *rt_off
   const int Wmin = wave_min(L > 0 ? W : 0x7fffffff);
   stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
 
-  const DpConst &K = A.k;
+  // the tile's longest read may allow a wider tag than the call's bound
+  DpConst K = A.k;
+  if (K.kbits16 < 6) set_int16_layout(K, (int64_t)K.match * Lmax);
   // The lane's record stays in LDS during the sweep, which needs every register
   // it can get: best keys (forward at [0], reverse at [64]), the CAL index at
   // [128] and the window start with the strand mask at [192].

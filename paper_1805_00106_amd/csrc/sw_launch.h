@@ -10,7 +10,7 @@
 #define SW_INTER16_STRIPS(X) X(24) X(32) X(40) X(44) X(48) X(50)
 #define SW_INTER32_STRIPS(X) X(24) X(32) X(38) X(48)
 // Strip heights available to the batched (work-queue) kernels, ascending.
-#define SW_QUEUE16_STRIPS(X) X(24) X(32) X(34) X(40) X(44) X(48) X(50)
+#define SW_QUEUE16_STRIPS(X) X(24) X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50)
 #define SW_QUEUE32_STRIPS(X) X(24) X(32) X(34) X(40) X(48) X(50)
 
 namespace swk {
