@@ -389,6 +389,8 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
       if (c->graphs.size() >= 8) {
         auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
                                     [](const GraphEntry &p, const GraphEntry &q) { return p.last_use < q.last_use; });
+        // a launch of the evicted graph may still be queued on the context stream
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return swapi::hip_fail(e);
         hipGraphExecDestroy(lru->exec);
         c->graphs.erase(lru);
       }

@@ -337,11 +337,11 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
     M[r] = pair(0u);
   }
   v2s hup_prev = TAGU + BIAS;
-  uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
+  // the hand-over row of the next column, loaded one column ahead
+  uint2 pf = make_uint2(0, 0);
   if (!FIRST) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    pf0 = scr[lane];
-    if (Wmax > 1) pf1 = scr[64 + lane];
+    pf = scr[lane];
   }
   for (int tb = 0; tb < Wmax; tb += U) {
     const int tend = min(tb + U, Wmax);
@@ -365,11 +365,9 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
         hup = pair(zt);
         F = pair(zt) - GOE_F;
       } else {
-        const uint2 cur = pf0;
-        pf0 = pf1;
-        if (c + 2 < Wmax) pf1 = scr[(c + 2) * 64 + lane];
-        hup = pair(cur.x);
-        F = pair(cur.y);
+        hup = pair(pf.x);
+        F = pair(pf.y);
+        if (c + 1 < Wmax) pf = (scr + (size_t)(c + 1) * 64)[lane];
       }
       // the zero of the next column (the tag one lower), where E is clamped
       const v2s ZTN = pair(zt - 0x00010001u);
@@ -397,7 +395,8 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
         if (!FR || TRACK) M[r] = vmax(M[r], H);
         Hl[r] = H;
       }
-      if (!LAST) scr[c * 64 + lane] = make_uint2(bits(Hl[R - 1]), bits(F));
+      // the column's scratch row: a wave-uniform base plus the lane
+      if (!LAST) (scr + (size_t)c * 64)[lane] = make_uint2(bits(Hl[R - 1]), bits(F));
     }
     if (FR && TRACK) {
       // read-end-anchored scoring: only row L-1 may hold the best cell
