@@ -767,9 +767,10 @@ def main():
             "kernel": "k_inter16_queue", "kernel_ms": round(kern_ms, 3),
             "kernel_gcups": round(cells / (kern_ms * 1e-3) / 1e9, 1),
             "gcups_peak": round(PEAK_INT16_TOPS * 1e12 / OPS_PER_CELL / 1e9, 1),
-            "note": "achieved counts 12 algorithmic lane-ops per cell; the kernel issues about 10.7 packed "
-                    "instructions per pair of cells (two cells per lane), so frac can exceed 1: issue.frac "
-                    "is the share of the VALU issue peak the kernel's instructions fill"}
+            "note": "achieved counts 12 algorithmic lane-ops per cell; the kernel issues fewer packed "
+                    "instructions per pair of cells (two cells per lane, issue.insts_per_cell_pair) than the 12 "
+                    "packed ops those cells count, so frac can exceed 1: issue.frac is the share of the VALU "
+                    "issue peak the kernel's instructions fill"}
     valu = load_issue("inter16_queue", "chromosome_scale")
     if valu:
         # packed instructions issued per second over all lanes, against 256 CUs x 64 lanes x 2.4 GHz
