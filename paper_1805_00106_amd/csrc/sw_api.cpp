@@ -90,6 +90,15 @@ DpConstHost make_consts(const sw_scoring_t *sc) {
   k.ge_f32 = ge * 4096;
   k.sm32 = sc->match * 4096 - 1;
   k.sx32 = sc->mismatch * 4096 - 1;
+  k.perm32 = sc->match <= 16 && sc->mismatch >= -15 ? 1 : 0;
+  if (k.perm32) {
+    const uint32_t m1 = ((uint32_t)k.sm32 >> 8) & 0xFFu, x1 = ((uint32_t)k.sx32 >> 8) & 0xFFu;
+    const uint32_t m2 = ((uint32_t)k.sm32 >> 16) & 0xFFu, x2 = ((uint32_t)k.sx32 >> 16) & 0xFFu;
+    k.xlo32 = x1 * 0x01010101u;
+    k.dlo32 = x1 ^ m1;
+    k.xhi32 = x2 * 0x01010101u;
+    k.dhi32 = x2 ^ m2;
+  }
   k.e0_32 = 0;
   k.final_row = sc->mode == SW_MODE_FINAL_ROW ? 1 : 0;
   return k;

@@ -535,7 +535,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // tagged with K = 12 bits (tiles of 4096 columns, wider than any window the
 // library accepts, so no tile change happens inside a sweep).
 
-template <int R>
+// P: substitution by byte permutation (DpConst::perm32), else compare and select.
+template <int R, bool P>
 __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off, const int64_t *rt_len,
                                        uint32_t *win, uint32_t *rdw, uint2 *scr, int lane, int64_t first,
                                        int count) {
@@ -558,14 +559,18 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
   const int nstrips = (Lmax + R - 1) / R;
   for (int s = 0; s < nstrips; ++s) {
     const int r0 = s * R;
+    // per row the read code (compare and select), or with P the byte selector
+    // (0xFF, table byte q, sign byte q, sign byte q); past the read end a code
+    // that never equals a window code, or the selector of 0xFFFF00FF (about -16 per row)
     int32_t q[R], Hl[R], E[R], M[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = r0 + r;
       if (i < L) {
         q[r] = h == 0 ? (int32_t)base_at(rdw, lane, i) : (int32_t)(3u - base_at(rdw, lane, L - 1 - i));
+        if (P) q[r] = 0x0D | (q[r] << 8) | ((q[r] | 4) << 16) | ((q[r] | 4) << 24);
       } else {
-        q[r] = 4;  // never equal to a window code: a mismatch-only row
+        q[r] = P ? 0x0D0D0C0D : 4;
       }
       Hl[r] = 4096;
       E[r] = 4095;  // E is kept clamped at zero: column 0 starts at its zero
@@ -586,7 +591,16 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       // past the lane's window: a wall (no diagonal move enters these columns, so
       // no cell there can beat a real cell of its row, which the final-row mode needs)
       int32_t sx = K.sx32;
-      if (c >= W) {
+      uint32_t tlo = 0, thi = 0;
+      if (P) {
+        const uint32_t sh8 = (uint32_t)w << 3;
+        tlo = K.xlo32 ^ (K.dlo32 << sh8);
+        thi = K.xhi32 ^ (K.dhi32 << sh8);
+        if (c >= W) {
+          tlo = 0u;           // 0x808000FF: about -2^31
+          thi = 0x80808080u;
+        }
+      } else if (c >= W) {
         w = 5;
         sx = -(1 << 30);
       }
@@ -604,14 +618,17 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       // E is carried as max(E, 0), so H = max(diagonal, E, F) is one v_max3_i32
       // and the clamp moves into E's own three-way maximum (with the next
       // column's zero, tag one lower)
-      int32_t t = hup_prev + (q[0] == w ? K.sm32 : sx);
+      auto subst = [&](int32_t qr) {
+        return P ? (int32_t)__builtin_amdgcn_perm(thi, tlo, (uint32_t)qr) : (qr == w ? K.sm32 : sx);
+      };
+      int32_t t = hup_prev + subst(q[0]);
       hup_prev = hup;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         // the diagonal of row r+1 is row r's previous H: consume it before row r's
         // new H takes its register
         int32_t tn = 0;
-        if (r + 1 < R) tn = Hl[r] + (q[r + 1] == w ? K.sm32 : sx);
+        if (r + 1 < R) tn = Hl[r] + subst(q[r + 1]);
         const int32_t H = max(max(t, E[r]), F);
         t = tn;
         M[r] = max(M[r], H);
@@ -635,7 +652,7 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
   if (L > 0) write_result(A, 2 * t.c + h, best, t.ws);
 }
 
-template <int R>
+template <int R, bool P>
 __global__ __launch_bounds__(64) void k_inter32(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
@@ -647,9 +664,10 @@ __global__ __launch_bounds__(64) void k_inter32(const AlignArgs A, const RefTabl
   TileIter it{(int64_t)blockIdx.x, (A.n_tasks + 63) / 64};
   int64_t first, ti;
   int count;
-  while (next_tile(A, it, first, count, ti)) tile32<R>(A, rt_off, rt_len, win, rdw, scr, lane, first, count);
+  while (next_tile(A, it, first, count, ti)) tile32<R, P>(A, rt_off, rt_len, win, rdw, scr, lane, first, count);
 }
 
+template <bool P>
 __global__ __launch_bounds__(64) void k_inter32_queue(const AlignArgs A, const RefTable T) {
   extern __shared__ uint32_t smem[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
@@ -663,9 +681,9 @@ __global__ __launch_bounds__(64) void k_inter32_queue(const AlignArgs A, const R
   int count;
   while (next_tile(A, it, first, count, ti)) {
     switch (A.tile_strips[ti]) {
-#define SW_Q32_CASE(RR)                                                 \
-  case RR:                                                              \
-    tile32<RR>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
+#define SW_Q32_CASE(RR)                                                  \
+  case RR:                                                               \
+    tile32<RR, P>(A, rt_off, rt_len, win, rdw, scr, lane, first, count); \
     break;
       SW_QUEUE32_STRIPS(SW_Q32_CASE)
 #undef SW_Q32_CASE
@@ -973,7 +991,10 @@ static hipError_t launch_inter16_r(const AlignArgs &A, const RefTable &T, int gr
 template <int R>
 static hipError_t launch_inter32_r(const AlignArgs &A, const RefTable &T, int grid, size_t lds,
                                    hipStream_t st) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter32<R>), dim3(grid), dim3(64), lds, st, A, T);
+  if (A.k.perm32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter32<R, true>), dim3(grid), dim3(64), lds, st, A, T);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter32<R, false>), dim3(grid), dim3(64), lds, st, A, T);
   return hipGetLastError();
 }
 
@@ -1018,15 +1039,17 @@ hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T,
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16_queue<true>), dim3(grid), dim3(64), lds, st, A, T);
   else if (int16)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter16_queue<false>), dim3(grid), dim3(64), lds, st, A, T);
+  else if (A.k.perm32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter32_queue<true>), dim3(grid), dim3(64), lds, st, A, T);
   else
-    hipLaunchKernelGGL(k_inter32_queue, dim3(grid), dim3(64), lds, st, A, T);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inter32_queue<false>), dim3(grid), dim3(64), lds, st, A, T);
   return hipGetLastError();
 }
 
 int queue_blocks_per_cu(bool int16) {
   int n = 0;
   const void *f = int16 ? reinterpret_cast<const void *>(&k_inter16_queue<false>)
-                        : reinterpret_cast<const void *>(&k_inter32_queue);
+                        : reinterpret_cast<const void *>(&k_inter32_queue<false>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, 8192) != hipSuccess) return 0;
   return n;
 }
@@ -1073,7 +1096,7 @@ static int occ16(size_t lds) {
 template <int R>
 static int occ32(size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_inter32<R>), 64,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_inter32<R, false>), 64,
                                                   lds) != hipSuccess)
     return 0;
   return n;

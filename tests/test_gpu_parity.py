@@ -82,8 +82,11 @@ def test_single_base_reads(precision):
 
 @pytest.mark.parametrize("precision", PRECISIONS)
 @pytest.mark.parametrize("sc", [wl.Scoring(1, 0, 0, 1, 10), wl.Scoring(3, -1, 1, 1, 10),
-                                wl.Scoring(2, -3, 0, 2, 10), wl.Scoring(1, -4, 6, 1, 10)])
+                                wl.Scoring(2, -3, 0, 2, 10), wl.Scoring(1, -4, 6, 1, 10),
+                                wl.Scoring(2, -20, 5, 2, 10)])
 def test_other_scorings(sc, precision):
+    """Several scorings; a mismatch below -15 takes the int32 compare-and-select
+    substitution instead of the byte permutation."""
     b = wl.random_small_batch(14, n_reads=60, read_len=(1, 80), band=10)
     b = dataclasses.replace(b, scoring=sc)
     _case(b, precision)
