@@ -310,7 +310,7 @@ __device__ __forceinline__ void fold16_row(const DpConst &K, v2s m, int row, int
 // is written to the scratch rows).  FR: final-row mode (only row L-1 may hold
 // the best cell); a template parameter so that the local mode keeps its
 // register budget.  TRACK: keep the per-row maxima; a final-row strip that holds
-// no lane's last row skips them (one packed op per cell of twelve).
+// no lane's last row skips them (one packed op per row of ten).
 template <int R, bool FIRST, bool LAST, bool FR, bool TRACK = true>
 __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
                                         int lane, int r0, int L, int W, int Wmin, int Wmax,
