@@ -355,6 +355,12 @@ __device__ __forceinline__ uint32_t code_at(const uint32_t *bits, int cmax, int 
 
 }  // namespace
 
+// P: substitution by byte permutation (both scores within -128..127): a table of
+// the score's low byte and of its sign byte per base, built per column, gives
+// the sign-extended score with one v_perm_b32; else compare and select.  With P
+// the rows below a lane's end row and the columns right of its end column take
+// ordinary substitutions: no cell of the traced rectangle depends on them.
+template <bool P>
 __global__ __launch_bounds__(64) void k_trace_inter(const TraceInterArgs I, const RefTable T) {
   extern __shared__ uint32_t tism[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
@@ -371,6 +377,10 @@ __global__ __launch_bounds__(64) void k_trace_inter(const TraceInterArgs I, cons
   uint32_t *bits = I.bits + (size_t)blockIdx.x * I.bits_stride;
   uint2 *bscr = I.bscr + (size_t)blockIdx.x * I.bscr_stride;
   const int32_t goe = A.goe, ge = A.ge;
+  // substitution tables (P): low byte and sign byte of the score, per base
+  const uint32_t lo_m = (uint32_t)A.match & 0xFFu, lo_x = (uint32_t)A.mismatch & 0xFFu;
+  const uint32_t hi_m = A.match < 0 ? 0xFFu : 0u, hi_x = A.mismatch < 0 ? 0xFFu : 0u;
+  const uint32_t xlo = lo_x * 0x01010101u, dlo = lo_x ^ lo_m, xhi = hi_x * 0x01010101u, dhi = hi_x ^ hi_m;
 
   for (int64_t first = (int64_t)blockIdx.x * 64; first < A.n_slots; first += (int64_t)gridDim.x * 64) {
     const int64_t t = first + lane;
@@ -462,14 +472,25 @@ __global__ __launch_bounds__(64) void k_trace_inter(const TraceInterArgs I, cons
       int32_t q[kTraceRows], Hl[kTraceRows], E[kTraceRows];
 #pragma unroll
       for (int x = 0; x < kTraceRows; ++x) {
-        q[x] = r0 + x < n_rows ? qbase(r0 + x) : 4;  // 4 never equals a window base
+        if (P) {
+          const int32_t b = r0 + x < n_rows ? qbase(r0 + x) : 0;
+          q[x] = b | ((b | 4) << 8) | ((b | 4) << 16) | ((b | 4) << 24);  // selector
+        } else {
+          q[x] = r0 + x < n_rows ? qbase(r0 + x) : 4;  // 4 never equals a window base
+        }
         Hl[x] = 0;                                    // H(i, -1)
         E[x] = -goe;                                  // E(i, 0)
       }
       int32_t hup_prev = 0;  // H(r0 - 1, -1)
       if (s > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       for (int c = 0; c < cmax; ++c) {
-        const int32_t w = c < n_cols ? wbase(c) : 5;
+        const int32_t w = P ? wbase(c) : (c < n_cols ? wbase(c) : 5);
+        uint32_t tlo = 0, thi = 0;
+        if (P) {
+          const uint32_t sh8 = (uint32_t)w << 3;
+          tlo = xlo ^ (dlo << sh8);
+          thi = xhi ^ (dhi << sh8);
+        }
         int32_t hup, F;
         if (s == 0) {
           hup = 0;
@@ -484,7 +505,8 @@ __global__ __launch_bounds__(64) void k_trace_inter(const TraceInterArgs I, cons
         uint32_t word[kTraceGroups];
 #pragma unroll
         for (int x = 0; x < kTraceRows; ++x) {
-          const int32_t diag = Hd + (q[x] == w ? A.match : A.mismatch);
+          const int32_t diag =
+              Hd + (P ? (int32_t)__builtin_amdgcn_perm(thi, tlo, (uint32_t)q[x]) : (q[x] == w ? A.match : A.mismatch));
           const int32_t H = max(max(diag, E[x]), max(F, 0));
           const uint32_t code = H == diag ? (Hd == 0 ? 3u : 0u) : (H == F ? 1u : 2u);
           const int32_t U = H - goe;
@@ -607,7 +629,7 @@ size_t trace_inter_block_bytes(int max_read_len, int wcap) {
 
 int trace_inter_blocks_per_cu() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_trace_inter), 64, 8192) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_trace_inter<true>), 64, 8192) !=
       hipSuccess)
     return 1;
   return n < 1 ? 1 : n;
@@ -616,7 +638,10 @@ int trace_inter_blocks_per_cu() {
 hipError_t launch_trace_inter(const TraceInterArgs &A, const RefTable &T, int grid, hipStream_t st) {
   if (A.a.n_slots == 0) return hipSuccess;
   const size_t lds = (size_t)(A.rwords + A.wwords) * 64 * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_trace_inter, dim3(grid), dim3(64), lds, st, A, T);
+  if (A.a.match <= 127 && A.a.mismatch >= -128)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_inter<true>), dim3(grid), dim3(64), lds, st, A, T);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_inter<false>), dim3(grid), dim3(64), lds, st, A, T);
   return hipGetLastError();
 }
 
