@@ -107,3 +107,13 @@ def test_trace_skip_invalid_and_capacity():
     assert (t["n_ops"] == -1).any() and (t["n_ops"] > 0).any()
     assert sw.error_count() == 3 * 2   # three invalid slots, traced by both kernel families
 
+
+
+@pytest.mark.parametrize("sc", [wl.Scoring(1, -4, 6, 1, 12), wl.Scoring(3, -200, 10, 3, 12)],
+                         ids=["small-scores", "mismatch-200"])
+def test_trace_other_scorings(sc):
+    """Other scorings; a mismatch below -128 takes the compare-and-select
+    substitution of the one-slot-per-lane sweep instead of the byte permutation."""
+    import dataclasses
+    b = wl.random_small_batch(79, n_reads=60, read_len=(1, 120), band=12)
+    _case(dataclasses.replace(b, scoring=sc))
