@@ -4,6 +4,7 @@ TEST INFRASTRUCTURE, run by hand (pytest does not collect it):
 
     python tests/full_size_parity.py uneven_lengths --band 16
     python tests/full_size_parity.py two_references --reads 4000000
+    python tests/full_size_parity.py chromosome_scale --final-row
 
 The whole batch is scored once on the GPU (batched context, per-read best);
 the oracle then scores it in chunks of reads on the host cores, and every slot
@@ -44,6 +45,7 @@ def main():
     ap.add_argument("--reads", type=int, default=0, help="reads (0: the workload's full size)")
     ap.add_argument("--band", type=int, default=32, help="band of uneven_lengths")
     ap.add_argument("--chunk", type=int, default=100_000, help="reads per oracle chunk")
+    ap.add_argument("--final-row", action="store_true", help="read-end-anchored scoring (the final-row mode)")
     args = ap.parse_args()
     threads = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
@@ -53,7 +55,8 @@ def main():
           f"{time.perf_counter() - t0:.0f} s", flush=True)
     refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
     db = sw.DeviceBatch.upload(b)
-    sc = sw.Scoring.make(sc0.match, sc0.mismatch, sc0.gap_open, sc0.gap_extend, sc0.band, prec, sw.KERNEL_AUTO, mrl)
+    mode = sw.MODE_FINAL_ROW if args.final_row else sw.MODE_LOCAL
+    sc = sw.Scoring.make(sc0.match, sc0.mismatch, sc0.gap_open, sc0.gap_extend, sc0.band, prec, sw.KERNEL_AUTO, mrl, mode)
     ctx = sw.Context(db.n_reads, db.n_cals)
     out = sw.Outputs(db.n_cals)
     ctx.align(db, refs, sc, out)
@@ -70,7 +73,7 @@ def main():
     for a in range(0, b.n_reads, args.chunk):
         idx = np.arange(a, min(a + args.chunk, b.n_reads))
         sub = b.subset_reads(idx)
-        s, r, e, _ = orc.align_batch(sub, n_threads=threads)
+        s, r, e, _ = orc.align_batch(sub, n_threads=threads, final_row=args.final_row)
         obs, obl, ont = orc.reduce_best(sub.cal_ptr, sub.cal_ref, sub.n_reads, sub.n_refs, s)
         c0 = int(b.cal_ptr[idx[0]])
         sl = slice(2 * c0, 2 * int(b.cal_ptr[idx[-1] + 1]))
@@ -79,7 +82,7 @@ def main():
         bad_best += int((gbs[idx] != obs).sum() + (gbl[idx] != obl).sum() + (gnt[idx] != ont).sum())
         print(f"{args.workload}: reads {idx[-1] + 1}/{b.n_reads}, differing slot entries {bad_slots}, "
               f"differing best entries {bad_best}, {time.perf_counter() - t1:.0f} s", flush=True)
-    print(f"{args.workload} (band {sc0.band}): {b.n_reads} reads, {2 * b.n_cals} slots, batched path [{plan}] vs "
+    print(f"{args.workload} (band {sc0.band}{', final row' if args.final_row else ''}): {b.n_reads} reads, {2 * b.n_cals} slots, batched path [{plan}] vs "
           f"oracle on {threads} threads: differing slot entries {bad_slots}, differing per-read best entries "
           f"{bad_best}; oracle {time.perf_counter() - t1:.0f} s", flush=True)
     sys.exit(1 if bad_slots or bad_best else 0)
