@@ -46,10 +46,13 @@ def main():
     ap.add_argument("--band", type=int, default=32, help="band of uneven_lengths")
     ap.add_argument("--chunk", type=int, default=100_000, help="reads per oracle chunk")
     ap.add_argument("--final-row", action="store_true", help="read-end-anchored scoring (the final-row mode)")
+    ap.add_argument("--int32", action="store_true", help="score in int32 (one strand per lane)")
     args = ap.parse_args()
     threads = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     b, prec, mrl = make_batch(args.workload, args.reads, args.band)
+    if args.int32:
+        prec = sw.PREC_INT32
     sc0 = b.scoring
     print(f"{args.workload}: {b.n_reads} reads, {b.n_cals} CALs, band {sc0.band}, generated in "
           f"{time.perf_counter() - t0:.0f} s", flush=True)
@@ -82,7 +85,7 @@ def main():
         bad_best += int((gbs[idx] != obs).sum() + (gbl[idx] != obl).sum() + (gnt[idx] != ont).sum())
         print(f"{args.workload}: reads {idx[-1] + 1}/{b.n_reads}, differing slot entries {bad_slots}, "
               f"differing best entries {bad_best}, {time.perf_counter() - t1:.0f} s", flush=True)
-    print(f"{args.workload} (band {sc0.band}{', final row' if args.final_row else ''}): {b.n_reads} reads, {2 * b.n_cals} slots, batched path [{plan}] vs "
+    print(f"{args.workload} (band {sc0.band}{', final row' if args.final_row else ''}{', int32' if args.int32 else ''}): {b.n_reads} reads, {2 * b.n_cals} slots, batched path [{plan}] vs "
           f"oracle on {threads} threads: differing slot entries {bad_slots}, differing per-read best entries "
           f"{bad_best}; oracle {time.perf_counter() - t1:.0f} s", flush=True)
     sys.exit(1 if bad_slots or bad_best else 0)
