@@ -15,10 +15,10 @@ from paper_1805_00106_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def _run(b, mrl, plain=True):
+def _run(b, mrl, plain=True, mode=sw.MODE_LOCAL):
     sc0 = b.scoring
     sc = sw.Scoring.make(sc0.match, sc0.mismatch, sc0.gap_open, sc0.gap_extend, sc0.band, sw.PREC_INT16,
-                         sw.KERNEL_AUTO, mrl)
+                         sw.KERNEL_AUTO, mrl, mode)
     refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
     db = sw.DeviceBatch.upload(b)
     ctx = sw.Context(db.n_reads, db.n_cals)
@@ -39,7 +39,7 @@ def _run(b, mrl, plain=True):
     return got
 
 
-def _properties(b, got):
+def _properties(b, got, final_row=False):
     sc = b.scoring
     owner = np.repeat(np.arange(b.n_reads), np.diff(b.cal_ptr))
     L = np.repeat(b.read_len[owner].astype(np.int64), 2)
@@ -52,6 +52,8 @@ def _properties(b, got):
     assert ((re == -1) == zero).all() and ((qe == -1) == zero).all()
     nz = ~zero
     assert ((qe[nz] >= 0) & (qe[nz] < L[nz])).all()
+    if final_row:
+        assert (qe[nz] == L[nz] - 1).all()   # the alignment ends at the read's last base
     assert ((re[nz] >= ws[nz]) & (re[nz] < we[nz])).all()
     # per read and reference: the best is the maximum of the read's slots on that
     # reference, the best slot the lowest one holding it, the tie count how many do
@@ -71,11 +73,11 @@ def _properties(b, got):
         np.testing.assert_array_equal(got["best_slot"][:, k], bl)
 
 
-def _sample(b, got, n=1500, seed=11):
+def _sample(b, got, n=1500, seed=11, final_row=False):
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(b.n_reads, n, replace=False))
     sub = b.subset_reads(idx)
-    s, r, e, _ = orc.align_batch(sub, n_threads=16)
+    s, r, e, _ = orc.align_batch(sub, n_threads=16, final_row=final_row)
     bs, bl, nt = orc.reduce_best(sub.cal_ptr, sub.cal_ref, sub.n_reads, sub.n_refs, s)
     sel = np.concatenate([np.arange(b.cal_ptr[i], b.cal_ptr[i + 1]) for i in idx])
     slots = np.stack([2 * sel, 2 * sel + 1], 1).reshape(-1)
@@ -118,3 +120,11 @@ def test_two_references_full_size():
     idx = np.sort(rng.choice(b.n_reads, 1000, replace=False))
     cls = sw.classify(torch.from_numpy(got["best_score"]).cuda(), 40).cpu().numpy()
     np.testing.assert_array_equal(cls[idx], orc.classify(got["best_score"][idx], 40))
+
+
+def test_chromosome_scale_full_size_final_row():
+    """The chromosome-scale workload in read-end-anchored (final-row) scoring."""
+    b = wl.chromosome_scale()
+    got = _run(b, 100, mode=sw.MODE_FINAL_ROW)
+    _properties(b, got, final_row=True)
+    _sample(b, got, n=1000, final_row=True)
