@@ -128,3 +128,44 @@ def test_chromosome_scale_full_size_final_row():
     got = _run(b, 100, mode=sw.MODE_FINAL_ROW)
     _properties(b, got, final_row=True)
     _sample(b, got, n=1000, final_row=True)
+
+
+def test_traceback_full_size_best_slots():
+    """Start and CIGAR of every read's best slot on the chromosome-scale workload
+    (1 M traced slots): a seeded sample against the oracle, and every CIGAR spans
+    its read and ends at the reported end cell."""
+    b = wl.chromosome_scale()
+    sc0 = b.scoring
+    sc = sw.Scoring.make(sc0.match, sc0.mismatch, sc0.gap_open, sc0.gap_extend, sc0.band, sw.PREC_INT16,
+                         sw.KERNEL_AUTO, 100)
+    refs = sw.RefSet.from_codes(torch.from_numpy(b.ref_codes).cuda(), b.ref_off, b.ref_len)
+    db = sw.DeviceBatch.upload(b)
+    out = sw.align_batch(db, refs, sc)
+    bs, bl, _ = sw.reduce_best(db, b.n_refs, out.score)
+    slots = bl[:, 0].contiguous()
+    rs, qs, nops, cig = sw.traceback(db, refs, sc, out, slots, cap=64)
+    torch.cuda.synchronize()
+    slots_h, nops_h = slots.cpu().numpy(), nops.cpu().numpy()
+    rs_h, qs_h = rs.cpu().numpy(), qs.cpu().numpy()
+    cig_h = cig.cpu().numpy().view(np.uint32).reshape(b.n_reads, 64)
+    score, ref_end = out.score.cpu().numpy(), out.ref_end.cpu().numpy()
+    assert (slots_h >= 0).all() and (nops_h > 0).all()
+    # every CIGAR: read bases consumed = L, reference span ends at ref_end
+    n = nops_h.astype(np.int64)
+    mask = np.arange(64)[None, :] < n[:, None]
+    length, op = (cig_h >> 4).astype(np.int64) * mask, (cig_h & 15) * mask
+    read_ops = np.isin(op, (1, 4, 7, 8)) & mask
+    ref_ops = np.isin(op, (2, 7, 8)) & mask
+    np.testing.assert_array_equal((length * read_ops).sum(1), b.read_len.astype(np.int64))
+    np.testing.assert_array_equal(rs_h + (length * ref_ops).sum(1) - 1, ref_end[slots_h])
+    # a sample against the oracle (its slots renumbered to the sample's batch)
+    rng = np.random.default_rng(13)
+    idx = np.sort(rng.choice(b.n_reads, 500, replace=False))
+    sub = b.subset_reads(idx)
+    s, r, e, _ = orc.align_batch(sub, n_threads=16)
+    obs, obl, _ = orc.reduce_best(sub.cal_ptr, sub.cal_ref, sub.n_reads, sub.n_refs, s)
+    ors, oqs, onops, ocig = orc.traceback(sub, s, r, e, obl[:, 0].astype(np.int64), cap=64, max_read_len=100)
+    np.testing.assert_array_equal(rs_h[idx], ors)
+    np.testing.assert_array_equal(qs_h[idx], oqs)
+    np.testing.assert_array_equal(nops_h[idx], onops)
+    np.testing.assert_array_equal(cig_h[idx], ocig.reshape(len(idx), 64))
