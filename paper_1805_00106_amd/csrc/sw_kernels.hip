@@ -16,6 +16,7 @@
 
 #include "sw_device.h"
 #include "sw_halfmax.h"
+#include "sw_lanes.h"
 #include "sw_launch.h"
 
 namespace swk {
@@ -736,8 +737,7 @@ __global__ __launch_bounds__(64) void k_intra32(const AlignArgs A, const RefTabl
     const int W = __shfl(t.W, 0, 64);
     const int k = __shfl(t.k, 0, 64);
     const int r = __shfl(t.r, 0, 64);
-    const int64_t ws = (int64_t)__shfl((int)(t.ws & 0xffffffff), 0, 64) |
-                       ((int64_t)__shfl((int)(t.ws >> 32), 0, 64) << 32);
+    const int64_t ws = shfl_i64([](int v, int src) { return __shfl(v, src, 64); }, t.ws, 0);
     __syncthreads();
     // stage the oriented read (one code per row) and the window words
     const uint32_t *rp = A.reads + A.read_word_off[r];

@@ -143,14 +143,21 @@ def concat_aligned(seqs: List[np.ndarray]):
     return out, offs, lens
 
 
-def uniform_genome(rng: np.random.Generator, n: int) -> np.ndarray:
-    """Uniform i.i.d. ACGT codes (four codes per random byte)."""
+def uniform_genome(rng: np.random.Generator, n: int, out: Optional[np.ndarray] = None) -> np.ndarray:
+    """Uniform i.i.d. ACGT codes (four codes per random byte).  With ``out`` (a
+    uint8 array of n codes), the codes are written there in place."""
     nbytes = (n + 3) // 4
     raw = rng.integers(0, 256, nbytes, dtype=np.uint8)
-    out = np.empty(nbytes * 4, dtype=np.uint8)
+    if out is None:
+        full = np.empty(nbytes * 4, dtype=np.uint8)
+        for k in range(4):
+            full[k::4] = (raw >> (2 * k)) & 3
+        return full[:n]
+    assert out.dtype == np.uint8 and out.shape == (n,)
     for k in range(4):
-        out[k::4] = (raw >> (2 * k)) & 3
-    return out[:n]
+        dst = out[k::4]
+        np.bitwise_and(np.right_shift(raw[:dst.shape[0]], 2 * k), 3, out=dst)
+    return out
 
 
 def _substitute(rng: np.random.Generator, codes: np.ndarray, rate: float) -> np.ndarray:
@@ -547,13 +554,86 @@ def random_small_batch(seed: int, n_refs: int = 2, ref_len=(40, 400), n_reads: i
 def served_references(scale: float = 1.0):
     """Two resident references (3.2 Gbp and 2.7 Gbp at scale 1), random with 5%
     planted repeats."""
+    codes, offs, lens = served_reference_pack(scale)
+    return [codes[int(o):int(o) + int(n)] for o, n in zip(offs, lens)]
+
+
+def served_reference_pack(scale: float = 1.0, progress=None):
+    """The two served references drawn straight into one concatenated code array
+    (each at a 16-aligned offset), as (codes, offsets, lengths): the same codes
+    as ``served_references`` without a second copy.  ``progress(msg)`` is called
+    after each reference."""
     g = seed_streams(5)
-    out = []
-    for n in (int(3.2e9 * scale), int(2.7e9 * scale)):
-        genome = uniform_genome(g["reference"], n)
+    lens = np.array([int(3.2e9 * scale), int(2.7e9 * scale)], dtype=np.int64)
+    offs, total = aligned_offsets(lens)
+    codes = np.zeros(total, dtype=np.uint8)
+    for k, n in enumerate(lens):
+        genome = codes[int(offs[k]):int(offs[k]) + int(n)]
+        uniform_genome(g["reference"], int(n), out=genome)
         plant_repeats(g["repeats"], genome, 0.05 if scale >= 0.01 else 0.0)
-        out.append(genome)
-    return out
+        if progress:
+            progress(f"served reference {k}: {int(n):,} bases drawn")
+    return codes, offs, lens
+
+
+def long_reference(n_reads: int = 600, long_len: int = (1 << 32) + 3_000_005, patch: int = 4096,
+                   read_len=(75, 250), band: int = 32) -> Batch:
+    """Reads on a reference longer than 2^32 bases, at the positions where 64-bit
+    reference coordinates matter: around 2^31 and 2^32, near both ends, and in
+    between.  Reference 0 is a short random sequence, so the long one (reference
+    1) starts past word 0.  The long reference is all code 0 except random
+    patches of ``patch`` bases around those loci: the array is allocated lazily,
+    so only the patches take host memory.  Reads (length uniform in
+    ``read_len``, 1% substitutions, either strand) come from the patches; each
+    has its true locus plus 1..5 decoys in other patches (either reference),
+    with both strands requested.  ``ref_patches`` lists the stretches that hold
+    random codes (everything else is code 0)."""
+    g = seed_streams(9)
+    short = uniform_genome(g["reference"], 10_000)
+    loci = [0, 1 << 30, (1 << 31) - patch // 2, (1 << 31) + patch, 3_000_000_000, (1 << 32) - patch // 2,
+            (1 << 32) + patch, long_len - patch]
+    lens = np.array([len(short), long_len], dtype=np.int64)
+    offs, total = aligned_offsets(lens)
+    ref_codes = np.zeros(total, dtype=np.uint8)  # lazily zero: untouched pages take no memory
+    ref_codes[offs[0]:offs[0] + lens[0]] = short
+    patches = [(0, 0, len(short))]
+    for a in loci:
+        a = int(min(max(a, 0), long_len - patch))
+        ref_codes[offs[1] + a:offs[1] + a + patch] = uniform_genome(g["reference"], patch)
+        patches.append((1, a, patch))
+    rr, re_ = g["reads"], g["errors"]
+    L = rr.integers(read_len[0], read_len[1] + 1, n_reads)
+    mat = np.zeros((n_reads, int(L.max())), dtype=np.uint8)
+    src = rr.integers(0, len(patches), n_reads)
+    true_ref = np.zeros(n_reads, np.int64)
+    true_pos = np.zeros(n_reads, np.int64)
+    rev = rr.integers(0, 2, n_reads)
+    for i in range(n_reads):
+        k, a, n = patches[src[i]]
+        start = a + int(rr.integers(0, n - L[i] + 1))
+        seq = ref_codes[offs[k] + start:offs[k] + start + L[i]].copy()
+        seq = _substitute(re_, seq, 0.01)
+        if rev[i]:
+            seq = (3 - seq)[::-1]
+        mat[i, :L[i]] = seq
+        true_ref[i], true_pos[i] = k, start
+    counts = 1 + g["cals"].integers(1, 6, n_reads)
+    cal_pos, cal_ref = [], []
+    for i in range(n_reads):
+        cal_pos.append(true_pos[i])
+        cal_ref.append(true_ref[i])
+        for _ in range(counts[i] - 1):
+            k, a, n = patches[int(g["cals"].integers(0, len(patches)))]
+            cal_pos.append(a + int(g["cals"].integers(0, max(1, n - L[i]))))
+            cal_ref.append(k)
+    cal_pos = np.array(cal_pos, np.int64)
+    cal_ref = np.array(cal_ref, np.int64)
+    strand = np.full(len(cal_pos), 3, np.int64)
+    b = _vector_batch([np.zeros(1, np.uint8)], mat, L.astype(np.int64), counts, cal_pos, cal_ref, strand,
+                      Scoring(2, -3, 5, 2, band), true_ref, true_pos, rev.astype(np.int64), "long_reference")
+    b.ref_codes, b.ref_off, b.ref_len = ref_codes, offs, lens
+    b.ref_patches = patches  # (reference, start, length) of every stretch that is not all code 0
+    return b
 
 
 def served_arrivals(rate_per_s: float, n_requests: int, seed: int = 0):

@@ -40,11 +40,22 @@ def oracle_align(batch, threads=8, mode=sw.MODE_LOCAL, topk=0):
     return res, errs
 
 
-def assert_same(got, exp, what=""):
-    for k in exp:
+# the per-slot outputs of a scoring call (without the Score Tracker's per-read ones)
+SLOTS = ("score", "ref_end", "read_end")
+
+
+def assert_same(got, exp, what="", keys=None):
+    """Element-wise equality of the outputs named by `keys` (default: every
+    output in `exp`).  An output missing from `got` fails: a dropped output must
+    not pass."""
+    for k in (exp.keys() if keys is None else keys):
         if k not in got:
-            continue
+            raise AssertionError(f"{what}: output {k} missing from the GPU results")
+        if k not in exp:
+            raise AssertionError(f"{what}: output {k} missing from the expected results")
         g, e = got[k], exp[k]
+        if g.shape != e.shape:
+            raise AssertionError(f"{what}: {k} has shape {g.shape}, expected {e.shape}")
         if not np.array_equal(g, e):
             bad = np.nonzero(g.reshape(-1) != e.reshape(-1))[0]
             i = int(bad[0])

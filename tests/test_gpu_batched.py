@@ -10,7 +10,7 @@ import torch
 
 import paper_1805_00106_amd as sw
 from paper_1805_00106_amd import workloads as wl
-from tests.gpu_util import assert_same, gpu_align, oracle_align, scoring_for
+from tests.gpu_util import SLOTS, assert_same, gpu_align, oracle_align, scoring_for
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_ctx_random_ragged(seed, precision):
     exp, _ = oracle_align(b)
     res, plan = _ctx_run(b, precision, repeats=3)
     for k, r in enumerate(res):
-        assert_same(r, exp, f"ctx seed {seed} replay {k} ({plan})")
+        assert_same(r, exp, f"ctx seed {seed} replay {k} ({plan})", keys=SLOTS)
 
 
 @pytest.mark.parametrize("band", [16, 32, 64])
@@ -56,7 +56,7 @@ def test_ctx_uneven_lengths_shape(band):
     exp, _ = oracle_align(b)
     res, plan = _ctx_run(b, sw.PREC_INT16, max_read_len=250, repeats=2)
     for r in res:
-        assert_same(r, exp, f"uneven_lengths band {band} ({plan})")
+        assert_same(r, exp, f"uneven_lengths band {band} ({plan})", keys=SLOTS)
     assert "longest first" in plan or "shortest first" in plan
 
 
@@ -77,7 +77,7 @@ def test_ctx_invalid_cals_and_capacity():
     exp, errs = oracle_align(b)
     ctx = sw.Context(b.n_reads, b.n_cals)
     res, _ = _ctx_run(b, sw.PREC_INT16, ctx=ctx)
-    assert_same(res[0], exp, "ctx invalid")
+    assert_same(res[0], exp, "ctx invalid", keys=SLOTS)
     assert ctx.error_count() == errs > 0
     small = sw.Context(1, 1)
     with pytest.raises(sw.SwError) as ei:
@@ -110,7 +110,7 @@ def test_ctx_shapes_change_and_graph_cache(tmp_path):
         for b, exp, (refs, db, out) in zip(batches, exps, prepared):
             out.score.fill_(-7)
             ctx.align(db, refs, scoring_for(b, sw.PREC_INT16, max_read_len=200), out)
-            assert_same(_host(out), exp, f"round {rnd} {ctx.last_plan()}")
+            assert_same(_host(out), exp, f"round {rnd} {ctx.last_plan()}", keys=SLOTS)
             plans.append(ctx.last_plan())
     ctx.close()
     assert all("replay" in p for p in plans[3:]), plans
@@ -122,7 +122,7 @@ def test_ctx_shapes_change_and_graph_cache(tmp_path):
     refs, db, out = prepared[0]
     ctx2.align(db, refs, scoring_for(batches[0], sw.PREC_INT16, max_read_len=200), out)
     assert "tuned=cached" in ctx2.last_plan()
-    assert_same(_host(out), exps[0], "cached plan")
+    assert_same(_host(out), exps[0], "cached plan", keys=SLOTS)
     ctx2.close()
 
 
@@ -142,5 +142,5 @@ def test_ctx_int16_tag_width_and_bias_edges(scoring, mrl):
         exp, _ = oracle_align(b)
         res, plan = _ctx_run(b, sw.PREC_INT16, max_read_len=mrl, repeats=2)
         for r in res:
-            assert_same(r, exp, f"{scoring} mrl {mrl} homopolymer={homo} ({plan})")
+            assert_same(r, exp, f"{scoring} mrl {mrl} homopolymer={homo} ({plan})", keys=SLOTS)
         assert plan.startswith("int16-pairs")

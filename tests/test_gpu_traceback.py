@@ -8,7 +8,7 @@ import torch
 import paper_1805_00106_amd as sw
 from oracle import oracle as orc
 from paper_1805_00106_amd import workloads as wl
-from tests.gpu_util import assert_same, oracle_align, scoring_for
+from tests.gpu_util import SLOTS, assert_same, oracle_align, scoring_for
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def _case(batch, slots=None, cap=64, max_read_len=None, mode=sw.MODE_LOCAL, **kw
     # both kernel families: one traced slot per lane, one per wavefront
     for kernel in (sw.KERNEL_INTER, sw.KERNEL_INTRA):
         got_s, got_t = _gpu_trace(batch, slots, cap, max_read_len=mrl, mode=mode, kernel=kernel, **kw)
-        assert_same(got_s, exp_s, f"{batch.name} scores kernel={kernel}")
+        assert_same(got_s, exp_s, f"{batch.name} scores kernel={kernel}", keys=SLOTS)
         assert_same(got_t, exp_t, f"{batch.name} traceback cap={cap} kernel={kernel}")
     # every traced CIGAR spans the read exactly and ends where the score says
     for t, slot in enumerate(slots):

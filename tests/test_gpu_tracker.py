@@ -6,7 +6,7 @@ import torch
 
 import paper_1805_00106_amd as sw
 from paper_1805_00106_amd import workloads as wl
-from tests.gpu_util import assert_same, gpu_align, oracle_align, scoring_for
+from tests.gpu_util import SLOTS, assert_same, gpu_align, oracle_align, scoring_for
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +64,7 @@ def test_final_row_batched_context_replays():
             torch.cuda.synchronize()
             got = dict(score=out.score.cpu().numpy(), ref_end=out.ref_end.cpu().numpy(),
                        read_end=out.read_end.cpu().numpy())
-            assert_same(got, want, f"ctx mode={mode} rep={rep} ({ctx.last_plan()})")
+            assert_same(got, want, f"ctx mode={mode} rep={rep} ({ctx.last_plan()})", keys=SLOTS)
     ctx.close()
 
 
