@@ -564,8 +564,7 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
     from paper_1805_00106_amd import workloads as wl
 
     t_gen = time.perf_counter()
-    refs = wl.served_references(scale=scale)
-    pack = wl.concat_aligned(refs)
+    pack = wl.served_reference_pack(scale=scale, progress=progress)
     refs = [pack[0][int(o):int(o) + int(n)] for o, n in zip(pack[1], pack[2])]  # views, no second copy
     codes = torch.from_numpy(pack[0]).cuda()
     rs = sw.RefSet.from_codes(codes, pack[1], pack[2])
@@ -576,6 +575,7 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
     pool = [wl.served_request(refs, int(n), 10_000 + k, ref_pack=pack) for k, n in enumerate(sizes)]
     pool_cells = [cells_of(b) for b in pool]
     t_gen = time.perf_counter() - t_gen
+    progress(f"served: references resident, pool of {pool_size} requests drawn ({t_gen:.0f} s)")
     sc = sw.Scoring.make(2, -3, 5, 2, 32, sw.PREC_AUTO, max_read_len=250)
     srv = sw.Server(sc, memory_budget=4 << 30, max_step_reads=65536, max_step_cals=step_cals, max_step_chunks=1024)
     srv.set_refs(rs)

@@ -34,6 +34,14 @@
 #include "sw_launch.h"
 #include "sw_serve.h"
 
+// Test builds of the host logic define SW_SERVE_MARK_BLOCK(host_ptr, bytes, live)
+// to poison the host bytes of arena blocks while they are free, so that the
+// address sanitizer reports any access outside a reservation; in the library it
+// does nothing.
+#ifndef SW_SERVE_MARK_BLOCK
+#define SW_SERVE_MARK_BLOCK(ptr, bytes, live) ((void)0)
+#endif
+
 namespace {
 
 double now_s() {
@@ -278,6 +286,7 @@ bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
     size_t off = 0;
     if (!s->arena->alloc(r.lay.total, &off)) return false;
     r.off = off;
+    SW_SERVE_MARK_BLOCK(s->arena_host + off, up256(r.lay.total), 1);
     stage_inputs(s, r, r.codes.data(), r.code_off.data(), r.cal_pos.data(), r.cal_ref.data(), r.strand.data());
   }
   r.t_admit = now_s();
@@ -457,6 +466,7 @@ void finish_loop(sw_server *s) {
     const double t = now_s();
     lk.lock();
     for (auto &rq : done) {
+      SW_SERVE_MARK_BLOCK(s->arena_host + rq->off, up256(rq->lay.total), 0);
       s->arena->release(rq->off, rq->lay.total);
       rq->t_done = t;
       rq->state = rq->error ? RS_FAILED : RS_DONE;
@@ -530,6 +540,7 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
     sw_server_destroy(s);
     return swapi::hip_fail(e);
   }
+  SW_SERVE_MARK_BLOCK(s->arena_host, opts->memory_budget, 0);
   const int64_t R = opts->max_step_reads, C = opts->max_step_cals;
   const int64_t W = R * ((m.max_read_len + 15) / 16);
   for (auto &st : s->slots) {
@@ -647,6 +658,7 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
     std::lock_guard<std::mutex> lk(s->mu);
     // reserve now if nobody waits ahead (arrival order) and memory is free
     if (s->pending.empty()) reserved = s->arena->alloc(r.lay.total, &r.off);
+    if (reserved) SW_SERVE_MARK_BLOCK(s->arena_host + r.off, up256(r.lay.total), 1);
   }
   if (reserved) {
     // the caller's thread stages its own inputs (reads packed) into the pinned arena
@@ -670,7 +682,10 @@ int sw_server_submit(sw_server_t *s, const uint8_t *read_codes, int64_t n_codes,
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
-      if (reserved) s->arena->release(r.off, r.lay.total);
+      if (reserved) {
+        SW_SERVE_MARK_BLOCK(s->arena_host + r.off, up256(r.lay.total), 0);
+        s->arena->release(r.off, r.lay.total);
+      }
       return SW_ERR_STATE;
     }
     r.id = s->next_id++;
@@ -757,7 +772,10 @@ int sw_server_destroy(sw_server_t *s) {
     if (st.hdr_host) hipHostFree(st.hdr_host);
     if (st.done) hipEventDestroy(st.done);
   }
-  if (s->arena_host) hipHostFree(s->arena_host);
+  if (s->arena_host) {
+    SW_SERVE_MARK_BLOCK(s->arena_host, s->opts.memory_budget, 1);
+    hipHostFree(s->arena_host);
+  }
   delete s;
   return SW_OK;
 }

@@ -9,9 +9,13 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <sys/resource.h>
+
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <string>
 #include <numeric>
 #include <random>
 #include <thread>
@@ -115,9 +119,225 @@ long check(const Req &q) {
   return bad;
 }
 
+
+// ---------------------------------------------------------------------------
+// The served benchmark's configuration, replayed on the CPU: a 4 GiB staging
+// budget, steps of up to 1024 chunks, 65536 reads and 1 M CALs, references of
+// 3.2 and 2.7 Gbp, a pool of requests of log-uniform 1..10000 reads (lengths
+// 75..250, 1..32 CALs per read, both strands), each reads' codes at a 16-aligned
+// offset back to back; a warm-up, then the pool submitted `rounds` times from
+// four client threads at once, then three Poisson load phases whose feeder
+// thread submits at scheduled times while the main thread waits, reads the
+// timestamps and releases each request in turn.  Every submission has its own
+// output buffers and shares its inputs with the other submissions of the same
+// pool request, as the benchmark's prepared submissions do.
+
+struct Sub {  // one submission of a pool request
+  const Req *in = nullptr;
+  Req out;  // only the output vectors and the id are used
+};
+
+Req make_bench_request(std::mt19937_64 &g, int n_reads, const int64_t *ref_len) {
+  Req q;
+  q.n_reads = n_reads;
+  q.len.resize(n_reads);
+  q.code_off.resize(n_reads);
+  int64_t at = 0;
+  for (int i = 0; i < n_reads; ++i) {
+    q.len[i] = 75 + (int)(g() % 176);
+    q.code_off[i] = at;
+    at += (q.len[i] + 15) / 16 * 16;
+  }
+  q.codes.resize((size_t)at);
+  for (auto &c : q.codes) c = (uint8_t)(g() % 4);
+  q.cal_ptr.assign(n_reads + 1, 0);
+  for (int i = 0; i < n_reads; ++i) q.cal_ptr[i + 1] = q.cal_ptr[i] + 1 + (int64_t)(g() % 32);
+  const int64_t nc = q.cal_ptr[n_reads];
+  q.cal_pos.resize(nc);
+  q.cal_ref.resize(nc);
+  q.strand.assign(nc, 3);
+  for (int64_t c = 0; c < nc; ++c) {
+    q.cal_ref[c] = (int16_t)(g() % kRefs);
+    q.cal_pos[c] = (int64_t)(g() % (uint64_t)ref_len[q.cal_ref[c]]);
+  }
+  return q;
+}
+
+void fresh_outputs(Sub &s) {
+  const Req &q = *s.in;
+  const int64_t nc = q.cal_ptr[q.n_reads];
+  s.out = Req();
+  s.out.n_reads = q.n_reads;
+  s.out.score.assign(2 * nc, -7);
+  s.out.ref_end.assign(2 * nc, -7);
+  s.out.read_end.assign(2 * nc, -7);
+  s.out.best_score.assign(q.n_reads * kRefs, -7);
+  s.out.best_slot.assign(q.n_reads * kRefs, -7);
+  s.out.n_tied.assign(q.n_reads * kRefs, -7);
+}
+
+int submit_sub(sw_server_t *srv, Sub &s) {
+  const Req &q = *s.in;
+  return sw_server_submit(srv, q.codes.data(), (int64_t)q.codes.size(), q.code_off.data(), q.len.data(), q.n_reads,
+                          q.cal_ptr.data(), q.cal_pos.data(), q.cal_ref.data(), q.strand.data(),
+                          q.cal_ptr[q.n_reads], s.out.score.data(), s.out.ref_end.data(), s.out.read_end.data(),
+                          s.out.best_score.data(), s.out.best_slot.data(), s.out.n_tied.data(), &s.out.id);
+}
+
+long check_sub(const Sub &s) {
+  Req view = *s.in;  // inputs of the pool request, outputs of this submission
+  view.score = s.out.score;
+  view.ref_end = s.out.ref_end;
+  view.read_end = s.out.read_end;
+  view.best_score = s.out.best_score;
+  view.best_slot = s.out.best_slot;
+  view.n_tied = s.out.n_tied;
+  return check(view);
+}
+
+double mono_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int run_bench(uint64_t seed, int pool_size, int rounds, int per_load) {
+  kMaxLen = 250;
+  sw_scoring_t sc{};
+  sc.match = 2;
+  sc.mismatch = -3;
+  sc.gap_open = 5;
+  sc.gap_extend = 2;
+  sc.band = 32;
+  sc.precision = SW_PREC_AUTO;
+  sc.kernel = SW_KERNEL_AUTO;
+  sc.max_read_len = 250;
+  sw_server_opts_t o{};
+  o.device = 0;
+  o.scoring = sc;
+  o.memory_budget = (size_t)4 << 30;
+  o.max_step_reads = 65536;
+  o.max_step_cals = 1 << 20;
+  o.max_step_chunks = 1024;
+  o.autotune = 0;
+  sw_server_t *srv = nullptr;
+  if (sw_server_create(&o, &srv) != SW_OK) {
+    fprintf(stderr, "create failed\n");
+    return 2;
+  }
+  static const int64_t rlen[kRefs] = {3200000000ll, 2700000000ll};
+  const int64_t woff[kRefs] = {0, (rlen[0] + 15) / 16};
+  std::vector<uint32_t> ref_words(64, 0);  // the scoring stand-in reads no reference words
+  sw_refset_t refs{ref_words.data(), woff, rlen, kRefs};
+  if (sw_server_set_refs(srv, &refs) != SW_OK) {
+    fprintf(stderr, "set_refs failed\n");
+    return 2;
+  }
+  std::mt19937_64 g(seed);
+  std::vector<Req> pool;
+  pool.reserve(pool_size);
+  double mean_reads = 0;
+  for (int k = 0; k < pool_size; ++k) {
+    const double u = (double)(g() >> 11) * (1.0 / 9007199254740992.0);
+    const int n = std::min(10000, std::max(1, (int)std::floor(std::exp(u * std::log(10001.0)))));
+    pool.push_back(make_bench_request(g, n, rlen));
+    mean_reads += n;
+  }
+  mean_reads /= pool_size;
+  long bad = 0, failed = 0, n_done = 0;
+  std::atomic<long> submit_errors{0};
+  auto finish = [&](Sub &s) {
+    int32_t done = 0;
+    if (sw_server_wait(srv, s.out.id, -1, &done) != SW_OK || !done) ++failed;
+    int32_t state = 0;
+    double t_sub = 0, t_adm = 0, t_done = 0;
+    if (sw_server_request_info(srv, s.out.id, &state, &t_sub, &t_adm, &t_done) != SW_OK || state != 3 ||
+        !(t_sub <= t_adm && t_adm <= t_done))
+      ++failed;
+    bad += check_sub(s);
+    if (sw_server_release(srv, s.out.id) != SW_OK) ++failed;
+    ++n_done;
+  };
+  // warm-up: the first requests one at a time
+  for (int k = 0; k < std::min(8, pool_size); ++k) {
+    Sub s;
+    s.in = &pool[k];
+    fresh_outputs(s);
+    if (submit_sub(srv, s) != SW_OK) submit_errors++;
+    finish(s);
+  }
+  // saturation: the pool `rounds` times over from four client threads
+  std::vector<Sub> subs((size_t)rounds * pool_size);
+  for (size_t i = 0; i < subs.size(); ++i) {
+    subs[i].in = &pool[i % pool_size];
+    fresh_outputs(subs[i]);
+  }
+  const int n_clients = 4;
+  double t0 = mono_s();
+  {
+    std::vector<std::thread> th;
+    for (int k = 0; k < n_clients; ++k)
+      th.emplace_back([&, k] {
+        for (size_t i = k; i < subs.size(); i += n_clients)
+          if (submit_sub(srv, subs[i]) != SW_OK) submit_errors++;
+      });
+    for (auto &x : th) x.join();
+  }
+  for (auto &s : subs) finish(s);
+  const double dt = mono_s() - t0;
+  double sat_reads = 0;
+  for (auto &s : subs) sat_reads += s.in->n_reads;
+  sat_reads /= dt;
+  subs.clear();
+  subs.shrink_to_fit();
+  // three Poisson load phases
+  for (double load : {0.3, 0.6, 0.9}) {
+    const double rate = load * sat_reads / mean_reads;
+    std::mt19937_64 gl(seed * 7919 + (uint64_t)(load * 1000));
+    std::exponential_distribution<double> gap(rate);
+    std::vector<double> arrive(per_load);
+    double t = 0;
+    std::vector<Sub> ls(per_load);
+    for (int i = 0; i < per_load; ++i) {
+      t += gap(gl);
+      arrive[i] = t;
+      ls[i].in = &pool[gl() % (uint64_t)pool_size];
+      fresh_outputs(ls[i]);
+    }
+    const double start = mono_s() + 0.05;
+    std::thread feeder([&] {
+      for (int i = 0; i < per_load; ++i) {
+        const double d = start + arrive[i] - mono_s();
+        if (d > 0) std::this_thread::sleep_for(std::chrono::duration<double>(d));
+        if (submit_sub(srv, ls[i]) != SW_OK) submit_errors++;
+      }
+    });
+    feeder.join();
+    for (auto &s : ls) finish(s);
+  }
+  sw_server_stats_t st{};
+  sw_server_stats(srv, &st);
+  sw_server_destroy(srv);
+  struct rusage ru {};
+  getrusage(RUSAGE_SELF, &ru);
+  printf("bench config: pool %d (mean %.1f reads), saturated %.0f reads/s on the stand-in\n", pool_size, mean_reads,
+         sat_reads);
+  printf("requests %ld, steps %lld (plain %ld, batched %ld), submit errors %ld, failed %ld, mismatches %ld, "
+         "peak rss %ld MiB\n",
+         n_done, (long long)st.steps, g_plain_calls.load(), g_ctx_calls.load(), submit_errors.load(), failed, bad,
+         (long)(ru.ru_maxrss / 1024));
+  return (bad || failed || submit_errors || g_ctx_calls == 0) ? 1 : 0;
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
+  if (argc > 1 && std::string(argv[1]) == "bench") {
+    const uint64_t seed = argc > 2 ? strtoull(argv[2], nullptr, 10) : 1;
+    const int pool_size = argc > 3 ? atoi(argv[3]) : 300;
+    const int rounds = argc > 4 ? atoi(argv[4]) : 3;
+    const int per_load = argc > 5 ? atoi(argv[5]) : 2000;
+    return run_bench(seed, pool_size, rounds, per_load);
+  }
+
   const uint64_t seed = argc > 1 ? strtoull(argv[1], nullptr, 10) : 1;
   const int n_clients = argc > 2 ? atoi(argv[2]) : 4;
   const int per_client = argc > 3 ? atoi(argv[3]) : 60;

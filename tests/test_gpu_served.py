@@ -1,7 +1,10 @@
 """GPU tests of the served path: results of every request are bit-identical
 alone and in a concurrent mix (continuous batching), match the oracle, survive
 admission under a tiny memory budget; oversize requests are rejected and
-destroy drains every submitted request."""
+destroy drains every submitted request.  The served references of the
+benchmark are longer than 2^31 bases; the last test serves requests on a
+reference longer than 2^32 bases, through small steps (one wavefront per task)
+and through the batched path."""
 import threading
 import time
 
@@ -13,13 +16,7 @@ import paper_1805_00106_amd as sw
 from oracle import oracle as orc
 from paper_1805_00106_amd import workloads as wl
 
-# Three GPU runs that included the served path ended with the GPU faulted and the
-# box lost, with no output; the cause is not shown, so the served path stays off
-# the GPU (its host logic and gather/scatter kernels run on the CPU in
-# test_host_serve.py).
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="served path kept off the GPU: three runs that included it faulted "
-                                      "the GPU, cause not shown (CPU host test: test_host_serve.py)")]
+pytestmark = pytest.mark.gpu
 
 _REFS = None
 
@@ -140,4 +137,31 @@ def test_latency_timestamps_are_ordered():
         assert srv.wait(h, 60000)
         state, t_sub, t_adm, t_done = srv.info(h)
         assert state == 3 and t_sub <= t_adm <= t_done
+    srv.close()
+
+
+@pytest.mark.parametrize("precision", [sw.PREC_AUTO, sw.PREC_INT16])
+def test_served_long_reference(precision):
+    """Requests on a reference longer than 2^32 bases.  With AUTO precision a step
+    of at most 16 CALs per compute unit takes the plain call, whose AUTO kernel
+    runs one wavefront per task; int16 keeps every step on the batched path."""
+    from tests.test_gpu_long_reference import batch_and_refs
+    b, refs, exp = batch_and_refs()
+    sc = sw.Scoring.make(2, -3, 5, 2, b.scoring.band, precision, max_read_len=int(b.read_len.max()))
+    srv = sw.Server(sc, memory_budget=64 << 20, max_step_reads=4096, max_step_cals=60000)
+    srv.set_refs(refs)
+    parts = np.array_split(np.arange(b.n_reads), 4)
+    subs = [b.subset_reads(idx) for idx in parts]
+    hs = [srv.submit_batch(x) for x in subs]
+    for h in hs:
+        assert srv.wait(h, 120000)
+    for idx, x, h in zip(parts, subs, hs):
+        s, r, e, _ = orc.align_batch(x, n_threads=8)
+        bs, bl, nt = orc.reduce_best(x.cal_ptr, x.cal_ref, x.n_reads, x.n_refs, s)
+        np.testing.assert_array_equal(h.score, s)
+        np.testing.assert_array_equal(h.ref_end, r)
+        np.testing.assert_array_equal(h.read_end, e)
+        np.testing.assert_array_equal(h.best_score, bs.reshape(-1))
+        np.testing.assert_array_equal(h.best_slot, bl.reshape(-1))
+        np.testing.assert_array_equal(h.n_tied, nt.reshape(-1))
     srv.close()

@@ -30,6 +30,14 @@ def test_usage_example_flow():
     best2, _, _ = sw.reduce_best(kept, b.n_refs, out2.score)
     # the seeds find the planted locus, whose score the synthetic CAL list also reaches
     assert (best2[:, 0] >= best[:, 0]).float().mean().item() > 0.99
-    # the served part of the example stays off the GPU (see test_gpu_served.py)
+    # served: submit host arrays, wait; the same outputs as the plain call
+    srv = sw.Server(sc, memory_budget=1 << 30)
+    srv.set_refs(refs)
+    req = srv.submit_batch(b.subset_reads(range(1000)))
+    assert srv.wait(req, 120000)
+    n_cals = int(b.cal_ptr[1000])
+    assert (req.score == out.score[:2 * n_cals].cpu().numpy()).all()
+    assert (req.ref_end == out.ref_end[:2 * n_cals].cpu().numpy()).all()
+    srv.close()
     ix.close()
     ctx.close()

@@ -1,13 +1,26 @@
 """Host test of the served path on the CPU: the server's scheduler, admission,
 staging and finisher threads, with its gather/scatter kernels run by a CPU
 stand-in of the HIP runtime (tests/host_serve/fake_hip) and the scoring calls
-replaced by a deterministic function of each read and CAL.  Several client
-threads submit requests under a small staging budget (admission waits, arena
-blocks reused, requests split over steps, both scoring paths), with read layouts
-that are tight, gapped and shuffled, or arbitrary; every output must belong to
-its own request, read, CAL and strand.  Built with the host address and
+replaced by a deterministic function of each read and CAL.
+
+The stand-in runtime is asynchronous like the real one: every stream's work
+runs later, on a worker thread of its own, with random delays; an event
+completes when the worker reaches it; a queued copy aborts if the host changed
+its source in the meantime; hipFree does not wait.  Free arena blocks are
+poisoned for the address sanitizer.  So a block released or re-staged while a
+queued step still reads it, a step header rewritten before its copy ran, or a
+buffer freed under queued work, all fail the test.
+
+Several client threads submit requests under a small staging budget (admission
+waits, arena blocks reused, requests split over steps, both scoring paths), with
+read layouts that are tight, gapped and shuffled, or arbitrary; and the served
+benchmark's own configuration is replayed (4 GiB budget, 1024 chunks, 65536
+reads and 1 M CALs per step, 3.2 and 2.7 Gbp references, a 300-request pool
+submitted three times from four client threads, then three Poisson load phases
+with waits, timestamps and releases).  Every output must belong to its own
+request, read, CAL and strand.  Built with the host address and
 undefined-behaviour sanitizers (and the thread sanitizer where ROCm's clang
-provides it), so an access outside any staging or step buffer fails the test."""
+provides it)."""
 import os
 import shutil
 import subprocess
@@ -18,7 +31,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "host_serve", f) for f in ("driver.cpp", "stubs.cpp", "serve_kernels.cpp")] + \
       [os.path.join(ROOT, "paper_1805_00106_amd", "csrc", "sw_server.cpp")]
-INC = ["-I" + os.path.join(HERE, "host_serve", "fake_hip")]
+INC = ["-I" + os.path.join(HERE, "host_serve", "fake_hip"),
+       "-include", os.path.join(HERE, "host_serve", "mark_block.h")]
 
 
 def _build(tmp_path, compiler, sanitize):
@@ -59,6 +73,13 @@ def test_served_routing_at_benchmark_scale(asan_exe):
     """The served benchmark's step sizes (1024 chunks, 65536 reads and 1 M CALs per
     step) and request sizes (1..10000 reads of up to 250 bases, up to 32 CALs)."""
     out = _run(asan_exe, 11, 4, 120, 2, 1)
+    assert "submit errors 0, failed 0" in out
+
+
+def test_served_benchmark_configuration(asan_exe):
+    """The served benchmark's configuration end to end (load phases shortened to
+    200 requests each)."""
+    out = _run(asan_exe, "bench", 7, 300, 3, 200)
     assert "submit errors 0, failed 0" in out
 
 
