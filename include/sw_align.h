@@ -347,7 +347,9 @@ typedef struct sw_ctx sw_ctx_t;
 typedef struct {
   int32_t device;         /* HIP device ordinal */
   int32_t max_reads;      /* capacity: reads per call */
-  int64_t max_cals;       /* capacity: CALs per call */
+  int64_t max_cals;       /* capacity: CALs per call, 0..(INT32_MAX / 2): the planner keeps task
+                             positions (two per CAL in int32 precision) in int32; larger
+                             capacities are rejected with SW_ERR_INVALID_ARG */
   int32_t use_graph;      /* 1: capture and replay HIP graphs per shape */
   int32_t autotune;       /* 1: time candidate plans on first use of a shape class */
   const char *tune_cache; /* optional JSON file for autotune results (may be NULL) */

@@ -162,9 +162,39 @@ def _stream(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dev(t: torch.Tensor, dtype) -> torch.Tensor:
-    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+def _dev(t: torch.Tensor, dtype, numel: Optional[int] = None, what: str = "tensor") -> torch.Tensor:
+    """A device tensor the C ABI may read or write through its address: on the
+    GPU, of the stated dtype, contiguous and (when given) of exactly `numel`
+    elements.  Raises ValueError otherwise, before any library call."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch.Tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: must be on the GPU, is on {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype must be {dtype}, is {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: must hold {numel} elements, holds {t.numel()}")
     return t
+
+
+def _check_batch(db: "DeviceBatch"):
+    """Every array of a batch, against the counts the C ABI is given."""
+    n, m = db.n_reads, db.n_cals
+    _dev(db.reads2bit, torch.int32, what="reads2bit")
+    _dev(db.read_word_off, torch.int64, n, "read_word_off")
+    _dev(db.read_len, torch.int32, n, "read_len")
+    _dev(db.cal_ptr, torch.int64, n + 1, "cal_ptr")
+    _dev(db.cal_pos, torch.int64, m, "cal_pos")
+    _dev(db.cal_ref, torch.int16, m, "cal_ref")
+    _dev(db.strand, torch.uint8, m, "strand")
+
+
+def _check_outputs(out: "Outputs", n_cals: int):
+    _dev(out.score, torch.int32, 2 * n_cals, "score")
+    _dev(out.ref_end, torch.int64, 2 * n_cals, "ref_end")
+    _dev(out.read_end, torch.int16, 2 * n_cals, "read_end")
 
 
 def pack_2bit(codes: torch.Tensor, stream=None) -> torch.Tensor:
@@ -180,6 +210,13 @@ class RefSet:
     """References resident in device memory (2-bit packed)."""
 
     def __init__(self, words: torch.Tensor, word_offset, length):
+        _dev(words, torch.int32, what="reference words")
+        if len(word_offset) != len(length) or not 1 <= len(length) <= MAX_REFS:
+            raise ValueError("word_offset and length must name the same 1..MAX_REFS references")
+        for o, n in zip(word_offset, length):
+            if int(o) < 0 or int(n) < 1 or int(o) + (int(n) + 15) // 16 > words.numel():
+                raise ValueError(f"reference at word {int(o)} of {int(n)} bases lies outside the "
+                                 f"{words.numel()} packed words")
         self.words = words
         self.word_offset = (ctypes.c_int64 * len(word_offset))(*[int(x) for x in word_offset])
         self.length = (ctypes.c_int64 * len(length))(*[int(x) for x in length])
@@ -251,12 +288,15 @@ class Outputs:
 def align_batch(db: DeviceBatch, refs: RefSet, sc: Scoring, out: Optional[Outputs] = None,
                 workspace: Optional[torch.Tensor] = None, stream=None) -> Outputs:
     """sw_align_batch on device tensors; returns (score, ref_end, read_end) tensors."""
+    _check_batch(db)
     n = db.n_cals
     if out is None:
         out = Outputs(n, db.cal_pos.device)
+    _check_outputs(out, n)
     need = workspace_bytes(db.n_reads, n, sc)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=db.cal_pos.device)
+    _dev(workspace, torch.uint8, what="workspace")
     rc = lib().sw_align_batch(_ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len), db.n_reads,
                               refs.c, _ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref), _ptr(db.strand), n,
                               ctypes.byref(sc), _ptr(out.score), _ptr(out.ref_end), _ptr(out.read_end),
@@ -266,6 +306,8 @@ def align_batch(db: DeviceBatch, refs: RefSet, sc: Scoring, out: Optional[Output
 
 
 def reduce_best(db: DeviceBatch, n_refs: int, score: torch.Tensor, stream=None):
+    _check_batch(db)
+    _dev(score, torch.int32, 2 * db.n_cals, "score")
     n = db.n_reads
     dev = score.device
     bs = torch.empty(n * n_refs, dtype=torch.int32, device=dev)
@@ -293,6 +335,8 @@ def check_half_max(stream=None) -> int:
 
 def topk(db: DeviceBatch, score: torch.Tensor, k: int, stream=None):
     """The k best slots of each read (score, slot), highest score first; -1 past the valid slots."""
+    _check_batch(db)
+    _dev(score, torch.int32, 2 * db.n_cals, "score")
     n = db.n_reads
     ts = torch.empty(n * k, dtype=torch.int32, device=score.device)
     tl = torch.empty(n * k, dtype=torch.int64, device=score.device)
@@ -303,6 +347,8 @@ def topk(db: DeviceBatch, score: torch.Tensor, k: int, stream=None):
 
 def tied_flags(db: DeviceBatch, score: torch.Tensor, stream=None) -> torch.Tensor:
     """1 for every slot whose score equals its read's best score, else 0."""
+    _check_batch(db)
+    _dev(score, torch.int32, 2 * db.n_cals, "score")
     fl = torch.empty(score.numel(), dtype=torch.uint8, device=score.device)
     _check(lib().sw_tied_flags(_ptr(db.cal_ptr), db.n_reads, db.n_cals, _ptr(score), _ptr(fl), _stream(stream)),
            "sw_tied_flags")
@@ -314,6 +360,8 @@ def traceback(db: DeviceBatch, refs: "RefSet", sc: Scoring, out: "Outputs", slot
     """Start position and CIGAR of each slot in `slots` (int64 device tensor, -1 to skip), from
     the outputs `out` of a scoring call on the same batch.  Returns (ref_start, read_start,
     n_ops, cigar[n, cap]); entries are (length << 4) | op with BAM op codes."""
+    _check_batch(db)
+    _check_outputs(out, db.n_cals)
     slots = slots.to(device=out.score.device, dtype=torch.int64).contiguous()
     n = slots.numel()
     dev = out.score.device
@@ -335,6 +383,7 @@ def cal_filter(db: DeviceBatch, bucket_bits: int = 0, stream=None, workspace: Op
     """CAL Filter on device: a DeviceBatch with each read's duplicate CALs folded
     into one (same reads), and cal_map (input CAL -> kept CAL).  Synchronises the
     stream once to read the number of kept CALs."""
+    _check_batch(db)
     dev = db.cal_pos.device
     n = db.n_cals
     out_ptr = torch.empty(db.n_reads + 1, dtype=torch.int64, device=dev)
@@ -377,6 +426,10 @@ class SeedIndex:
     def find(self, db: DeviceBatch, stride: int = 1, max_cals_per_seed: int = 0, max_read_len: int = 0,
              capacity: Optional[int] = None, stream=None) -> DeviceBatch:
         """CALs of the reads of `db` (its own CAL arrays are ignored)."""
+        n = db.n_reads
+        _dev(db.reads2bit, torch.int32, what="reads2bit")
+        _dev(db.read_word_off, torch.int64, n, "read_word_off")
+        _dev(db.read_len, torch.int32, n, "read_len")
         dev = db.read_len.device
         o = _FindOpts(stride, max_cals_per_seed, max_read_len)
         ptr = torch.empty(db.n_reads + 1, dtype=torch.int64, device=dev)
@@ -429,6 +482,9 @@ def cigar_text(entries, n_ops: int, extended: bool = True) -> str:
 
 
 def classify(best_score: torch.Tensor, threshold: int, stream=None) -> torch.Tensor:
+    if best_score.dim() != 2:
+        raise ValueError("best_score must be [n_reads, n_refs]")
+    best_score = _dev(best_score.contiguous(), torch.int32, what="best_score")
     n, k = best_score.shape
     cls = torch.empty(n, dtype=torch.int32, device=best_score.device)
     _check(lib().sw_classify(_ptr(best_score.contiguous()), n, k, threshold, _ptr(cls), _stream(stream)),
@@ -460,8 +516,10 @@ class Context:
             pass
 
     def align(self, db: DeviceBatch, refs: RefSet, sc: Scoring, out: Optional[Outputs] = None, stream=None):
+        _check_batch(db)
         if out is None:
             out = Outputs(db.n_cals, db.cal_pos.device)
+        _check_outputs(out, db.n_cals)
         rc = lib().sw_align_batch_ctx(self._h, _ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len),
                                       db.n_reads, refs.c, _ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref),
                                       _ptr(db.strand), db.n_cals, ctypes.byref(sc), _ptr(out.score),

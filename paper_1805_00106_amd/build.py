@@ -25,7 +25,18 @@ def _compile(src, obj):
     return r.stderr
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src, obj):
+    """An object older than its source or than any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(os.path.dirname(HERE), "include", "sw_align.h"))
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, changed_only: bool = False) -> str:
+    """Compile every source (changed_only: only objects older than their inputs) and link."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     from concurrent.futures import ThreadPoolExecutor
@@ -34,6 +45,8 @@ def build(verbose: bool = False) -> str:
         for s in SOURCES:
             obj = os.path.join(BUILD, os.path.splitext(s)[0] + ".o")
             objs.append(obj)
+            if changed_only and not _stale(s, obj):
+                continue
             jobs.append((s, ex.submit(_compile, s, obj)))
         for s, j in jobs:
             t0 = time.time()
@@ -49,4 +62,4 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     t = time.time()
-    print(build(verbose=True), f"{time.time() - t:.1f}s")
+    print(build(verbose=True, changed_only="--changed" in sys.argv), f"{time.time() - t:.1f}s")

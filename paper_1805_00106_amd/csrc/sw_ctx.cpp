@@ -222,6 +222,8 @@ int sw_ctx_create(const sw_ctx_opts_t *opts, sw_ctx_t **out) {
   if (!opts || !out) return SW_ERR_INVALID_ARG;
   *out = nullptr;
   if (opts->max_reads < 0 || opts->max_cals < 0 || opts->device < 0) return SW_ERR_INVALID_ARG;
+  // the planner keeps task positions (up to two per CAL) in int32
+  if (opts->max_cals > (int64_t)INT32_MAX / 2) return SW_ERR_INVALID_ARG;
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess) return swapi::hip_fail(e);
@@ -318,6 +320,7 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
   swk::RefTable T;
   rc = swapi::validate_refs(refs, n_cals, &T);
   if (rc) return rc;
+  // within the capacity, which also keeps every task position inside int32
   if (n_reads > c->max_reads || n_cals > c->max_cals) return SW_ERR_WORKSPACE;
   if (n_cals == 0) return SW_OK;
   hipError_t e = hipSetDevice(c->device);

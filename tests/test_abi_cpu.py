@@ -168,3 +168,32 @@ def test_alu_peak_validation(sw):
     assert L.sw_alu_peak(16, 4, ctypes.byref(v), None) == -1
     assert L.sw_alu_peak(32, 1 << 10, None, None) == -1
     assert L.sw_check_half_max(None, None) == -1
+
+
+def test_ctx_capacity_validation(sw):
+    """Task positions are int32 in the batched planner (two tasks per CAL in int32
+    precision): a capacity whose task count leaves int32 is rejected before any
+    HIP call."""
+    L = sw.lib()
+    h = ctypes.c_void_p()
+    for max_cals in (-1, (2**31 - 1) // 2 + 1, 1 << 40):
+        o = sw._CtxOpts(0, 16, max_cals, 1, 0, None)
+        assert L.sw_ctx_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    o = sw._CtxOpts(-1, 16, 16, 1, 0, None)
+    assert L.sw_ctx_create(ctypes.byref(o), ctypes.byref(h)) == -1
+
+
+def test_binding_rejects_malformed_tensors(sw):
+    """The binding checks dtype, device, contiguity and element counts of every
+    tensor before any library call (on this host, CPU tensors fail the device
+    check first)."""
+    import torch
+    t = torch.zeros(4, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        sw._dev(t, torch.int64, what="cal_pos")
+    db = sw.DeviceBatch(torch.zeros(4, dtype=torch.int32), torch.zeros(2, dtype=torch.int64),
+                        torch.zeros(2, dtype=torch.int32), torch.zeros(3, dtype=torch.int64),
+                        torch.zeros(3, dtype=torch.int32), torch.zeros(3, dtype=torch.int16),
+                        torch.zeros(3, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        sw._check_batch(db)
