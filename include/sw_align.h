@@ -147,6 +147,26 @@ int sw_align_batch(const uint32_t *reads2bit, const int64_t *read_word_off, cons
                    int64_t n_cals, const sw_scoring_t *sc, int32_t *score, int64_t *ref_end,
                    int16_t *read_end, void *workspace, size_t workspace_bytes, sw_stream_t stream);
 
+/*
+ * sw_align_batch without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The same kernels and
+ * outputs as sw_align_batch; its scratch (the owner-read array and the strip
+ * scratch, sw_workspace_bytes(n_reads, n_cals, sc) bytes) lives in one static
+ * device array of SW_NOALLOC_SCRATCH_BYTES per device, which the library holds
+ * from load until the process ends.  A call whose scratch would exceed it
+ * returns SW_ERR_WORKSPACE.  Every call on a device shares that device's array:
+ * calls that overlap on one device (other streams, other host threads) race and
+ * must be serialised by the caller.  The first call on a device looks up the
+ * array's device address (no allocation); nothing in it needs clearing.
+ */
+#define SW_NOALLOC_SCRATCH_BYTES (128u << 20)
+int sw_align_batch_noalloc(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
+                           int32_t n_reads, const sw_refset_t *refs, const int64_t *cal_ptr,
+                           const int64_t *cal_pos, const int16_t *cal_ref, const uint8_t *strand,
+                           int64_t n_cals, const sw_scoring_t *sc, int32_t *score, int64_t *ref_end,
+                           int16_t *read_end, sw_stream_t stream);
+
 /* Workspace size for sw_align_batch (0 is never returned for n_cals > 0). */
 size_t sw_workspace_bytes(int32_t n_reads, int64_t n_cals, const sw_scoring_t *sc);
 

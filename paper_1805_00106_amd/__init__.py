@@ -14,7 +14,7 @@ from typing import Optional
 import torch  # load torch's HIP runtime before the library so both share it
 
 __all__ = [
-    "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch",
+    "lib", "Scoring", "RefSet", "DeviceBatch", "pack_2bit", "workspace_bytes", "align_batch", "align_batch_noalloc",
     "reduce_best", "topk", "tied_flags", "classify", "error_count", "traceback", "cigar_text", "cal_filter", "SeedIndex", "alu_peak", "check_half_max", "SwError", "Context", "Outputs", "Server", "Request",
     "PREC_AUTO", "PREC_INT16", "PREC_INT32", "KERNEL_AUTO", "KERNEL_INTER", "KERNEL_INTRA",
     "MODE_LOCAL", "MODE_FINAL_ROW", "MAX_READ_LEN", "MAX_REFS", "MAX_TOPK",
@@ -101,6 +101,8 @@ def lib():
         L.sw_workspace_bytes.argtypes = [i32, i64, ctypes.POINTER(Scoring)]
         L.sw_align_batch.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, vp, i64,
                                      ctypes.POINTER(Scoring), vp, vp, vp, vp, sz, vp]
+        L.sw_align_batch_noalloc.argtypes = [vp, vp, vp, i32, ctypes.POINTER(_RefSetC), vp, vp, vp, vp, i64,
+                                             ctypes.POINTER(Scoring), vp, vp, vp, vp]
         L.sw_error_count.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.sw_reduce_best.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp, vp]
         L.sw_classify.argtypes = [vp, i32, i32, i32, vp, vp]
@@ -302,6 +304,23 @@ def align_batch(db: DeviceBatch, refs: RefSet, sc: Scoring, out: Optional[Output
                               ctypes.byref(sc), _ptr(out.score), _ptr(out.ref_end), _ptr(out.read_end),
                               _ptr(workspace), workspace.numel(), _stream(stream))
     _check(rc, "sw_align_batch")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def align_batch_noalloc(db: DeviceBatch, refs: RefSet, sc: Scoring, out: Outputs, stream=None) -> Outputs:
+    """sw_align_batch_noalloc: the plain scoring call with its scratch in the
+    library's static device array (no allocation in the library; the caller
+    brings the outputs).  Calls that overlap on one device race."""
+    _check_batch(db)
+    _check_outputs(out, db.n_cals)
+    rc = lib().sw_align_batch_noalloc(_ptr(db.reads2bit), _ptr(db.read_word_off), _ptr(db.read_len), db.n_reads,
+                                      refs.c, _ptr(db.cal_ptr), _ptr(db.cal_pos), _ptr(db.cal_ref), _ptr(db.strand),
+                                      db.n_cals, ctypes.byref(sc), _ptr(out.score), _ptr(out.ref_end),
+                                      _ptr(out.read_end), _stream(stream))
+    _check(rc, "sw_align_batch_noalloc")
     return out
 
 

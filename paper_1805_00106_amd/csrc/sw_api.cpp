@@ -350,6 +350,64 @@ int sw_align_batch(const uint32_t *reads2bit, const int64_t *read_word_off, cons
                    n_cals, sc, score, ref_end, read_end, workspace, err, (hipStream_t)stream);
 }
 
+// The scratch of sw_align_batch_noalloc: a file-scope device array that the
+// code object loads once per device (held until the process ends).  In host
+// code its name is only a stand-in for the symbol; the device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[SW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[64];
+
+int noalloc_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= 64) return SW_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (!p) return hip_fail(hipErrorInvalidSymbol);
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return SW_OK;
+}
+}  // namespace
+
+int sw_align_batch_noalloc(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,
+                           int32_t n_reads, const sw_refset_t *refs, const int64_t *cal_ptr, const int64_t *cal_pos,
+                           const int16_t *cal_ref, const uint8_t *strand, int64_t n_cals, const sw_scoring_t *sc,
+                           int32_t *score, int64_t *ref_end, int16_t *read_end, sw_stream_t stream) {
+  ScoreMode m;
+  int rc = validate_scoring(sc, &m);
+  if (rc) return rc;
+  rc = validate_batch(reads2bit, read_word_off, read_len, n_reads, cal_ptr, cal_pos, cal_ref, strand, n_cals,
+                      score, ref_end, read_end);
+  if (rc) return rc;
+  swk::RefTable T;
+  rc = validate_refs(refs, n_cals, &T);
+  if (rc) return rc;
+  if (n_cals == 0) return SW_OK;
+  PlainPlan plan;
+  rc = make_plan(n_cals, sc, 0, &plan);
+  if (rc) return rc;
+  // the plan's owner-read array and strip scratch must fit the static array
+  if (plan.bytes > (size_t)SW_NOALLOC_SCRATCH_BYTES) return SW_ERR_WORKSPACE;
+  void *ws = nullptr;
+  rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  unsigned long long *err = swk::error_counter();
+  if (!err) return hip_fail(hipErrorInvalidDevice);
+  // nothing in the scratch has to start at zero: the owner-read array is filled
+  // by the expansion kernels and each strip row is written before it is read
+  return run_plain(plan, T, reads2bit, read_word_off, read_len, n_reads, refs, cal_ptr, cal_pos, cal_ref, strand,
+                   n_cals, sc, score, ref_end, read_end, ws, err, (hipStream_t)stream);
+}
+
 int sw_error_count(int64_t *n_invalid, int reset) {
   if (!n_invalid) return SW_ERR_INVALID_ARG;
   unsigned long long *err = swk::error_counter();
