@@ -40,12 +40,15 @@ OPS_PER_CELL = 12  # algorithmic integer ops per DP cell (E: 3, F: 3, substituti
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 32-bit lane-ops/s; packed 16-bit ops do two per lane.
 PEAK_INT16_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
+# The bound the scoring kernels reach: VALU instruction issue, one instruction per lane per cycle
+# on every SIMD (256 CUs x 64 lanes x 2.4 GHz), packed or not.
+ISSUE_PEAK = 256 * 64 * 2.4e9
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("sw_kernels.hip", "sw_device.h", "sw_halfmax.h", "sw_launch.h"):
+    for name in ("sw_kernels.hip", "sw_device.h", "sw_halfmax.h", "sw_launch.h", "sw_lanes.h"):
         with open(os.path.join(ROOT, "paper_1805_00106_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -77,6 +80,34 @@ def load_issue(kernel: str, workload: str):
     return rec
 
 
+def roofline(kernel: str, workload: str, cells: int, kern_ms: float, packed: bool) -> dict:
+    """VALU-issue roofline of one scoring kernel.  `achieved` = VALU lane-instructions
+    the kernel issues per second: its lane-instructions per cell, from the rocprofv3
+    counter profile taken on the current kernel source (SQ_INSTS_VALU x 64 / cells),
+    times the cells, over the kernel time measured here; `peak` = one instruction
+    per lane per cycle on every SIMD.  The 12-algorithmic-op view is kept apart: the
+    kernels do those 12 ops in fewer instructions (one three-way maximum does a
+    maximum and its clamp, one byte permutation gives both strands' substitution
+    scores), so it is not a fraction of any peak."""
+    rec = {"bound": "alu", "unit": "T VALU lane-instructions/s", "peak": round(ISSUE_PEAK / 1e12, 2),
+           "kernel": kernel, "kernel_ms": round(kern_ms, 3),
+           "kernel_gcups": round(cells / (kern_ms * 1e-3) / 1e9, 1)}
+    v = load_issue(kernel, workload)
+    if v:
+        issued = v["lane_insts_per_cell"] * cells / (kern_ms * 1e-3)
+        rec.update(achieved=round(issued / 1e12, 3), frac=round(issued / ISSUE_PEAK, 4),
+                   lane_insts_per_cell=v["lane_insts_per_cell"], valu_busy_profiled=v.get("valu_busy"),
+                   profile=f"profiles/valu_{kernel}_{workload}.json")
+    else:
+        rec.update(achieved=None, frac=None,
+                   note="no VALU counter profile taken on the current kernel source")
+    alg_peak = PEAK_INT16_TOPS if packed else PEAK_INT32_TOPS
+    alg = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
+    rec["alg_ops_per_s"] = {"ops_per_cell": OPS_PER_CELL, "achieved_tops": round(alg, 2),
+                            "published_int_peak_tops": round(alg_peak, 2), "ratio": round(alg / alg_peak, 4)}
+    return rec
+
+
 def cells_of(batch) -> int:
     """Sum of L x W over the requested tasks (W clipped at the reference ends)."""
     r_of = np.repeat(np.arange(batch.n_reads), np.diff(batch.cal_ptr))
@@ -92,7 +123,11 @@ def cpu_baseline(batch, target_s: float = 15.0):
     """Time the oracle (as it stands) on a bounded sample of the same workload."""
     from oracle import oracle as orc
 
-    cores = min(16, os.cpu_count() or 1)
+    # one oracle thread per host core this process may use, up to the 16 cores that
+    # are one GPU's share of the host on this machine class
+    nproc = os.cpu_count() or 1
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
+    cores = max(1, min(usable, 16))
     rng = np.random.default_rng(12345)
     probe = batch.subset_reads(np.sort(rng.choice(batch.n_reads, 200, replace=False)))
     t0 = time.perf_counter()
@@ -110,6 +145,7 @@ def cpu_baseline(batch, target_s: float = 15.0):
     orc.align_batch(one, n_threads=1)
     dt1 = time.perf_counter() - t0
     return {"value": round(cells_of(sample) / dt / 1e9, 3), "unit": "GCUPS", "cores": cores, "kind": "oracle",
+            "nproc": nproc, "usable_cores": usable,
             "sample": f"{n} of {batch.n_reads} reads ({sample.n_cals} CALs, both strands, "
                       f"{cells_of(sample):.3e} cells) in {dt:.1f} s",
             "reads_per_s": round(n / dt, 1),
@@ -324,8 +360,8 @@ class Leg:
         sc = self.batch.scoring
         res = {}
         measured = {"int32": sw.alu_peak(32) / 1e12, "final_row_int16": sw.alu_peak(16) / 1e12}
-        for name, prec, mode, peak in (("int32", sw.PREC_INT32, sw.MODE_LOCAL, PEAK_INT32_TOPS),
-                                       ("final_row_int16", sw.PREC_INT16, sw.MODE_FINAL_ROW, PEAK_INT16_TOPS)):
+        for name, prec, mode in (("int32", sw.PREC_INT32, sw.MODE_LOCAL),
+                                 ("final_row_int16", sw.PREC_INT16, sw.MODE_FINAL_ROW)):
             scv = sw.Scoring.make(sc.match, sc.mismatch, sc.gap_open, sc.gap_extend, sc.band, prec,
                                   sw.KERNEL_INTER, self.scoring.max_read_len, mode)
             out = sw.Outputs(self.db.n_cals, self.db.read_len.device)
@@ -340,10 +376,10 @@ class Leg:
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             gcups = self.cells / (ms * 1e-3) / 1e9
+            kern = "inter32_queue" if prec == sw.PREC_INT32 else "inter16_queue_final_row"
             res[name] = {"ms_per_step": round(ms, 3), "gcups": round(gcups, 1),
-                         "roofline_frac": round(OPS_PER_CELL * gcups * 1e9 / (peak * 1e12), 4),
+                         "roofline": roofline(kern, "chromosome_scale", self.cells, ms, prec != sw.PREC_INT32),
                          "peak_measured_tops": round(measured[name], 2),
-                         "frac_of_measured": round(OPS_PER_CELL * gcups * 1e9 / (measured[name] * 1e12), 4),
                          "plan": self.ctx.last_plan()}
             if self.parity_reads:
                 res[name]["parity_sample_ok"] = parity_sample(self.batch, out,
@@ -554,7 +590,12 @@ def classification_leg(n_reads: int, threshold: int = ALIGNED_THRESHOLD, parity:
     return out
 
 
-def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9), step_cals: int = 1 << 20):
+def sat_reads_of(pool, rounds, dt):
+    return rounds * sum(b.n_reads for b in pool) / dt
+
+
+def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9), step_cals: int = 1 << 20,
+               parity_requests: int = 24):
     """Served requests: two resident references, Poisson arrivals of log-uniform request
     sizes, p50/p99 latency (scheduled arrival -> completion) at three loads
     relative to the measured saturated throughput."""
@@ -603,12 +644,30 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
     dt = time.monotonic() - t0
     for h in hs:
         srv.release(h)
+    # results of the first pass over the pool: every later submission of the same
+    # request, in whatever mix of other requests, must give exactly these
+    first = [(h.score, h.ref_end, h.read_end, h.best_score, h.best_slot, h.n_tied) for h in hs[:pool_size]]
     del preps, hs
-    sat_reads = rounds * sum(b.n_reads for b in pool) / dt
+    # per-request oracle parity on a seeded sample of the pool (not timed)
+    from oracle import oracle as orc
+    prng = np.random.default_rng(5)
+    sample = np.sort(prng.choice(pool_size, min(parity_requests, pool_size), replace=False)) if parity_requests else []
+    parity_ok = True
+    for k in sample:
+        b = pool[int(k)]
+        s_, r_, e_, _ = orc.align_batch(b, n_threads=min(16, os.cpu_count() or 1))
+        bs_, bl_, nt_ = orc.reduce_best(b.cal_ptr, b.cal_ref, b.n_reads, b.n_refs, s_)
+        got = first[int(k)]
+        parity_ok &= all(np.array_equal(x, y) for x, y in zip(got, (s_, r_, e_, bs_.reshape(-1), bl_.reshape(-1),
+                                                                  nt_.reshape(-1))))
+    progress(f"served: saturated {sat_reads_of(pool, rounds, dt):.0f} reads/s; oracle parity on "
+             f"{len(sample)} requests: {parity_ok}")
+    sat_reads = sat_reads_of(pool, rounds, dt)
     sat_gcups = rounds * sum(pool_cells) / dt / 1e9
     mean_reads = float(np.mean([b.n_reads for b in pool]))
 
     results = []
+    same_in_every_mix = True
     for load in loads:
         rate = load * sat_reads / mean_reads          # requests per second
         g = np.random.default_rng(int(load * 1000))
@@ -635,6 +694,8 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
             lat[i] = t_done - (start + arrivals[i])
             done_last = max(done_last, t_done)
             srv.release(h)
+            same_in_every_mix &= all(np.array_equal(x, y) for x, y in zip(
+                (h.score, h.ref_end, h.read_end, h.best_score, h.best_slot, h.n_tied), first[int(picks[i])]))
         keep = lat[per_load // 10:]                    # 10% warm-up dropped
         span = done_last - start
         results.append({"load": load, "offered_requests_per_s": round(rate, 1), "requests": per_load,
@@ -643,6 +704,7 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
                         "mean_ms": round(float(keep.mean()) * 1e3, 3),
                         "achieved_reads_per_s": round(sum(pool[k].n_reads for k in picks) / span, 1),
                         "achieved_gcups": round(sum(pool_cells[k] for k in picks) / span / 1e9, 1)})
+        progress(f"served: load {load}: p50 {results[-1]['p50_ms']} ms, p99 {results[-1]['p99_ms']} ms")
     stats = srv.stats()
     srv.close()
     return {"workload": f"served requests: resident references of {int(pack[2][0]):,} and {int(pack[2][1]):,} bp "
@@ -652,6 +714,8 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
             "saturated": {"reads_per_s": round(sat_reads, 1), "gcups": round(sat_gcups, 1),
                           "requests_per_s": round(rounds * pool_size / dt, 1)},
             "mean_request_reads": round(mean_reads, 1), "loads": results, "steps": stats["steps"],
+            "parity_sample_ok": bool(parity_ok), "parity_requests": len(sample),
+            "same_result_in_every_mix": bool(same_in_every_mix),
             "max_step_cals": step_cals,
             "gen_s": round(t_gen, 1)}
 
@@ -672,10 +736,8 @@ def main():
     ap.add_argument("--uneven-bands", default="16,32,64", help="bands of the uneven-length leg")
     ap.add_argument("--two-ref-reads", type=int, default=4_000_000,
                     help="reads of the two-reference classification leg (0 skips it)")
-    ap.add_argument("--serve-scale", type=float, default=0.0,
-                    help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0, the default, "
-                         "skips it: the served path is kept off the GPU after runs that included it "
-                         "faulted the GPU)")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=300)
     ap.add_argument("--serve-step-cals", type=int, default=1 << 20, help="CALs per device step of the server")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
@@ -757,28 +819,11 @@ def main():
 
     step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
     gcups = cells / (step_ms * 1e-3) / 1e9
-    achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
-    traffic = load_traffic("inter16_queue", "chromosome_scale")
     import paper_1805_00106_amd as sw
     measured = sw.alu_peak(16) / 1e12  # sustained packed-int16 add/max rate on this device
-    roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_INT16_TOPS, 2),
-            "unit": "Tops/s (int16 lane-ops)", "frac": round(achieved / PEAK_INT16_TOPS, 4), "traffic": traffic,
-            "peak_measured": round(measured, 2), "frac_of_measured": round(achieved / measured, 4),
-            "kernel": "k_inter16_queue", "kernel_ms": round(kern_ms, 3),
-            "kernel_gcups": round(cells / (kern_ms * 1e-3) / 1e9, 1),
-            "gcups_peak": round(PEAK_INT16_TOPS * 1e12 / OPS_PER_CELL / 1e9, 1),
-            "note": "achieved counts 12 algorithmic lane-ops per cell; the kernel issues fewer packed "
-                    "instructions per pair of cells (two cells per lane, issue.insts_per_cell_pair) than the 12 "
-                    "packed ops those cells count, so frac can exceed 1: issue.frac is the share of the VALU "
-                    "issue peak the kernel's instructions fill"}
-    valu = load_issue("inter16_queue", "chromosome_scale")
-    if valu:
-        # packed instructions issued per second over all lanes, against 256 CUs x 64 lanes x 2.4 GHz
-        issued = valu["insts_per_cell_pair"] * (cells / 2) / (kern_ms * 1e-3)
-        peak_issue = 256 * 64 * 2.4e9
-        roof["issue"] = {"insts_per_cell_pair": valu["insts_per_cell_pair"], "achieved": round(issued / 1e12, 2),
-                         "peak": round(peak_issue / 1e12, 2), "unit": "T packed instructions/s",
-                         "frac": round(issued / peak_issue, 4), "valu_busy_profiled": valu["valu_busy"]}
+    roof = roofline("inter16_queue", "chromosome_scale", cells, kern_ms, True)
+    roof["traffic"] = load_traffic("inter16_queue", "chromosome_scale")
+    roof["peak_measured_alu_tops"] = round(measured, 2)
     res = {
         "metric": METRIC, "value": round(gcups, 1), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
@@ -806,9 +851,6 @@ def main():
         res["uneven_lengths"] = c3
     if c4:
         res["two_references"] = c4
-    if not served:
-        res["served"] = {"skipped": "served path kept off the GPU: three runs that included it ended with "
-                                    "the GPU faulted, cause not shown"}
     if served:
         res["served"] = served
         res["p50_ms"] = served["loads"][-1]["p50_ms"]

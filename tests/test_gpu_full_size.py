@@ -101,12 +101,21 @@ def test_chromosome_scale_full_size():
     _sample(b, got)
 
 
-def test_uneven_lengths_full_size_band64():
-    """2 M reads of 75..250 bp, 16.0 M CALs (geometric counts), band 64, int16."""
-    b = wl.uneven_lengths(band=64)
+_UNEVEN = {}
+
+
+@pytest.mark.parametrize("band", [16, 32, 64])
+def test_uneven_lengths_full_size(band):
+    """2 M reads of 75..250 bp, 16.0 M CALs (geometric counts), bands 16, 32 and 64, int16
+    (the reads and CALs do not depend on the band)."""
+    import dataclasses
+    if "base" not in _UNEVEN:
+        _UNEVEN["base"] = wl.uneven_lengths(band=32)
+    base = _UNEVEN["base"]
+    b = dataclasses.replace(base, scoring=dataclasses.replace(base.scoring, band=band))
     got = _run(b, 250, plain=False)
     _properties(b, got)
-    _sample(b, got, n=800)
+    _sample(b, got, n=800, seed=11 + band)
 
 
 def test_two_references_full_size():
