@@ -218,7 +218,9 @@ def small_batch_latency(batch, n_reads=24, reps=20):
     results = {}
     for name, kern, prec in (("inter_int16", sw.KERNEL_INTER, sw.PREC_INT16),
                              ("inter_int32", sw.KERNEL_INTER, sw.PREC_INT32),
-                             ("intra_int32", sw.KERNEL_INTRA, sw.PREC_INT32)):
+                             ("intra_int16", sw.KERNEL_INTRA, sw.PREC_INT16),
+                             ("intra_int32", sw.KERNEL_INTRA, sw.PREC_INT32),
+                             ("auto", sw.KERNEL_AUTO, sw.PREC_AUTO)):
         sc = sw.Scoring.make(2, -3, 5, 2, 32, prec, kern, 100)
         ws = torch.empty(max(1, sw.workspace_bytes(db.n_reads, db.n_cals, sc)), dtype=torch.uint8, device="cuda")
         for _ in range(3):
@@ -428,7 +430,8 @@ class Leg:
         res = {"reads": n, "ms": round(ms, 3), "reads_per_s": round(n / (ms * 1e-3), 1),
                "rectangle_cells": cells, "rectangle_gcups": round(cells / (ms * 1e-3) / 1e9, 1),
                "traced_fraction": round(float((nops > 0).float().mean().item()), 4),
-               "kernel": "one slot per lane" if self.scoring.kernel != sw.KERNEL_INTRA else "one slot per wavefront",
+               "kernel": ("one slot per wavefront" if self.scoring.kernel == sw.KERNEL_INTRA else
+                          "slots per lane (two per lane in int16 halves where that layout holds)"),
                "workspace_mb": round(nb / 2**20, 1)}
         # the other kernel family (one traced slot per wavefront) on the same slots: time and agreement
         sc = self.scoring

@@ -68,10 +68,12 @@ typedef struct ihipStream_t *sw_stream_t; /* a hipStream_t */
 #define SW_PREC_INT32 2
 
 /* kernel family */
-#define SW_KERNEL_AUTO 0  /* one wavefront per task for small int32-capable batches (at most
-                             32 tasks per compute unit), one CAL per lane otherwise */
-#define SW_KERNEL_INTER 1 /* one CAL per lane (both strands in one lane) */
-#define SW_KERNEL_INTRA 2 /* one wavefront per CAL, lanes hold window columns */
+#define SW_KERNEL_AUTO 0  /* one wavefront per task for small batches (at most 64 wavefronts
+                             per compute unit), one CAL per lane otherwise */
+#define SW_KERNEL_INTER 1 /* one CAL per lane (int16: both strands in one lane; int32: one
+                             strand per lane) */
+#define SW_KERNEL_INTRA 2 /* one wavefront per task, lanes hold window columns (int16: one
+                             CAL, both strands in the 16-bit halves; int32: one CAL strand) */
 
 /* which cells may end an alignment */
 #define SW_MODE_LOCAL 0     /* any cell: the full local maximum */

@@ -177,17 +177,17 @@ int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainP
   if (rc) return rc;
   // Kernel family: the intra-task kernel (one wavefront per task, lanes =
   // window columns) has the lowest latency per task and wins while the batch is
-  // too small to give the SIMDs more than one inter-task tile each (measured:
-  // 1000 reads of 76 bp with 2 CALs each, 4000 tasks on 256 CUs, 116 us against
-  // 316 us); it computes in int32.
+  // too small to give the SIMDs more than one inter-task tile each.  Its
+  // wavefronts hold one CAL (both strands) in int16 pairs and one (CAL, strand)
+  // in int32.  Measured on 100-bp reads with 7 CALs each (band 32, 256 CUs), one
+  // wavefront per task is faster up to about 16 K CALs in int16 (13.9 K: 301 us
+  // against 358 us) and about 8 K CALs in int32 (7.0 K: 353 us against 432 us),
+  // so AUTO takes it up to 64 wavefronts per CU.
   const int cus = device_cus();
   bool intra = sc->kernel == SW_KERNEL_INTRA;
-  if (sc->kernel == SW_KERNEL_AUTO) intra = sc->precision != SW_PREC_INT16 && 2 * n_cals <= 32 * (int64_t)cus;
+  const int64_t intra_waves = m.int16 ? n_cals : 2 * n_cals;
+  if (sc->kernel == SW_KERNEL_AUTO) intra = intra_waves <= kIntraWavesPerCu * (int64_t)cus;
   p->intra = intra;
-  if (intra) {
-    if (sc->precision == SW_PREC_INT16) return SW_ERR_INVALID_ARG;  // the intra kernel is int32 only
-    m.int16 = false;
-  }
   p->mode = m;
   p->wwords = (m.wcap + 15) / 16;
   p->rwords = (m.max_read_len + 15) / 16;
@@ -195,9 +195,9 @@ int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainP
   p->scratch_off = align_up((size_t)std::max<int64_t>(n_cals, 1) * sizeof(int32_t), 256);
   if (intra) {
     p->strip_rows = 0;
-    p->n_tasks = 2 * n_cals;
+    p->n_tasks = intra_waves;
     const size_t lds = (size_t)m.max_read_len * 16 + (size_t)p->wwords * 4;
-    int occ = swk::intra_blocks_per_cu(lds);
+    int occ = swk::intra_blocks_per_cu(m.int16, lds);
     if (occ <= 0) occ = 8;
     p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(p->n_tasks, (int64_t)cus * occ));
     p->bytes = p->scratch_off;
@@ -276,7 +276,8 @@ int run_plain(const PlainPlan &plan, const swk::RefTable &T, const uint32_t *rea
   A.band = sc->band;
   A.strip_rows = plan.strip_rows;
   A.k = make_consts(sc);
-  e = plan.intra ? swk::launch_intra(A, T, plan.grid, st) : swk::launch_inter(plan.mode.int16, A, T, plan.grid, st);
+  e = plan.intra ? swk::launch_intra(plan.mode.int16, A, T, plan.grid, st)
+                 : swk::launch_inter(plan.mode.int16, A, T, plan.grid, st);
   if (e != hipSuccess) return hip_fail(e);
   return SW_OK;
 }
@@ -445,13 +446,19 @@ namespace {
 // (64 per wavefront) unless its per-block bit buffer would exceed 4 MiB (very
 // long reads or wide bands) or the caller asks for the wavefront-per-slot kernel.
 constexpr size_t kTraceInterBlockLimit = 4u << 20;
+// Two slots per lane: per-block buffers up to 8 MiB, and the grid trimmed so that
+// all blocks' buffers stay within 4 GiB.
+constexpr size_t kTracePairBlockLimit = 8u << 20;
+constexpr size_t kTracePairWorkspace = (size_t)4 << 30;
 
 struct TraceLaunch {
   bool inter;
+  bool pair;         // two slots per lane in int16 halves (else one per lane, int32)
+  int32_t beta;      // bias of the two-slots-per-lane kernel's values
   swk::TracePlan P;  // wavefront-per-slot kernel
   int grid;
-  size_t block_bytes;     // one-slot-per-lane kernel: bits + boundary rows per block
-  size_t cal_read_bytes;  // one-slot-per-lane kernel: owner read per CAL
+  size_t block_bytes;     // slot-per-lane kernels: bits + boundary rows per block
+  size_t cal_read_bytes;  // slot-per-lane kernels: owner read per CAL
   size_t bytes;           // total workspace
 };
 
@@ -462,7 +469,22 @@ int trace_launch(int64_t n_slots, int64_t n_cals, const sw_scoring_t *sc, TraceL
   int rc = validate_scoring(sc, &m);
   if (rc) return rc;
   const size_t bb = swk::trace_inter_block_bytes(m.max_read_len, m.wcap);
-  t->inter = sc->kernel == SW_KERNEL_INTER || (sc->kernel == SW_KERNEL_AUTO && bb <= kTraceInterBlockLimit);
+  const size_t bp = swk::trace_pair_block_bytes(m.max_read_len, m.wcap);
+  t->beta = 0;
+  const bool pair_fits = swk::trace_pair_fits(sc->match, sc->mismatch, sc->gap_open + sc->gap_extend, sc->gap_extend,
+                                              m.max_read_len, m.wcap, &t->beta) != 0;
+  t->pair = pair_fits && (sc->kernel == SW_KERNEL_INTER || (sc->kernel == SW_KERNEL_AUTO && bp <= kTracePairBlockLimit));
+  t->inter = t->pair || sc->kernel == SW_KERNEL_INTER || (sc->kernel == SW_KERNEL_AUTO && bb <= kTraceInterBlockLimit);
+  if (t->pair) {
+    const int64_t tiles = (n_slots + 127) / 128;
+    const int64_t resident = (int64_t)device_cus() * swk::trace_pair_blocks_per_cu();
+    const int64_t budget = std::max<int64_t>(device_cus(), (int64_t)(kTracePairWorkspace / align256(bp)));
+    t->grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(tiles, resident), budget));
+    t->block_bytes = align256(bp);
+    t->cal_read_bytes = align256(sizeof(int32_t) * (size_t)std::max<int64_t>(n_cals, 1));
+    t->bytes = t->cal_read_bytes + (size_t)t->grid * t->block_bytes;
+    return SW_OK;
+  }
   if (t->inter) {
     const int64_t tiles = (n_slots + 63) / 64;
     const int64_t resident = (int64_t)device_cus() * swk::trace_inter_blocks_per_cu();
@@ -554,15 +576,20 @@ int sw_traceback(const uint32_t *reads2bit, const int64_t *read_word_off, const 
     I.cal_read = cal_read;
     I.bits = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + tl.cal_read_bytes);
     // per block, one block_bytes slice: [bits | boundary rows]
-    const size_t bits_bytes = swk::trace_inter_block_bytes(m.max_read_len, m.wcap) - (size_t)m.wcap * 64 * 8;
+    const size_t bits_bytes = (tl.pair ? swk::trace_pair_block_bytes(m.max_read_len, m.wcap)
+                                       : swk::trace_inter_block_bytes(m.max_read_len, m.wcap)) -
+                              (size_t)m.wcap * 64 * 8;
     I.bits_stride = (int64_t)(tl.block_bytes / 4);
     I.bscr = reinterpret_cast<uint2 *>(static_cast<char *>(workspace) + tl.cal_read_bytes + bits_bytes);
     I.bscr_stride = (int64_t)(tl.block_bytes / 8);
     I.wcap = m.wcap;
     I.rwords = (m.max_read_len + 15) / 16;
     I.wwords = (m.wcap + 15) / 16;
+    I.beta = tl.beta;
     e = swk::launch_expand(cal_ptr, n_reads, n_cals, cal_read, (hipStream_t)stream);
-    if (e == hipSuccess) e = swk::launch_trace_inter(I, T, tl.grid, (hipStream_t)stream);
+    if (e == hipSuccess)
+      e = tl.pair ? swk::launch_trace_pair(I, T, tl.grid, (hipStream_t)stream)
+                  : swk::launch_trace_inter(I, T, tl.grid, (hipStream_t)stream);
   } else {
     e = swk::launch_trace(A, T, tl.P, tl.grid, (hipStream_t)stream);
   }

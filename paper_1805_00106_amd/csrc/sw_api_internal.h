@@ -45,5 +45,8 @@ int strip_rows_supported(bool int16, int R);
 int device_cus();
 int blocks_per_cu(bool int16, int R);
 int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainPlan *p);
+// AUTO kernel choice: one wavefront per task while the call needs at most this
+// many wavefronts per compute unit (one per CAL in int16 pairs, two in int32)
+constexpr int kIntraWavesPerCu = 64;
 
 }  // namespace swapi

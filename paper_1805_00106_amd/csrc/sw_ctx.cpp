@@ -17,9 +17,14 @@
 
 namespace {
 
+// One batched plan: how tasks are binned and ordered, which strip height each
+// bin takes, and how many persistent blocks pop the queue.
 struct TunedPlan {
   int bin_width = 4;
   int descending = 1;
+  int strip_cap = 0;      // tallest strip height a bin may take (0: any)
+  int strip_slack = 0;    // padding rows accepted to save one strip hand-over
+  int grid_quarters = 4;  // persistent blocks, in quarters of the resident capacity
   float ms = 0.f;
 };
 
@@ -74,11 +79,16 @@ void load_tune_cache(sw_ctx *c) {
   if (!f) return;
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
-    // one entry per line: "key": {"bin_width": N, "descending": N, "ms": X}
+    // one entry per line: "key": {"bin_width": N, "descending": N, "strip_cap": N,
+    // "strip_slack": N, "grid_quarters": N, "ms": X}
     char key[256];
     TunedPlan p;
-    if (std::sscanf(line, " \"%255[^\"]\": {\"bin_width\": %d, \"descending\": %d, \"ms\": %f", key, &p.bin_width,
-                    &p.descending, &p.ms) == 4)
+    if (std::sscanf(line,
+                    " \"%255[^\"]\": {\"bin_width\": %d, \"descending\": %d, \"strip_cap\": %d, "
+                    "\"strip_slack\": %d, \"grid_quarters\": %d, \"ms\": %f",
+                    key, &p.bin_width, &p.descending, &p.strip_cap, &p.strip_slack, &p.grid_quarters, &p.ms) == 7 &&
+        p.bin_width >= 1 && p.bin_width <= SW_MAX_READ_LEN && p.grid_quarters >= 1 && p.grid_quarters <= 4 &&
+        p.strip_cap >= 0 && p.strip_slack >= 0)
       c->tuned[key] = p;
   }
   std::fclose(f);
@@ -91,8 +101,12 @@ void save_tune_cache(const sw_ctx *c) {
   std::fprintf(f, "{\n");
   size_t i = 0;
   for (const auto &kv : c->tuned) {
-    std::fprintf(f, "  \"%s\": {\"bin_width\": %d, \"descending\": %d, \"ms\": %.4f}%s\n", kv.first.c_str(),
-                 kv.second.bin_width, kv.second.descending, kv.second.ms, ++i < c->tuned.size() ? "," : "");
+    const TunedPlan &t = kv.second;
+    std::fprintf(f,
+                 "  \"%s\": {\"bin_width\": %d, \"descending\": %d, \"strip_cap\": %d, \"strip_slack\": %d, "
+                 "\"grid_quarters\": %d, \"ms\": %.4f}%s\n",
+                 kv.first.c_str(), t.bin_width, t.descending, t.strip_cap, t.strip_slack, t.grid_quarters, t.ms,
+                 ++i < c->tuned.size() ? "," : "");
   }
   std::fprintf(f, "}\n");
   std::fclose(f);
@@ -125,7 +139,26 @@ swk::BinParams bin_params(const swapi::ScoreMode &m, const TunedPlan &t) {
   const int n = m.int16 ? (int)(sizeof(kQueueStrips16) / sizeof(int)) : (int)(sizeof(kQueueStrips32) / sizeof(int));
   P.n_strips = 0;
   for (int i = 0; i < n; ++i) P.strips[P.n_strips++] = s[i];
+  P.strip_cap = t.strip_cap;
+  P.strip_slack = t.strip_slack;
   return P;
+}
+
+// The strip height of every length bin under plan t, as "lo-hi:R" runs.
+std::string plan_heights(const swk::BinParams &P) {
+  std::string out;
+  int run_lo = 1, run_r = -1;
+  for (int b = 0; b < P.nb; ++b) {
+    const int lo = b * P.bin_width + 1, hi = std::min((b + 1) * P.bin_width, P.max_read_len);
+    const int R = swk::bin_strip_height(P, hi);
+    if (R != run_r) {
+      if (run_r > 0) out += std::to_string(run_lo) + "-" + std::to_string(lo - 1) + ":" + std::to_string(run_r) + " ";
+      run_lo = lo;
+      run_r = R;
+    }
+  }
+  if (run_r > 0) out += std::to_string(run_lo) + "-" + std::to_string(P.max_read_len) + ":" + std::to_string(run_r);
+  return out;
 }
 
 int queue_grid(bool int16, int64_t n_tasks) {
@@ -190,13 +223,13 @@ int enqueue(sw_ctx *c, const CallArgs &a, const swapi::ScoreMode &m, const swk::
 
 std::string graph_key(const CallArgs &a, const swapi::ScoreMode &m, const TunedPlan &t, int grid) {
   char k[1024];
-  std::snprintf(k, sizeof k, "%p %p %p %d %p %d %p %p %p %p %p %lld %d %d %d %d %d %d %p %p %p %d %d %d %d %d",
+  std::snprintf(k, sizeof k, "%p %p %p %d %p %d %p %p %p %p %p %lld %d %d %d %d %d %d %p %p %p %d %d %d %d %d %d %d",
                 (const void *)a.reads2bit, (const void *)a.read_word_off, (const void *)a.read_len, a.n_reads,
                 (const void *)a.refs->words, a.refs->n_refs, (const void *)a.cal_ptr, (const void *)a.cal_pos,
                 (const void *)a.cal_ref, (const void *)a.strand, (const void *)a.score, (long long)a.n_cals,
                 a.sc->match, a.sc->mismatch, a.sc->gap_open, a.sc->gap_extend, a.sc->band, m.max_read_len,
                 (const void *)a.ref_end, (const void *)a.read_end, (const void *)nullptr, (int)m.int16, t.bin_width,
-                t.descending, grid, a.sc->mode);
+                t.descending, grid, a.sc->mode, t.strip_cap, t.strip_slack);
   std::string s(k);
   for (int i = 0; i < a.refs->n_refs; ++i) {
     char r[64];
@@ -326,7 +359,8 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return swapi::hip_fail(e);
   const int64_t n_tasks = m.int16 ? n_cals : 2 * n_cals;
-  const int grid = queue_grid(m.int16, n_tasks);
+  const int full_grid = queue_grid(m.int16, n_tasks);
+  auto grid_of = [&](const TunedPlan &t) { return std::max(1, full_grid * t.grid_quarters / 4); };
   // scratch for the full resident grid, so that shapes with fewer tiles reuse it
   // (and the graphs captured with it) instead of reallocating
   const size_t need = (size_t)queue_grid(m.int16, INT64_MAX / 4) * (size_t)m.wcap * 64 * sizeof(uint2);
@@ -347,33 +381,55 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
              n_cals, sc, score, ref_end, read_end};
   hipStream_t user = (hipStream_t)stream;
 
-  // plan: tuned on first use of this shape class
+  // plan: tuned on first use of this shape class, by coordinate search over the
+  // bin width and order, then the strip-height policy, then the grid; each
+  // candidate runs the whole pipeline once on the caller's inputs (every plan
+  // gives the same outputs)
   const std::string tk = tune_key(m, sc, n_tasks);
   auto it = c->tuned.find(tk);
   bool tuned_now = false;
+  int n_tried = 0;
   if (it == c->tuned.end()) {
     TunedPlan best;
     if (c->autotune) {
-      const int widths[] = {1, 4, 16};
       float best_ms = 1e30f;
-      for (int w : widths) {
+      auto time_plan = [&](const TunedPlan &cand) -> int {
+        hipError_t he;
+        if ((he = hipEventRecord(c->ev_t0, user)) != hipSuccess) return swapi::hip_fail(he);
+        int r = enqueue(c, a, m, T, cand, grid_of(cand), user);
+        if (r) return r;
+        if ((he = hipEventRecord(c->ev_t1, user)) != hipSuccess) return swapi::hip_fail(he);
+        if ((he = hipEventSynchronize(c->ev_t1)) != hipSuccess) return swapi::hip_fail(he);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1);
+        ++n_tried;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cand;
+          best.ms = ms;
+        }
+        return SW_OK;
+      };
+      for (int w : {1, 2, 4, 8, 16})
         for (int d = 1; d >= 0; --d) {
           TunedPlan cand;
           cand.bin_width = w;
           cand.descending = d;
-          if ((e = hipEventRecord(c->ev_t0, user)) != hipSuccess) return swapi::hip_fail(e);
-          rc = enqueue(c, a, m, T, cand, grid, user);
-          if (rc) return rc;
-          if ((e = hipEventRecord(c->ev_t1, user)) != hipSuccess) return swapi::hip_fail(e);
-          if ((e = hipEventSynchronize(c->ev_t1)) != hipSuccess) return swapi::hip_fail(e);
-          float ms = 0.f;
-          hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1);
-          if (ms < best_ms) {
-            best_ms = ms;
-            best = cand;
-            best.ms = ms;
-          }
+          if ((rc = time_plan(cand))) return rc;
         }
+      const TunedPlan base = best;
+      const int strip_policies[][2] = {{0, 8}, {0, 16}, {0, 32}, {40, 0}, {44, 0}};
+      for (const auto &sp : strip_policies) {
+        TunedPlan cand = base;
+        cand.strip_cap = sp[0];
+        cand.strip_slack = sp[1];
+        if ((rc = time_plan(cand))) return rc;
+      }
+      const TunedPlan base2 = best;
+      for (int q : {3, 2}) {
+        TunedPlan cand = base2;
+        cand.grid_quarters = q;
+        if ((rc = time_plan(cand))) return rc;
       }
       tuned_now = true;
     }
@@ -381,6 +437,7 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
     if (tuned_now) save_tune_cache(c);
   }
   const TunedPlan plan = it->second;
+  const int grid = grid_of(plan);
 
   bool graph_hit = false;
   if (c->use_graph) {
@@ -428,13 +485,16 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
     rc = enqueue(c, a, m, T, plan, grid, user);
     if (rc) return rc;
   }
-  char desc[256];
+  char desc[320];
   std::snprintf(desc, sizeof desc,
-                "%s tasks=%lld bins=%d(width %d, %s) grid=%d graph=%s tuned=%s(%.3f ms)",
+                "%s tasks=%lld bins=%d(width %d, %s) strips(cap %d, slack %d) grid=%d(%d/4) graph=%s tuned=%s(%.3f ms",
                 m.int16 ? "int16-pairs" : "int32", (long long)n_tasks, (m.max_read_len + plan.bin_width - 1) / plan.bin_width,
-                plan.bin_width, plan.descending ? "longest first" : "shortest first", grid,
-                c->use_graph ? (graph_hit ? "replay" : "captured") : "off", tuned_now ? "now" : "cached", plan.ms);
+                plan.bin_width, plan.descending ? "longest first" : "shortest first", plan.strip_cap, plan.strip_slack,
+                grid, plan.grid_quarters, c->use_graph ? (graph_hit ? "replay" : "captured") : "off",
+                tuned_now ? "now" : "cached", plan.ms);
   c->last_plan = desc;
+  if (tuned_now) c->last_plan += ", " + std::to_string(n_tried) + " plans";
+  c->last_plan += ") heights " + plan_heights(bin_params(m, plan));
   return SW_OK;
 }
 

@@ -835,6 +835,153 @@ __global__ __launch_bounds__(64) void k_intra32(const AlignArgs A, const RefTabl
   }
 }
 
+// --------------------------------------------------------------------------- intra-task kernel, int16 pairs
+//
+// One wavefront per CAL with both strands in the 16-bit halves of every
+// register (low: forward, high: reverse complement of the read), swept along
+// anti-diagonals as in k_intra32: lane j holds window column 64*s + j of strip
+// s and computes row i = t - j at step t; the selector of row i's read base, E
+// and H move one lane per step through wave_shr:1.
+//
+// Values carry a bias beta (>= |mismatch|, gap_open + gap_extend, gap_extend) so
+// that every operand of the three-way maxima is a non-negative int16 below
+// 0x7C00, where the packed half-precision maximum orders as the integer one:
+// H = max(diagonal, E, F) and the clamped gap terms max(E - ge, H - go - ge, 0)
+// and max(F - ge, H - go - ge, 0) are one v_pk_maximum3_f16 each (clamping E
+// and F at zero leaves H unchanged, and the clamped terms follow the same
+// recurrence).  The zero of H is the bias itself.
+//
+// No position tags ride on the values: each lane keeps, per half, a running
+// 32-bit maximum of (H << 16 | 0xFFFF - t).  A lane meets its column's rows in
+// increasing order, so among equal values the largest key is the earliest step,
+// i.e. the smallest row.
+//
+// The substitution comes from one v_perm_b32 per cell: the lane's column base
+// fixes a table of the score's low and high bytes per read base, and each row's
+// selector word holds (q_fwd, q_fwd + 4, q_rev, q_rev + 4).
+
+template <bool FR>
+__global__ __launch_bounds__(64) void k_intra16(const AlignArgs A, const RefTable T) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const int lane = threadIdx.x;
+  load_ref_table(T, A.n_refs, rt_off, rt_len, lane);
+  uint4 *rows = reinterpret_cast<uint4 *>(smem);  // [max_read_len]: selector, E and H of lane 63
+  uint32_t *win = smem + 4 * A.max_read_len;       // [wwords]
+  const DpConst &K = A.k;
+  const uint32_t beta = (uint32_t)K.beta16 * 0x00010001u;
+  const uint32_t goe2 = (uint32_t)K.goe * 0x00010001u, ge2 = (uint32_t)K.ge * 0x00010001u;
+  const uint32_t xlo = (uint32_t)K.mismatch & 0xFFu, mlo = (uint32_t)K.match & 0xFFu;
+  const uint32_t xhi = ((uint32_t)K.mismatch >> 8) & 0xFFu, mhi = ((uint32_t)K.match >> 8) & 0xFFu;
+
+  for (int64_t c = blockIdx.x; c < A.n_cals; c += gridDim.x) {
+    LaneTask t{};
+    if (lane == 0) t = load_task(A, rt_len, c, 3);
+    const int L = __shfl(t.L, 0, 64);
+    if (L == 0) continue;
+    const int W = __shfl(t.W, 0, 64);
+    const int k = __shfl(t.k, 0, 64);
+    const int r = __shfl(t.r, 0, 64);
+    const int mask = __shfl(t.mask, 0, 64);
+    const int64_t ws = shfl_i64([](int v, int src) { return __shfl(v, src, 64); }, t.ws, 0);
+    __syncthreads();
+    // stage the selectors of the oriented read rows and the window words
+    const uint32_t *rp = A.reads + A.read_word_off[r];
+    for (int i = lane; i < L; i += 64) {
+      const uint32_t bf = (rp[i >> 4] >> (2 * (i & 15))) & 3u;
+      const int ir = L - 1 - i;
+      const uint32_t br = 3u - ((rp[ir >> 4] >> (2 * (ir & 15))) & 3u);
+      // the first strip's left boundary: E(i, 0) and H(i, -1) are zero
+      rows[i] = make_uint4(bf | ((bf + 4u) << 8) | (br << 16) | ((br + 4u) << 24), beta, beta, 0u);
+    }
+    const int64_t first = rt_off[k] + (ws >> 4);
+    const int64_t last = rt_off[k] + ((rt_len[k] - 1) >> 4);
+    const uint32_t sh = 2u * (uint32_t)(ws & 15);
+    const int nww = (W + 15) >> 4;
+    for (int q = lane; q < nww; q += 64) {
+      const uint32_t lo = A.ref_words[first + q];
+      const uint32_t hi = (first + q + 1 <= last) ? A.ref_words[first + q + 1] : 0u;
+      win[q] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+    }
+    __syncthreads();
+
+    uint64_t best_f = 0, best_r = 0;
+    const int nstrips = (W + 63) >> 6;
+    for (int s = 0; s < nstrips; ++s) {
+      const int col = 64 * s + lane;
+      // the lane's substitution table: every read base against its column's base
+      // (columns past the window score mismatches; nothing reported comes from them)
+      uint32_t tlo = xlo * 0x01010101u, thi = xhi * 0x01010101u;
+      if (col < W) {
+        const uint32_t w = (win[col >> 4] >> (2 * (col & 15))) & 3u;
+        tlo ^= (xlo ^ mlo) << (8 * w);
+        thi ^= (xhi ^ mhi) << (8 * w);
+      }
+      const int width = min(64, W - 64 * s);
+      const int nsteps = L + width - 1;
+      uint32_t H = beta, Hd1 = beta, F = beta, Eout = beta, q = 0;
+      uint32_t M_f = 0, M_r = 0;
+      // lane 0's left boundary for row st (its selector, E(st, 64s) and H(st, 64s - 1)),
+      // read one step ahead; past the last row the entry of row L - 1 stands in (lane 0
+      // and every lane it feeds are past the read's end there, so it is never used)
+      uint4 nb = rows[0];
+      for (int st = 0; st < nsteps; ++st) {
+        const uint4 rb = nb;
+        nb = rows[min(st + 1, L - 1)];
+        q = (uint32_t)shr1((int32_t)rb.x, (int32_t)q);
+        const uint32_t Ein = (uint32_t)shr1((int32_t)rb.y, (int32_t)Eout);
+        const uint32_t Hs = (uint32_t)shr1((int32_t)rb.z, (int32_t)H);
+        const int i = st - lane;
+        if (i >= 0 && i < L) {
+          const uint32_t sub = __builtin_amdgcn_perm(thi, tlo, q);
+          const uint32_t diag = bits(pair(Hd1) + pair(sub));
+          const uint32_t Hn = half_max3(diag, Ein, F);
+          if (!FR || i == L - 1) {
+            const uint32_t tag = 0xFFFFu - (uint32_t)st;
+            M_f = max(M_f, (Hn << 16) | tag);
+            M_r = max(M_r, (Hn & 0xFFFF0000u) | tag);
+          }
+          const uint32_t U = bits(pair(Hn) - pair(goe2));
+          Eout = half_max3(bits(pair(Ein) - pair(ge2)), U, beta);
+          F = half_max3(bits(pair(F) - pair(ge2)), U, beta);
+          H = Hn;
+          if (lane == 63) {
+            rows[i].y = Eout;
+            rows[i].z = Hn;
+          }
+        }
+        Hd1 = Hs;
+      }
+      if (col < W) {
+        const int32_t vf = (int32_t)(M_f >> 16) - K.beta16, vr = (int32_t)(M_r >> 16) - K.beta16;
+        if (vf > 0) {
+          const uint64_t kk = cell_key(vf, col, (int32_t)(0xFFFFu - (M_f & 0xFFFFu)) - lane);
+          best_f = kk > best_f ? kk : best_f;
+        }
+        if (vr > 0) {
+          const uint64_t kk = cell_key(vr, col, (int32_t)(0xFFFFu - (M_r & 0xFFFFu)) - lane);
+          best_r = kk > best_r ? kk : best_r;
+        }
+      }
+      __syncthreads();
+    }
+    // wave maxima of the 64-bit keys
+    for (int m = 32; m; m >>= 1) {
+      const uint64_t of = ((uint64_t)(uint32_t)__shfl_xor((int)(best_f >> 32), m, 64) << 32) |
+                          (uint32_t)__shfl_xor((int)(best_f & 0xffffffffu), m, 64);
+      const uint64_t orr = ((uint64_t)(uint32_t)__shfl_xor((int)(best_r >> 32), m, 64) << 32) |
+                           (uint32_t)__shfl_xor((int)(best_r & 0xffffffffu), m, 64);
+      best_f = of > best_f ? of : best_f;
+      best_r = orr > best_r ? orr : best_r;
+    }
+    if (lane == 0) {
+      if (mask & 1) write_result(A, 2 * c, best_f, ws);
+      if (mask & 2) write_result(A, 2 * c + 1, best_r, ws);
+    }
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------------------------- batched planning
 //
 // Tasks are binned by read length so that the lanes of a tile share their
@@ -882,20 +1029,7 @@ __global__ void k_bin_plan(const int32_t *__restrict__ bin_count, int32_t *__res
     const int32_t cnt = bin_count[b];
     pos += cnt;
     tiles += (cnt + 63) / 64;
-    int best = P.strips[0];
-    if (b < P.nb) {
-      const int Lb = min((b + 1) * P.bin_width, P.max_read_len);
-      int best_cost = 0x7fffffff;
-      for (int j = 0; j < P.n_strips; ++j) {
-        const int R = P.strips[j];
-        const int cost = (Lb + R - 1) / R * R;
-        if (cost < best_cost || (cost == best_cost && R > best)) {
-          best_cost = cost;
-          best = R;
-        }
-      }
-    }
-    strip_of_bin[b] = best;
+    strip_of_bin[b] = b < P.nb ? bin_strip_height(P, min((b + 1) * P.bin_width, P.max_read_len)) : P.strips[0];
   }
   tile_off[P.nb + 1] = tiles;
   *n_tiles = tiles;
@@ -1054,17 +1188,21 @@ int queue_blocks_per_cu(bool int16) {
   return n;
 }
 
-hipError_t launch_intra(const AlignArgs &A, const RefTable &T, int grid, hipStream_t st) {
+hipError_t launch_intra(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st) {
   const size_t lds = (size_t)A.max_read_len * sizeof(int4) + (size_t)A.wwords * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_intra32, dim3(grid), dim3(64), lds, st, A, T);
+  if (!int16)
+    hipLaunchKernelGGL(k_intra32, dim3(grid), dim3(64), lds, st, A, T);
+  else if (A.k.final_row)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_intra16<true>), dim3(grid), dim3(64), lds, st, A, T);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_intra16<false>), dim3(grid), dim3(64), lds, st, A, T);
   return hipGetLastError();
 }
 
-int intra_blocks_per_cu(size_t lds) {
+int intra_blocks_per_cu(bool int16, size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_intra32), 64, lds) !=
-      hipSuccess)
-    return 0;
+  const void *f = int16 ? reinterpret_cast<const void *>(&k_intra16<false>) : reinterpret_cast<const void *>(&k_intra32);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, lds) != hipSuccess) return 0;
   return n;
 }
 

@@ -24,7 +24,28 @@ struct BinParams {
   int32_t descending;    // 1: longest bin first
   int32_t n_strips;      // compiled strip heights available
   int32_t strips[16];    // ascending
+  int32_t strip_cap;     // tallest strip height a bin may take (0: any)
+  int32_t strip_slack;   // padding rows worth one strip hand-over in the choice (0: padding only)
 };
+
+// Strip height of a length bin whose reads are at most `Lb` bases: among the
+// compiled heights up to strip_cap (the lowest is always allowed), the one with
+// the fewest padded rows plus strip_slack per strip, the taller on ties.  The
+// planning kernel and the host's plan description both call it.
+__host__ __device__ inline int bin_strip_height(const BinParams &P, int Lb) {
+  int best = P.strips[0], best_cost = 0x7fffffff;
+  for (int j = 0; j < P.n_strips; ++j) {
+    const int R = P.strips[j];
+    if (j > 0 && P.strip_cap > 0 && R > P.strip_cap) continue;
+    const int ns = (Lb + R - 1) / R;
+    const int cost = ns * R + P.strip_slack * ns;
+    if (cost < best_cost || (cost == best_cost && R > best)) {
+      best_cost = cost;
+      best = R;
+    }
+  }
+  return best;
+}
 
 // Device buffers of the batched path (owned by a context).
 struct BatchBufs {
@@ -55,8 +76,10 @@ hipError_t launch_batch_plan(const BatchBufs &B, const int32_t *read_len, int32_
                              const BinParams &P, hipStream_t st);
 hipError_t launch_inter_queue(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
 int queue_blocks_per_cu(bool int16);
-hipError_t launch_intra(const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
-int intra_blocks_per_cu(size_t lds);
+// One wavefront per task: int32 (one strand per wavefront) or int16 pairs (one
+// CAL per wavefront, both strands in the 16-bit halves).
+hipError_t launch_intra(bool int16, const AlignArgs &A, const RefTable &T, int grid, hipStream_t st);
+int intra_blocks_per_cu(bool int16, size_t lds);
 // Traceback: LDS layout and plane storage of one launch.
 constexpr size_t kTraceLdsLimit = 64 * 1024;  // plane buffers move to device memory above this
 struct TracePlan {

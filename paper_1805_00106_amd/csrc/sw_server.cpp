@@ -523,11 +523,12 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
   s->mode = m;
   s->sc_small = opts->scoring;
   s->sc_small.kernel = SW_KERNEL_AUTO;
-  // the AUTO rule picks one wavefront per task up to 32 tasks (16 CALs) per CU
-  // when int32 is allowed; otherwise small steps stay on the batched path
-  s->small_step_cals = (opts->scoring.precision == SW_PREC_INT16 || opts->scoring.kernel != SW_KERNEL_AUTO)
+  // steps small enough for the AUTO rule's one-wavefront-per-task kernel (one
+  // wavefront per CAL in int16 pairs, two in int32) take the plain call; with a
+  // fixed kernel family every step stays on the batched path
+  s->small_step_cals = opts->scoring.kernel != SW_KERNEL_AUTO
                            ? 0
-                           : 16 * (int64_t)swapi::device_cus();
+                           : (int64_t)swapi::kIntraWavesPerCu * swapi::device_cus() / (m.int16 ? 1 : 2);
   s->arena.reset(new Arena(opts->memory_budget));
   // coherent: blocks are rewritten by the host for each new request, and the
   // device must never see a previous request's bytes through its caches

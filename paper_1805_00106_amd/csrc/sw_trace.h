@@ -21,11 +21,19 @@ struct TraceInterArgs {
   int64_t bscr_stride;       // entries per block
   int32_t wcap;              // widest window (columns)
   int32_t rwords, wwords;    // LDS words per lane for the read and the window
+  int32_t beta;              // two-slots-per-lane kernel: bias of its int16 values
 };
 
 // Per-block device bytes of the one-slot-per-lane traceback for these shapes.
 size_t trace_inter_block_bytes(int max_read_len, int wcap);
 int trace_inter_blocks_per_cu();
 hipError_t launch_trace_inter(const TraceInterArgs &A, const RefTable &T, int grid, hipStream_t st);
+
+// Two traced slots per lane in int16 halves (128 slots per wavefront), when the
+// layout holds the scoring's values (trace_pair_fits, which sets beta).
+size_t trace_pair_block_bytes(int max_read_len, int wcap);
+int trace_pair_blocks_per_cu();
+int trace_pair_fits(int match, int mismatch, int goe, int ge, int max_read_len, int wcap, int32_t *beta);
+hipError_t launch_trace_pair(const TraceInterArgs &A, const RefTable &T, int grid, hipStream_t st);
 
 }  // namespace swk

@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include "sw_device.h"
+#include "sw_halfmax.h"
 #include "sw_launch.h"
 
 namespace swk {
@@ -620,6 +621,376 @@ __global__ __launch_bounds__(64) void k_trace_inter(const TraceInterArgs I, cons
       }
     }
   }
+}
+
+// --------------------------------------------------------------------------- two slots per lane
+//
+// Two traced slots per lane in the 16-bit halves of every register (low half:
+// slot first + lane, high half: slot first + 64 + lane), the rows of a strip
+// in registers and the window columns swept left to right as in
+// k_trace_inter.  Every value V of window column j is held as
+// 16 * (V + beta + j * c) + tag, with c = -mismatch and beta at least
+// |mismatch|, gap_open + gap_extend and gap_extend:
+//   * with the column offset c every substitution plus c is non-negative, so a
+//     per-column byte table of 16 * (s + c) + 8 per read base gives both halves'
+//     diagonal terms with one v_perm_b32 (the high bytes select 0x00);
+//   * every move that consumes a window base (diagonal, gap along the read's
+//     row) adds c, a move down the column adds none, so every term reaching
+//     cell (i, j) carries j * c and the zero of column j is 16 * (beta + j * c);
+//   * beta keeps every operand of the three-way maxima non-negative and below
+//     0x7C00, where the packed half-precision maximum orders exactly as the
+//     integer one, so H = max(diagonal, E, F) and the clamped gap terms
+//     max(E - ge, H - go - ge, 0) and max(F - ge, H - go - ge, 0) are one
+//     v_pk_maximum3_f16 each (clamping E and F at zero leaves H unchanged).
+// The 4 tag bits are the cell's choices.  Bits 3:2 name the source of H: 3 zero,
+// 2 diagonal, 1 gap consuming a read base (F), 0 gap consuming a window base
+// (E); on equal values the maximum takes the higher tag, which is the walk's
+// order, with H = 0 ahead of all.  Bit 1 says F(i, j) was opened from H(i-1, j)
+// and bit 0 that E(i, j) was opened from H(i, j-1) (an opening term carries the
+// bit, an extension clears it, so opening wins on equal values).  A cell's
+// 4-bit code is then the tag bits of H, F and E gathered with two and-or
+// operations.  Codes of a column: 4 rows x 2 halves per 32-bit word, stored
+// coalesced as [strip][column][group][lane]; each lane then walks both of its
+// slots back through its words.
+
+namespace {
+
+struct PairTask {
+  int live, L, h, k, ie, je, sc;
+  int64_t r, ws;
+};
+
+// The lane's task for traced slot t; untraced and invalid slots are written out
+// here (score <= 0: -1 and no operations; invalid: -2) and stay idle.
+__device__ __forceinline__ PairTask pair_task(const TraceInterArgs &I, const int64_t *rt_len, int64_t t) {
+  const TraceArgs &A = I.a;
+  PairTask p{};
+  p.ie = p.je = -1;
+  p.r = -1;
+  if (t >= A.n_slots) return p;
+  int status = 0;
+  const int64_t slot = A.slots[t];
+  if (slot != -1) {
+    if (slot < 0 || slot >= 2 * A.n_cals) {
+      status = -2;
+    } else if ((p.sc = A.score[slot]) > 0) {
+      const int64_t c = slot >> 1;
+      p.h = (int)(slot & 1);
+      p.r = I.cal_read[c];
+      const int64_t pos = A.cal_pos[c];
+      p.k = A.cal_ref[c];
+      p.L = p.r >= 0 && p.r < A.n_reads ? A.read_len[p.r] : 0;
+      if (p.r < 0 || p.L < 1 || p.L > A.max_read_len || p.k < 0 || p.k >= A.n_refs || pos < 0 || pos >= rt_len[p.k]) {
+        status = -2;
+      } else {
+        p.ws = pos - A.band < 0 ? 0 : pos - A.band;
+        const int64_t we = min(rt_len[p.k], pos + p.L + A.band);
+        p.ie = A.read_end[slot];
+        const int64_t je64 = A.ref_end[slot] - p.ws;
+        if (p.ie < 0 || p.ie >= p.L || je64 < 0 || je64 >= we - p.ws) {
+          status = -2;
+        } else {
+          p.je = (int)je64;
+          p.live = 1;
+        }
+      }
+    }
+  }
+  if (!p.live) {
+    A.ref_start[t] = -1;
+    A.read_start[t] = -1;
+    A.n_ops[t] = status;
+    if (status) atomicAdd(A.err, 1ull);
+  }
+  return p;
+}
+
+typedef unsigned short v2u16 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(v2u16, a) + __builtin_bit_cast(v2u16, b));
+}
+
+}  // namespace
+
+template <int R>
+__global__ __launch_bounds__(64) void k_trace_pair(const TraceInterArgs I, const RefTable T) {
+  constexpr int G = R / 4;  // code words per column per lane (4 rows x 2 halves each)
+  extern __shared__ uint32_t tpsm[];
+  __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
+  const TraceArgs &A = I.a;
+  const int lane = threadIdx.x;
+  for (int i = 0; i < A.n_refs; ++i)
+    if (lane == i) {
+      rt_off[i] = T.word_off[i];
+      rt_len[i] = T.len[i];
+    }
+  __syncthreads();
+  // LDS: read words of both halves, then window words of both halves, [word][lane]
+  uint32_t *rdw0 = tpsm, *rdw1 = tpsm + I.rwords * 64;
+  uint32_t *win0 = tpsm + 2 * I.rwords * 64, *win1 = win0 + I.wwords * 64;
+  uint32_t *bits = I.bits + (size_t)blockIdx.x * I.bits_stride;
+  uint2 *bscr = I.bscr + (size_t)blockIdx.x * I.bscr_stride;
+  const int32_t c0 = -A.mismatch, beta = I.beta;
+  const uint32_t P1 = 0x00010001u;
+  const uint32_t sx = 8u, sm = (uint32_t)(16 * (A.match + c0) + 8);
+  const uint32_t kue = (uint32_t)(uint16_t)(16 * (c0 - A.goe) + 1) * P1;  // E opened from H: tag bit 0
+  const uint32_t kuf = (uint32_t)(uint16_t)(6 - 16 * A.goe) * P1;         // F opened from H: tags 01 and bit 1
+  const uint32_t kee = (uint32_t)(uint16_t)(16 * (c0 - A.ge)) * P1;       // E extended
+  const uint32_t kfe = (uint32_t)(uint16_t)(-16 * A.ge) * P1;             // F extended (bit 1 cleared first)
+  const uint32_t zc = (uint32_t)(16 * c0) * P1;                           // zero: +16c per column
+  const uint32_t z0 = (uint32_t)(16 * beta + 12) * P1;                    // zero of column 0, tag 3
+  const uint32_t hleft = (uint32_t)(16 * (beta - c0)) * P1;               // H(i, -1) = 0, clean
+
+  for (int64_t first = (int64_t)blockIdx.x * 128; first < A.n_slots; first += (int64_t)gridDim.x * 128) {
+    const PairTask ta = pair_task(I, rt_len, first + lane), tb = pair_task(I, rt_len, first + 64 + lane);
+    const int n_rows = max(ta.live ? ta.ie + 1 : 0, tb.live ? tb.ie + 1 : 0);
+    const int n_cols = max(ta.live ? ta.je + 1 : 0, tb.live ? tb.je + 1 : 0);
+    int rmax = n_rows, cmax = n_cols, lmax = max(ta.live ? ta.L : 0, tb.live ? tb.L : 0);
+    for (int m = 32; m; m >>= 1) {
+      rmax = max(rmax, __shfl_xor(rmax, m, 64));
+      cmax = max(cmax, __shfl_xor(cmax, m, 64));
+      lmax = max(lmax, __shfl_xor(lmax, m, 64));
+    }
+    if (rmax == 0) continue;
+    // ---- stage both halves' read and window words
+    __syncthreads();
+    {
+      const int nrw = (lmax + 15) >> 4, nww = (cmax + 15) >> 4;
+      for (int hf = 0; hf < 2; ++hf) {
+        const PairTask &p = hf ? tb : ta;
+        uint32_t *rdw = hf ? rdw1 : rdw0, *win = hf ? win1 : win0;
+        if (p.live) {
+          const uint32_t *rp = A.reads + A.read_word_off[p.r];
+          const int lw = (p.L + 15) >> 4;
+          for (int q = 0; q < nrw; ++q) rdw[q * 64 + lane] = q < lw ? rp[q] : 0u;
+          const int64_t fw = rt_off[p.k] + (p.ws >> 4);
+          const int64_t last = rt_off[p.k] + ((rt_len[p.k] - 1) >> 4);
+          const uint32_t sh = 2u * (uint32_t)(p.ws & 15);
+          uint32_t lo = A.ref_words[fw];
+          for (int q = 0; q < nww; ++q) {
+            const uint32_t hi = fw + q + 1 <= last ? A.ref_words[fw + q + 1] : 0u;
+            win[q * 64 + lane] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+            lo = hi;
+          }
+        } else {
+          for (int q = 0; q < nrw; ++q) rdw[q * 64 + lane] = 0u;
+          for (int q = 0; q < nww; ++q) win[q * 64 + lane] = 0u;
+        }
+      }
+    }
+    __syncthreads();
+    auto qbase = [&](int hf, int i) -> uint32_t {  // oriented read base of row i (0 past the read)
+      const PairTask &p = hf ? tb : ta;
+      if (i >= p.L) return 0u;
+      const uint32_t *rdw = hf ? rdw1 : rdw0;
+      const int src = p.h == 0 ? i : p.L - 1 - i;
+      const uint32_t b = (rdw[(src >> 4) * 64 + lane] >> (2 * (src & 15))) & 3u;
+      return p.h == 0 ? b : 3u - b;
+    };
+    auto wbase = [&](int hf, int j) -> uint32_t {
+      const uint32_t *win = hf ? win1 : win0;
+      return (win[(j >> 4) * 64 + lane] >> (2 * (j & 15))) & 3u;
+    };
+
+    // ---- sweep: strips of R rows, columns left to right
+    uint32_t endv0 = 0, endv1 = 0;
+    const int nstrips = (rmax + R - 1) / R;
+    for (int s = 0; s < nstrips; ++s) {
+      const int r0 = s * R;
+      uint32_t sel[R], Hl[R], E[R];
+#pragma unroll
+      for (int x = 0; x < R; ++x) {
+        sel[x] = qbase(0, r0 + x) | (12u << 8) | ((4u + qbase(1, r0 + x)) << 16) | (12u << 24);
+        Hl[x] = hleft;  // H(i, -1) = 0, clean
+        E[x] = z0;      // E(i, 0) = zero
+      }
+      uint32_t hup_prev = hleft;  // H(r0 - 1, -1)
+      uint32_t Zj = z0;
+      if (s > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      for (int c = 0; c < cmax; ++c) {
+        const uint32_t Zn = padd(Zj, zc);
+        const uint32_t tlo = sx * 0x01010101u ^ ((sx ^ sm) << (8 * wbase(0, c)));
+        const uint32_t thi = sx * 0x01010101u ^ ((sx ^ sm) << (8 * wbase(1, c)));
+        uint32_t hup, F;
+        if (s == 0) {
+          hup = Zj & 0xFFF0FFF0u;  // H(-1, c) = 0, clean
+          F = Zj;                  // F(0, c) clamped to zero
+        } else {
+          const uint2 b = bscr[c * 64 + lane];
+          hup = b.x;
+          F = b.y;
+        }
+        uint32_t Hd = hup_prev;
+        hup_prev = hup;
+        uint32_t word[G];
+#pragma unroll
+        for (int x = 0; x < R; ++x) {
+          const uint32_t diag = padd(Hd, __builtin_amdgcn_perm(thi, tlo, sel[x]));
+          const uint32_t Ht = half_max3(diag, E[x], F);
+          const uint32_t nib = (Ht & 0x000C000Cu) | (E[x] & 0x00010001u) | (F & 0x00020002u);
+          if ((x & 3) == 0)
+            word[x >> 2] = nib;
+          else
+            word[x >> 2] |= nib << (4 * (x & 3));
+          const uint32_t Hc = Ht & 0xFFF0FFF0u;
+          const uint32_t En = half_max3(padd(E[x] & 0xFFFEFFFEu, kee), padd(Hc, kue), Zn);
+          F = half_max3(padd(F & 0xFFFDFFFDu, kfe), padd(Hc, kuf), Zj);
+          Hd = Hl[x];
+          Hl[x] = Hc;
+          E[x] = En;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) bits[(((int64_t)s * cmax + c) * G + g) * 64 + lane] = word[g];
+        if (s + 1 < nstrips) bscr[c * 64 + lane] = make_uint2(Hl[R - 1], F);
+        if ((c == ta.je && ta.ie >= r0 && ta.ie < r0 + R) || (c == tb.je && tb.ie >= r0 && tb.ie < r0 + R)) {
+#pragma unroll
+          for (int x = 0; x < R; ++x) {
+            if (c == ta.je && ta.ie == r0 + x) endv0 = Hl[x] & 0xFFFFu;
+            if (c == tb.je && tb.ie == r0 + x) endv1 = Hl[x] >> 16;
+          }
+        }
+        Zj = Zn;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __syncthreads();
+    }
+
+    // ---- walk each half's slot back from its end cell
+    auto code_at = [&](int hf, int i, int j) -> uint32_t {
+      const int s = i / R, r = i - s * R;
+      const uint32_t w = bits[(((int64_t)s * cmax + j) * G + (r >> 2)) * 64 + lane];
+      return (w >> (16 * hf + 4 * (r & 3))) & 15u;
+    };
+    for (int hf = 0; hf < 2; ++hf) {
+      const PairTask &p = hf ? tb : ta;
+      if (!p.live) continue;
+      const int64_t t = first + 64 * hf + lane;
+      const int32_t endval = (int32_t)((hf ? endv1 : endv0) >> 4) - beta - p.je * c0;
+      if (endval != p.sc) {
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = -2;
+        atomicAdd(A.err, 1ull);
+        continue;
+      }
+      uint32_t *out = A.cigar + t * (int64_t)A.cap;
+      int n = 0;
+      uint32_t cur_op = 0, cur_len = 0;
+      auto flush = [&]() {
+        if (cur_len) {
+          if (n < A.cap) out[n] = (cur_len << 4) | cur_op;
+          ++n;
+        }
+      };
+      auto emit = [&](uint32_t op) {
+        if (op != cur_op) {
+          flush();
+          cur_op = op;
+          cur_len = 0;
+        }
+        ++cur_len;
+      };
+      if (p.L - 1 - p.ie > 0) {
+        cur_op = 4;
+        cur_len = (uint32_t)(p.L - 1 - p.ie);
+      }
+      // state 0: in H; 1: in a gap consuming read bases (F); 2: consuming window bases (E)
+      int i = p.ie, j = p.je, state = 0, start_i = 0, start_j = 0;
+      uint32_t code = code_at(hf, i, j);
+      for (;;) {
+        if (state == 0) {
+          const uint32_t src = code >> 2;
+          if (src == 2u) {
+            emit(qbase(hf, i) == wbase(hf, j) ? 7u : 8u);
+            start_i = i;
+            start_j = j;
+            if (i == 0 || j == 0) break;  // a diagonal from the boundary starts the alignment
+            code = code_at(hf, i - 1, j - 1);
+            if ((code >> 2) == 3u) break;  // a diagonal from a cell with H = 0 starts it
+            --i;
+            --j;
+          } else if (src == 1u) {
+            state = 1;
+          } else if (src == 0u) {
+            state = 2;
+          } else {  // H = 0 on the path: cannot happen for a consistent matrix
+            start_i = i + 1;
+            start_j = j + 1;
+            break;
+          }
+        } else if (state == 1) {
+          emit(1u);
+          const bool open = (code >> 1) & 1u;
+          if (i == 0) break;  // cannot happen: F(0, j) is at most zero
+          --i;
+          if (open) state = 0;
+          code = code_at(hf, i, j);
+        } else {
+          emit(2u);
+          const bool open = code & 1u;
+          if (j == 0) break;  // cannot happen: E(i, 0) is at most zero
+          --j;
+          if (open) state = 0;
+          code = code_at(hf, i, j);
+        }
+      }
+      if (start_i > 0) {
+        emit(4u);
+        cur_len = (uint32_t)start_i;
+      }
+      flush();
+      if (n > A.cap) {
+        for (int x = 0; x < A.cap; ++x) out[x] = 0u;  // an over-capacity row is cleared
+        A.ref_start[t] = -1;
+        A.read_start[t] = -1;
+        A.n_ops[t] = -1;
+      } else {
+        for (int x = 0; x < n / 2; ++x) {
+          const uint32_t a = out[x];
+          out[x] = out[n - 1 - x];
+          out[n - 1 - x] = a;
+        }
+        A.ref_start[t] = p.ws + start_j;
+        A.read_start[t] = (int16_t)start_i;
+        A.n_ops[t] = n;
+      }
+    }
+  }
+}
+
+size_t trace_pair_block_bytes(int max_read_len, int wcap) {
+  const size_t strips = (size_t)(max_read_len + kTraceRows - 1) / kTraceRows;
+  return strips * (size_t)wcap * (kTraceRows / 4) * 64 * 4 + (size_t)wcap * 64 * 8;
+}
+
+int trace_pair_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_trace_pair<kTraceRows>), 64,
+                                                  16384) != hipSuccess)
+    return 1;
+  return n < 1 ? 1 : n;
+}
+
+// The int16-pair layout holds every value of the traced rectangles: scores up to
+// match * max_read_len, column offsets up to (wcap - 1) * c, the bias and a tag,
+// below 0x7C00 after scaling by 16; and each table byte 16 * (s + c) + 8 fits.
+int trace_pair_fits(int match, int mismatch, int goe, int ge, int max_read_len, int wcap, int32_t *beta) {
+  const int c = -mismatch;
+  int b = c;
+  if (goe > b) b = goe;
+  if (ge > b) b = ge;
+  if (16 * (match + c) + 8 > 255) return 0;
+  const int64_t top = (int64_t)match * max_read_len + b + (int64_t)(wcap - 1) * c + 1;
+  if (top * 16 > 0x7BFF) return 0;
+  *beta = b;
+  return 1;
+}
+
+hipError_t launch_trace_pair(const TraceInterArgs &A, const RefTable &T, int grid, hipStream_t st) {
+  if (A.a.n_slots == 0) return hipSuccess;
+  const size_t lds = (size_t)(A.rwords + A.wwords) * 2 * 64 * sizeof(uint32_t);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_pair<kTraceRows>), dim3(grid), dim3(64), lds, st, A, T);
+  return hipGetLastError();
 }
 
 size_t trace_inter_block_bytes(int max_read_len, int wcap) {

@@ -116,7 +116,10 @@ def test_ctx_shapes_change_and_graph_cache(tmp_path):
     assert all("replay" in p for p in plans[3:]), plans
     with open(cache) as f:
         tuned = json.load(f)
-    assert tuned and all("bin_width" in v for v in tuned.values())
+    fields = ("bin_width", "descending", "strip_cap", "strip_slack", "grid_quarters", "ms")
+    assert tuned and all(all(f in v for f in fields) for v in tuned.values())
+    # the plan names the strip height each length range takes and how many plans were timed
+    assert "heights 1-" in plans[0] and " plans)" in plans[0], plans[0]
     # a new context reads the cache and does not tune again
     ctx2 = sw.Context(5000, 60000, tune_cache=cache)
     refs, db, out = prepared[0]

@@ -54,7 +54,8 @@ def test_long_reference_reaches_past_2_32():
 
 
 @pytest.mark.parametrize("precision,kernel", [(sw.PREC_INT16, sw.KERNEL_INTER), (sw.PREC_INT32, sw.KERNEL_INTER),
-                                              (sw.PREC_INT32, sw.KERNEL_INTRA), (sw.PREC_AUTO, sw.KERNEL_AUTO)])
+                                              (sw.PREC_INT16, sw.KERNEL_INTRA), (sw.PREC_INT32, sw.KERNEL_INTRA),
+                                              (sw.PREC_AUTO, sw.KERNEL_AUTO)])
 def test_plain_kernels_match_oracle(precision, kernel):
     b, refs, exp = batch_and_refs()
     db = sw.DeviceBatch.upload(b)

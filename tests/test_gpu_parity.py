@@ -20,8 +20,9 @@ PRECISIONS = [sw.PREC_INT16, sw.PREC_INT32]
 
 def _case(batch, precision, **kw):
     exp, _ = oracle_align(batch)
-    if precision == sw.PREC_INT32 and "kernel" not in kw:
-        # int32 runs both kernel families: one CAL strand per lane, one wavefront per task
+    if precision in (sw.PREC_INT16, sw.PREC_INT32) and "kernel" not in kw:
+        # both kernel families: one CAL (int16) or one CAL strand (int32) per lane, and
+        # one wavefront per task (int16: one CAL, both strands in the halves)
         for kernel in (sw.KERNEL_INTER, sw.KERNEL_INTRA):
             got = gpu_align(batch, precision, kernel=kernel, **kw)
             assert_same(got, exp, f"{batch.name} prec={precision} kernel={kernel} {kw}")
@@ -49,9 +50,12 @@ def test_auto_kernel_choice_small_and_large():
 
 @pytest.mark.parametrize("seed", range(3))
 def test_intra_long_reads_many_strips(seed):
-    """Wide windows: several 64-column strips handed over through LDS."""
+    """Wide windows: several 64-column strips handed over through LDS (int32; int16
+    pairs up to the 255-base read bound of the int16 path)."""
     b = wl.random_small_batch(60 + seed, n_reads=25, read_len=(150, 400), ref_len=(500, 5000), band=100)
     _case(b, sw.PREC_INT32, kernel=sw.KERNEL_INTRA, max_read_len=400)
+    b16 = wl.random_small_batch(63 + seed, n_reads=25, read_len=(120, 255), ref_len=(500, 5000), band=150)
+    _case(b16, sw.PREC_INT16, kernel=sw.KERNEL_INTRA, max_read_len=255)
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
@@ -185,8 +189,9 @@ def test_int16_tag_width_and_bias_edges(edge, mode):
             # near the reference ends, with mixed strand masks)
             b = dataclasses.replace(b, cal_pos=np.full_like(b.cal_pos, 12), strand=np.full_like(b.strand, 3))
         exp, _ = oracle_align(b, mode=mode)
-        got = gpu_align(b, sw.PREC_INT16, kernel=sw.KERNEL_INTER, max_read_len=mrl, mode=mode)
-        assert_same(got, exp, f"{edge} homopolymer={homo} mode={mode}")
+        for kernel in (sw.KERNEL_INTER, sw.KERNEL_INTRA):
+            got = gpu_align(b, sw.PREC_INT16, kernel=kernel, max_read_len=mrl, mode=mode)
+            assert_same(got, exp, f"{edge} homopolymer={homo} mode={mode} kernel={kernel}")
         if homo:
             # the top of the range is reached: the longest read with a CAL scores match * L
             has_cal = np.diff(b.cal_ptr) > 0

@@ -11,7 +11,8 @@ from tests.gpu_util import SLOTS, assert_same, gpu_align, oracle_align, scoring_
 pytestmark = pytest.mark.gpu
 
 FR = sw.MODE_FINAL_ROW
-KERNELS = [(sw.PREC_INT16, sw.KERNEL_INTER), (sw.PREC_INT32, sw.KERNEL_INTER), (sw.PREC_INT32, sw.KERNEL_INTRA)]
+KERNELS = [(sw.PREC_INT16, sw.KERNEL_INTER), (sw.PREC_INT16, sw.KERNEL_INTRA), (sw.PREC_INT32, sw.KERNEL_INTER),
+           (sw.PREC_INT32, sw.KERNEL_INTRA)]
 
 
 def _fr_case(batch, **kw):
