@@ -193,8 +193,7 @@ int sw_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t n_rea
                    sw_stream_t stream);
 
 /*
- * Score Tracker variants (section 4.2: keep the best CAL, a number of
- * highest-scoring CALs, or every CAL tied for the highest score).
+ * Score Tracker variants (section 4.2): best CAL, top-k CALs, or all tied CALs.
  *
  * sw_topk: the k best slots of each read over all its CALs and both strands,
  * highest score first and the lower slot index first among equal scores.

@@ -288,8 +288,7 @@ void oracle_reduce_best(const int64_t *cal_ptr, const int16_t *cal_ref, int32_t 
 }
 
 /*
- * Score Tracker variants (section 4.2: the single best CAL, some number of
- * highest-scoring CALs, or all CALs tied for the highest score).
+ * Score Tracker variants (section 4.2): best CAL, top-k CALs, or all tied CALs.
  * Top k slots of each read over all its CALs and strands: highest score first,
  * lower slot index first among equal scores; negative scores are skipped and
  * missing entries are (-1, -1).  Outputs [n_reads * k].
