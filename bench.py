@@ -54,6 +54,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def seeding_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("sw_index.hip", "sw_index.h", "sw_filter.hip", "sw_filter.h", "sw_seed.cpp"):
+        with open(os.path.join(ROOT, "paper_1805_00106_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# The kernels of each seeding stage whose HBM bytes the traffic profile holds.
+SEED_STAGE_KERNELS = {"index_build": ("k_index_seeds", "k_index_ptr"), "find": ("k_find_count", "k_find_write"),
+                      "filter": ("k_filter_count_wave", "k_filter_write_wave")}
+
+
+def load_seeding_traffic(workload: str = "chromosome_scale"):
+    """Per-kernel HBM bytes of the seeding and filter kernels from the committed
+    rocprofv3 counter summary, if it was taken on the current seeding source."""
+    path = os.path.join(PROFILE_DIR, f"traffic_seeding_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != seeding_source_hash():
+        return None
+    return rec.get("kernels")
+
+
 def load_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current kernel source."""
@@ -508,7 +534,18 @@ class Leg:
             ((best % 2 == 1) == np.asarray(b.true_strand, bool))
         info = ix.info()
         ix.close()
+        # HBM rate of each stage: its kernels' bytes (from the counter profile) over its time here
+        traffic = load_seeding_traffic()
+        gbps = None
+        if traffic:
+            gbps = {}
+            for stage, kernels in SEED_STAGE_KERNELS.items():
+                nbytes = sum(traffic[k]["fetch_bytes"] + traffic[k]["write_bytes"] for k in kernels if k in traffic)
+                t_s = build_s if stage == "index_build" else ms[stage] * 1e-3
+                gbps[stage] = round(nbytes / t_s / 1e9, 1)
         return {"seed_len": seed_len, "stride": stride, "max_cals_per_seed": limit,
+                "hbm_gbps": gbps, "hbm_note": "bytes of each stage's own kernels (counter profile) over its "
+                                              "wall time between synchronisations; peak 8000 GB/s",
                 "index_build_s": round(build_s, 3), "index_entries": info["entries"],
                 "index_gb": round(info["device_bytes"] / 1e9, 3),
                 "raw_cals": found.n_cals, "kept_cals": kept.n_cals,

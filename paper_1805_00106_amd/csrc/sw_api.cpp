@@ -477,7 +477,7 @@ int trace_launch(int64_t n_slots, int64_t n_cals, const sw_scoring_t *sc, TraceL
   t->inter = t->pair || sc->kernel == SW_KERNEL_INTER || (sc->kernel == SW_KERNEL_AUTO && bb <= kTraceInterBlockLimit);
   if (t->pair) {
     const int64_t tiles = (n_slots + 127) / 128;
-    const int64_t resident = (int64_t)device_cus() * swk::trace_pair_blocks_per_cu();
+    const int64_t resident = (int64_t)device_cus() * swk::trace_pair_blocks_per_cu(m.max_read_len);
     const int64_t budget = std::max<int64_t>(device_cus(), (int64_t)(kTracePairWorkspace / align256(bp)));
     t->grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(tiles, resident), budget));
     t->block_bytes = align256(bp);

@@ -31,8 +31,12 @@ hipError_t launch_trace_inter(const TraceInterArgs &A, const RefTable &T, int gr
 
 // Two traced slots per lane in int16 halves (128 slots per wavefront), when the
 // layout holds the scoring's values (trace_pair_fits, which sets beta).
+// Strip heights (rows per lane in registers) compiled for it; the one used is a
+// function of the read-length bound.
+#define SW_TRACE_PAIR_ROWS(X) X(24) X(28) X(32) X(34)
+int trace_pair_rows(int max_read_len);
 size_t trace_pair_block_bytes(int max_read_len, int wcap);
-int trace_pair_blocks_per_cu();
+int trace_pair_blocks_per_cu(int max_read_len);
 int trace_pair_fits(int match, int mismatch, int goe, int ge, int max_read_len, int wcap, int32_t *beta);
 hipError_t launch_trace_pair(const TraceInterArgs &A, const RefTable &T, int grid, hipStream_t st);
 

@@ -714,7 +714,7 @@ __device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) {
 
 template <int R>
 __global__ __launch_bounds__(64) void k_trace_pair(const TraceInterArgs I, const RefTable T) {
-  constexpr int G = R / 4;  // code words per column per lane (4 rows x 2 halves each)
+  constexpr int G = (R + 3) / 4;  // code words per column per lane (4 rows x 2 halves each)
   extern __shared__ uint32_t tpsm[];
   __shared__ int64_t rt_off[SW_MAX_REFS], rt_len[SW_MAX_REFS];
   const TraceArgs &A = I.a;
@@ -958,16 +958,46 @@ __global__ __launch_bounds__(64) void k_trace_pair(const TraceInterArgs I, const
   }
 }
 
-size_t trace_pair_block_bytes(int max_read_len, int wcap) {
-  const size_t strips = (size_t)(max_read_len + kTraceRows - 1) / kTraceRows;
-  return strips * (size_t)wcap * (kTraceRows / 4) * 64 * 4 + (size_t)wcap * 64 * 8;
+// Strip height of the two-slots-per-lane traceback for a read-length bound: the
+// compiled height with the fewest swept rows, counting each strip's column
+// overhead (table, boundary row, code stores) as four rows; the taller on ties.
+int trace_pair_rows(int max_read_len) {
+  int best = 0, best_cost = 0x7fffffff;
+#define SW_TP_CHOOSE(RR)                                        \
+  {                                                             \
+    const int ns = (max_read_len + RR - 1) / RR;                \
+    const int cost = ns * RR + 4 * ns;                          \
+    if (cost < best_cost || (cost == best_cost && RR > best)) { \
+      best_cost = cost;                                         \
+      best = RR;                                                \
+    }                                                           \
+  }
+  SW_TRACE_PAIR_ROWS(SW_TP_CHOOSE)
+#undef SW_TP_CHOOSE
+  return best;
 }
 
-int trace_pair_blocks_per_cu() {
+size_t trace_pair_block_bytes(int max_read_len, int wcap) {
+  const int R = trace_pair_rows(max_read_len);
+  const size_t strips = (size_t)(max_read_len + R - 1) / R;
+  return strips * (size_t)wcap * (size_t)((R + 3) / 4) * 64 * 4 + (size_t)wcap * 64 * 8;
+}
+
+int trace_pair_blocks_per_cu(int max_read_len) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_trace_pair<kTraceRows>), 64,
-                                                  16384) != hipSuccess)
-    return 1;
+  hipError_t e = hipErrorInvalidValue;
+  switch (trace_pair_rows(max_read_len)) {
+#define SW_TP_OCC(RR)                                                                                          \
+  case RR:                                                                                                     \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_trace_pair<RR>), 64, \
+                                                     16384);                                                   \
+    break;
+    SW_TRACE_PAIR_ROWS(SW_TP_OCC)
+#undef SW_TP_OCC
+    default:
+      break;
+  }
+  if (e != hipSuccess) return 1;
   return n < 1 ? 1 : n;
 }
 
@@ -989,7 +1019,16 @@ int trace_pair_fits(int match, int mismatch, int goe, int ge, int max_read_len, 
 hipError_t launch_trace_pair(const TraceInterArgs &A, const RefTable &T, int grid, hipStream_t st) {
   if (A.a.n_slots == 0) return hipSuccess;
   const size_t lds = (size_t)(A.rwords + A.wwords) * 2 * 64 * sizeof(uint32_t);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_pair<kTraceRows>), dim3(grid), dim3(64), lds, st, A, T);
+  switch (trace_pair_rows(A.a.max_read_len)) {
+#define SW_TP_LAUNCH(RR)                                                                           \
+  case RR:                                                                                         \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_pair<RR>), dim3(grid), dim3(64), lds, st, A, T); \
+    break;
+    SW_TRACE_PAIR_ROWS(SW_TP_LAUNCH)
+#undef SW_TP_LAUNCH
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
