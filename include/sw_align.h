@@ -62,7 +62,14 @@ typedef struct ihipStream_t *sw_stream_t; /* a hipStream_t */
 #define SW_MAX_REFS 64       /* references per reference set */
 #define SW_MAX_BAND 1024     /* widest band accepted */
 
-/* precision of the dynamic-programming values inside the kernels */
+/* precision of the dynamic-programming values inside the kernels.  The int16
+ * bound: match * max_read_len <= 510, mismatch >= -511, gap_open + 2 * gap_extend
+ * <= 511, and some K in {6, 5, 4} with
+ *   (beta + match * max_read_len + 1 + 49 * gap_extend) * 2^K <= 0x7BFF,
+ *   beta = max(-mismatch, gap_open + gap_extend + 1, ceil(256 / 2^K) + gap_extend)
+ * (the int16 sweep holds biased scores with K position bits, and offsets row r
+ * of a strip of at most 50 rows by r * gap_extend).  At K = 4 and gap_extend <= 19
+ * the first three conditions imply the fourth. */
 #define SW_PREC_AUTO 0  /* int16 pairs when the bound holds, else int32 */
 #define SW_PREC_INT16 1 /* error SW_ERR_BOUND if the bound does not hold */
 #define SW_PREC_INT32 2

@@ -42,7 +42,8 @@ int validate_scoring(const sw_scoring_t *sc, ScoreMode *mode) {
   // int32 path: values are V * 4096 + tag with |V| < 2^19
   const int64_t top = (int64_t)sc->match * mrl;
   if (top > (1 << 19) - 2 || -(int64_t)sc->mismatch > (1 << 18) || goe2 > (1 << 18)) return SW_ERR_SCORING;
-  // int16 path: values are V * 64 + tag in int16; the bound needs V <= 510 everywhere
+  // int16 path: biased values with K tag bits and per-row offsets (DpConst) in
+  // int16; the bound needs V <= 510 everywhere and a tag width that holds them
   int32_t kb = 0, beta = 0;
   const bool fits16 = top <= 510 && sc->mismatch >= -511 && goe2 <= 511 && int16_layout(sc, &kb, &beta);
   bool int16;

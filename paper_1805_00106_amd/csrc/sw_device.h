@@ -34,18 +34,27 @@ struct RefTable {
 // non-negative halves, in increasing order), so H = max(diagonal, E, F) and the
 // clamped gap term E = max(E - ge, H - go - ge, 0) are one v_pk_maximum3_f16
 // each; a wall column (substitution 0x8000) makes the diagonal operand a
-// negative half, below every other operand.  K is the largest of 6, 5, 4 for
-// which (beta + top + 1) * 2^K stays below 0x7C00, top = match * (longest read):
-// chosen for the call's read-length bound, and again per tile of 64 CALs for
-// the tile's longest read (shorter reads allow the wider tag).
+// negative half, below every other operand.
+//
+// In the one-CAL-per-lane sweep, row r of a strip (r < kInt16StripRowsMax)
+// further carries r * gap_extend * 2^K.  A vertical gap move then keeps its
+// value (F = max(F, H - gap_open)), a diagonal move carries + gap_extend * 2^K in
+// its substitution, and the zero of row r is the column's zero plus the row's
+// offset (a wave-uniform value).  K is the largest of 6, 5, 4 for which
+// (beta + top + 1 + (kInt16StripRowsMax - 1) * gap_extend) * 2^K stays below
+// 0x7C00, top = match * (longest read): chosen for the call's read-length bound,
+// and again per tile of 64 CALs for the tile's longest read (shorter reads allow
+// the wider tag).
+constexpr int kInt16StripRowsMax = 50;
+
 struct DpConst {
   // int16 pairs, both halves hold the same constant
-  uint32_t goe_e16, ge_e16, goe_f16, ge_f16;
+  uint32_t goe_e16, ge_e16, goe_f16, ge_f16;  // ge_f16 is also the row step
   uint32_t tag16;    // 2^K
   uint32_t bias16;   // beta * 2^K
   int32_t kbits16;   // K
   int32_t beta16;    // beta
-  uint32_t xlo, dlo, xhi, dhi;  // substitution table bytes (see the kernel)
+  uint32_t xlo, dlo, xhi, dhi;  // substitution (with the row step) table bytes
   int32_t match, mismatch, goe, ge;  // the scoring (goe = gap_open + gap_extend)
   // int32 (K = 12)
   int32_t goe_e32, ge_e32, goe_f32, ge_f32, sm32, sx32, e0_32;
@@ -66,8 +75,11 @@ __host__ __device__ inline int set_int16_layout(DpConst &K, int64_t top) {
     const int32_t U = 1 << kb;
     int32_t b = -K.mismatch;
     if (K.goe + 1 > b) b = K.goe + 1;
-    if ((256 + U - 1) / U > b) b = (256 + U - 1) / U;
-    if (b > 0x7BFF || ((int64_t)b + top + 1) * U > 0x7BFF) continue;
+    // the padding rows' substitution (-256) on a strip's row 0, whose diagonal
+    // operand is handed over as H - gap_extend * 2^K
+    if ((256 + U - 1) / U + K.ge > b) b = (256 + U - 1) / U + K.ge;
+    const int64_t rows = (int64_t)(kInt16StripRowsMax - 1) * K.ge;
+    if (b > 0x7BFF || ((int64_t)b + top + 1 + rows) * U > 0x7BFF) continue;
     const uint32_t pair1 = 0x00010001u;
     K.goe_e16 = (uint32_t)(uint16_t)(K.goe * U + 1) * pair1;
     K.ge_e16 = (uint32_t)(uint16_t)(K.ge * U + 1) * pair1;
@@ -77,8 +89,9 @@ __host__ __device__ inline int set_int16_layout(DpConst &K, int64_t top) {
     K.bias16 = (uint32_t)(b * U) * pair1;
     K.kbits16 = kb;
     K.beta16 = b;
-    // substitution s * 2^K - 1 (the tag step of a diagonal move), as bytes
-    const uint32_t sm = (uint16_t)(K.match * U - 1), sx = (uint16_t)(K.mismatch * U - 1);
+    // substitution s * 2^K - 1 (the tag step of a diagonal move) plus the row
+    // step gap_extend * 2^K, as bytes
+    const uint32_t sm = (uint16_t)((K.match + K.ge) * U - 1), sx = (uint16_t)((K.mismatch + K.ge) * U - 1);
     const uint32_t lo_m = sm & 0xFFu, hi_m = sm >> 8, lo_x = sx & 0xFFu, hi_x = sx >> 8;
     K.xlo = lo_x * 0x01010101u;
     K.dlo = lo_x ^ lo_m;

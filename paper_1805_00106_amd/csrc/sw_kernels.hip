@@ -306,6 +306,14 @@ __device__ __forceinline__ void fold16_row(const DpConst &K, v2s m, int row, int
   }
 }
 
+// A wave-uniform value the compiler may not see through: a running sum taken
+// through it is formed row by row (one scalar add each) instead of being
+// rewritten as row * step and hoisted into one scalar register per row.
+__device__ __forceinline__ uint32_t opaque_s(uint32_t x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 // One strip of R read rows swept over every window column.  FIRST: the strip
 // starts at read row 0 (top boundary H = 0); LAST: no strip follows (nothing
 // is written to the scratch rows).  FR: final-row mode (only row L-1 may hold
@@ -316,12 +324,22 @@ template <int R, bool FIRST, bool LAST, bool FR, bool TRACK = true>
 __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, const uint32_t *rdw, uint2 *scr,
                                         int lane, int r0, int L, int W, int Wmin, int Wmax,
                                         volatile uint64_t *best) {
+  static_assert(R <= kInt16StripRowsMax, "the int16 layout holds row offsets of at most kInt16StripRowsMax rows");
   const v2s GOE_E = pair(K.goe_e16), GE_E = pair(K.ge_e16);
-  const v2s GOE_F = pair(K.goe_f16), GE_F = pair(K.ge_f16);
+  // Row r of the strip carries + r * GF (GF = gap_extend * 2^K): F then moves down
+  // a row with no gap-extend step, F = max(F, H - gap_open).  The rows above and
+  // below the strip are handed over at offset 0 (H as H - GF, for the diagonal
+  // step's + GF).
+  const uint32_t GFu = K.ge_f16;
+  const v2s GOE_F = pair(K.goe_f16), GO_F = pair(K.goe_f16 - GFu), GF = pair(GFu);
+  const v2s RGF = pair((uint32_t)R * GFu);
   const v2s TAGU = pair(K.tag16), BIAS = pair(K.bias16);
   const int U = 1 << K.kbits16;
   uint32_t sel[R];
   v2s Hl[R], E[R], M[R];
+  // column -1 (H = 0, tag 2^K) on row r, formed row by row in this strip (hoisted,
+  // the 2R starting values would stay live across the whole kernel)
+  uint32_t h0 = K.tag16 + K.bias16;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = r0 + r;
@@ -332,12 +350,13 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
     } else {
       sel[r] = 0x0D0C0D0Cu;
     }
-    Hl[r] = TAGU + BIAS;
+    Hl[r] = pair(h0);
     // E is kept clamped at zero (see below): column 0 starts at its zero
-    E[r] = TAGU + BIAS - pair(0x00010001u);
+    E[r] = pair(h0 - 0x00010001u);
     M[r] = pair(0u);
+    h0 = opaque_s(h0 + GFu);
   }
-  v2s hup_prev = TAGU + BIAS;
+  v2s hup_prev = TAGU + BIAS - GF;
   // the hand-over row of the next column, loaded one column ahead
   uint2 pf = make_uint2(0, 0);
   if (!FIRST) {
@@ -363,7 +382,7 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
       }
       v2s hup, F;
       if (FIRST) {
-        hup = pair(zt);
+        hup = pair(zt) - GF;
         F = pair(zt) - GOE_F;
       } else {
         hup = pair(pf.x);
@@ -371,14 +390,16 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
         if (c + 1 < Wmax) pf = (scr + (size_t)(c + 1) * 64)[lane];
       }
       // the zero of the next column (the tag one lower), where E is clamped
-      const v2s ZTN = pair(zt - 0x00010001u);
+      const uint32_t ztn = zt - 0x00010001u;
       // E is carried as max(E, 0): then H = max(diagonal, E, F) needs no zero
       // operand, and the clamped E obeys the same recurrence clamped at zero
       // (max(max(E, 0) - ge, H - go - ge, 0) = max(E - ge, H - go - ge, 0)).
-      // Per row: H in one three-way maximum, F and E in three ops each, the
-      // diagonal operand of the next row in two, the running maximum in one.
+      // Per row: H in one three-way maximum, E in three ops (its zero, with the
+      // row's offset, is wave-uniform), F in two, the diagonal operand of the
+      // next row in two, the running maximum in one.
       v2s t = hup_prev + pair(__builtin_amdgcn_perm(thi, tlo, sel[0]));
       hup_prev = hup;
+      uint32_t zr = ztn;  // the zero of the next column on row r
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         // the diagonal of row r+1 is row r's previous H: consume it before row r's
@@ -387,17 +408,17 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
         if (r + 1 < R) tn = Hl[r] + pair(__builtin_amdgcn_perm(thi, tlo, sel[r + 1]));
         const v2s H = vmax3h(t, E[r], F);
         if (r + 1 < R) t = tn;
-        const v2s f2 = F - GE_F;
         const v2s e2 = E[r] - GE_E;
-        const v2s v = H - GOE_F;
+        const v2s v = H - GO_F;
         const v2s u = H - GOE_E;
-        F = vmax(f2, v);
-        E[r] = vmax3h(e2, u, ZTN);
+        F = vmax(F, v);
+        E[r] = vmax3h(e2, u, pair(zr));
+        zr = opaque_s(zr + GFu);
         if (!FR || TRACK) M[r] = vmax(M[r], H);
         Hl[r] = H;
       }
       // the column's scratch row: a wave-uniform base plus the lane
-      if (!LAST) (scr + (size_t)c * 64)[lane] = make_uint2(bits(Hl[R - 1]), bits(F));
+      if (!LAST) (scr + (size_t)c * 64)[lane] = make_uint2(bits(Hl[R - 1] - RGF), bits(F - RGF));
     }
     if (FR && TRACK) {
       // read-end-anchored scoring: only row L-1 may hold the best cell
@@ -405,8 +426,16 @@ __device__ __forceinline__ void strip16(const DpConst &K, const uint32_t *win, c
       v2s m = pair(0u);
 #pragma unroll
       for (int r = 0; r < R; ++r) m = r == rr ? M[r] : m;
+      if (rr > 0 && rr < R) m = m - pair((uint32_t)rr * GFu);  // the row's offset
       fold16_row(K, m, L - 1, tb, best);
     } else if (!FR) {
+      // the rows' offsets off, so that maxima compare across rows
+      uint32_t off = 0;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        off = opaque_s(off + GFu);
+        M[r] = M[r] - pair(off);
+      }
       fold16<R>(K, M, r0, tb, best);
     }
     if (tend < Wmax) {

@@ -81,6 +81,15 @@ def test_int16_bound_rejected_when_requested(sw):
     assert _call(sw, sc) == -4
     sc = sw.Scoring.make(precision=sw.PREC_INT16, max_read_len=255)
     assert _call(sw, sc) == -5                                         # passes bound, then no workspace
+    # the one-CAL-per-lane sweep offsets row r of a strip by r * gap_extend * 2^K:
+    # (beta + match * L + 1 + 49 * gap_extend) * 16 must stay below 0x7C00 (K = 4),
+    # beta = max(|mismatch|, gap_open + gap_extend + 1, 16 + gap_extend)
+    for (m, x, go, ge, mrl), code in (((3, -1, 10, 29, 170), -5),     # (45 + 510 + 1 + 1421) * 16 = 31632
+                                      ((3, -1, 10, 30, 170), -4),     # (46 + 510 + 1 + 1470) * 16 = 32432
+                                      ((1, -1, 300, 2, 80), -5),
+                                      ((1, -1, 300, 100, 80), -4)):   # 49 * 100 of row offsets
+        sc = sw.Scoring.make(m, x, go, ge, 8, sw.PREC_INT16, max_read_len=mrl)
+        assert _call(sw, sc) == code, (m, x, go, ge, mrl)
 
 
 def test_reference_set_validation(sw):

@@ -129,12 +129,14 @@ def test_ctx_shapes_change_and_graph_cache(tmp_path):
     ctx2.close()
 
 
-@pytest.mark.parametrize("scoring,mrl", [((2, -3, 5, 2), 243), ((2, -500, 5, 2), 250), ((1, -1, 300, 100), 80)],
-                         ids=["K6-top", "K4", "K6-gap-terms"])
+@pytest.mark.parametrize("scoring,mrl", [((2, -3, 5, 2), 194), ((2, -500, 5, 2), 250), ((1, -1, 300, 2), 80),
+                                         ((3, -1, 10, 29), 170)],
+                         ids=["K6-top", "K4", "K6-gap-terms", "K4-row-offsets"])
 def test_ctx_int16_tag_width_and_bias_edges(scoring, mrl):
     """The batched path at the edges of the int16 layout (tag width 6 at the top of
-    its range, tag width 4, the largest gap terms) on homopolymers with full windows
-    (the largest values) and on mixed reads."""
+    its range, tag width 4, large gap terms, the largest row offsets at the top of
+    tag width 4) on homopolymers with full windows (the largest values) and on
+    mixed reads."""
     import dataclasses
     for seed, homo in ((23, True), (24, False)):
         b = wl.random_small_batch(seed, n_reads=150, read_len=(1, mrl), ref_len=(400, 1500), band=12,

@@ -157,19 +157,21 @@ def test_half_max_order_on_device():
     assert sw.check_half_max() == 0
 
 
-# The int16 sweep keeps (V + beta) * 2^K + tag in each half, beta covering the
-# largest single penalty (|mismatch|, gap_open + gap_extend + 1, 256 / 2^K) and K
-# the widest of 6, 5, 4 with (beta + match * max_read_len + 1) * 2^K <= 0x7BFF.
-# Each case sits at an edge of that layout: values at the top of the range,
-# each term setting beta, and each tag width.
+# The int16 sweep keeps (V + beta) * 2^K + tag in each half, plus r * gap_extend *
+# 2^K on row r of a strip (at most 50 rows), beta covering the largest single
+# penalty (|mismatch|, gap_open + gap_extend + 1, 256 / 2^K + gap_extend) and K the
+# widest of 6, 5, 4 with (beta + match * max_read_len + 1 + 49 * gap_extend) * 2^K
+# <= 0x7BFF.  Each case sits at an edge of that layout: values at the top of the
+# range, each term setting beta, and each tag width.
 TAG_EDGES = [
     # (match, mismatch, gap_open, gap_extend, max_read_len, read lengths): K, beta
-    ((2, -3, 5, 2), 243, (200, 243)),     # K 6, beta 8: (8 + 486 + 1) * 64 = 31680, just inside
-    ((2, -3, 5, 2), 244, (200, 244)),     # K 5 from one base more
+    ((2, -3, 5, 2), 194, (150, 194)),     # K 6, beta 8: (8 + 388 + 1 + 98) * 64 = 31680, just inside
+    ((2, -3, 5, 2), 195, (150, 195)),     # K 5 from one base more (beta 10 from the padding rows)
     ((2, -500, 5, 2), 250, (150, 250)),   # K 4, beta from the mismatch
-    ((1, -1, 300, 100), 80, (1, 80)),     # K 6, beta 401 from the gap terms
+    ((1, -1, 300, 2), 80, (1, 80)),       # K 6, beta 303 from the gap terms
     ((1, -400, 0, 1), 100, (1, 100)),     # K 5, beta 400 from the mismatch, no gap opening
-    ((3, -1, 1, 1), 150, (100, 150)),     # K 6, beta 4 from the padding rows
+    ((3, -1, 1, 1), 146, (100, 146)),     # K 6, beta 5 from the padding rows: (5 + 438 + 1 + 49) * 64 = 31552
+    ((3, -1, 10, 29), 170, (150, 170)),   # K 4, beta 45, row offsets up to 49 * 29: (45 + 510 + 1 + 1421) * 16 = 31632
 ]
 
 

@@ -8,9 +8,11 @@ runs the same sweep on the CPU, lane by lane (numpy over the 64 lanes of a
 tile): 16-bit wrapping adds and subtracts, the signed 16-bit maximum, and a
 three-way maximum that asserts every operand lies in that domain before
 ranking it.  It uses the layout rules the library states (the widest K of 6, 5,
-4 with (beta + top + 1) * 2^K <= 0x7BFF, beta = max(|mismatch|, gap_open +
-gap_extend + 1, 256 / 2^K), chosen per tile from its longest read), strips of R
-rows handed over column by column, the tile folds and re-bases, padding rows
+4 with (beta + top + 1 + 49 * gap_extend) * 2^K <= 0x7BFF, beta = max(|mismatch|,
+gap_open + gap_extend + 1, 256 / 2^K + gap_extend), chosen per tile from its
+longest read), row r of a strip offset by r * gap_extend * 2^K (so that F moves
+down a row with no gap-extend step), strips of R rows handed over column by
+column at offset 0, the tile folds (offsets removed) and re-bases, padding rows
 and wall columns, and compares every slot with the oracle.
 """
 import dataclasses
@@ -24,11 +26,15 @@ from paper_1805_00106_amd import workloads as wl
 M16 = 0xFFFF
 
 
-def _layout(match, mismatch, goe, top):
+ROW_OFFSET_ROWS = 49   # a strip holds at most 50 rows: row r of a strip carries r * gap_extend
+
+
+def _layout(match, mismatch, goe, ge, top):
     for k in (6, 5, 4):
         u = 1 << k
-        beta = max(-mismatch, goe + 1, (256 + u - 1) // u)
-        if (beta + top + 1) * u <= 0x7BFF:
+        # the padding rows' substitution (-256) on the row handed over as H - GF
+        beta = max(-mismatch, goe + 1, (256 + u - 1) // u + ge)
+        if (beta + top + 1 + ROW_OFFSET_ROWS * ge) * u <= 0x7BFF:
             return k, beta
     return None
 
@@ -65,10 +71,11 @@ def _tile(reads, wins, sc, R):
     W = np.array([len(w) for w in wins])
     Lmax, Wmax = int(L.max()), int(W.max())
     goe, ge = sc.gap_open + sc.gap_extend, sc.gap_extend
-    K, beta = _layout(sc.match, sc.mismatch, goe, sc.match * Lmax)
+    K, beta = _layout(sc.match, sc.mismatch, goe, ge, sc.match * Lmax)
     U, B = 1 << K, beta << K
-    GOE_E, GE_E, GOE_F, GE_F = goe * U + 1, ge * U + 1, goe * U, ge * U
-    SM, SX = (sc.match * U - 1) & M16, (sc.mismatch * U - 1) & M16
+    GOE_E, GE_E, GO_F, GF = goe * U + 1, ge * U + 1, (goe - ge) * U, ge * U
+    # a diagonal move goes one row down: the substitution carries the row step GF
+    SM, SX = (sc.match * U - 1 + GF) & M16, (sc.mismatch * U - 1 + GF) & M16
     q = np.full((n, Lmax), -1, np.int64)
     for l, rd in enumerate(reads):
         q[l, :len(rd)] = rd
@@ -81,16 +88,19 @@ def _tile(reads, wins, sc, R):
     nstrips = (Lmax + R - 1) // R
     for s in range(nstrips):
         r0 = s * R
-        Hl = np.full((R, n), U + B, np.int64)
-        E = np.full((R, n), U + B - 1, np.int64)
+        # strip row r carries + r * GF (so F needs no gap-extend step); the rows
+        # above the strip are handed over as H - GF and F at offset 0
+        off = np.arange(R, dtype=np.int64)[:, None] * GF
+        Hl = np.full((R, n), U + B, np.int64) + off
+        E = np.full((R, n), U + B - 1, np.int64) + off
         M = np.zeros((R, n), np.int64)
-        hup_prev = np.full(n, U + B, np.int64)
+        hup_prev = np.full(n, U + B - GF, np.int64)
         for tb in range(0, Wmax, U):
             for c in range(tb, min(tb + U, Wmax)):
                 zt = U - 1 - (c - tb) + B
                 if s == 0:
-                    hup = np.full(n, zt, np.int64)
-                    F = np.full(n, (zt - GOE_F) & M16, np.int64)
+                    hup = np.full(n, zt - GF, np.int64)
+                    F = np.full(n, (zt - GO_F - GF) & M16, np.int64)
                 else:
                     hup, F = scr_h[c].copy(), scr_f[c].copy()
 
@@ -108,14 +118,14 @@ def _tile(reads, wins, sc, R):
                     tn = (Hl[r] + sub(r + 1)) & M16 if r + 1 < R else None
                     H = _hmax3(t, E[r], F)
                     t = tn
-                    f2, e2 = (F - GE_F) & M16, (E[r] - GE_E) & M16
-                    v, u = (H - GOE_F) & M16, (H - GOE_E) & M16
-                    F = _imax(f2, v)
-                    E[r] = _hmax3(e2, u, zt - 1)
+                    e2, u = (E[r] - GE_E) & M16, (H - GOE_E) & M16
+                    F = _imax(F, (H - GO_F) & M16)
+                    E[r] = _hmax3(e2, u, zt - 1 + r * GF)
                     M[r] = _imax(M[r], H)
                     Hl[r] = H
-                scr_h[c], scr_f[c] = Hl[R - 1], F
+                scr_h[c], scr_f[c] = (Hl[R - 1] - R * GF) & M16, (F - R * GF) & M16
             # fold: best value per lane, its smallest column (largest tag), then smallest row
+            M = (M - off) & M16
             mx = M.max(axis=0)
             V = (mx >> K) - beta
             col = tb + (U - 1) - (mx & (U - 1))
@@ -165,15 +175,32 @@ def _model(batch, R):
 
 
 CASES = [
-    # scoring, read lengths, strip rows: K 6 at the top of its range, K 5, K 4,
-    # large gap terms, beta from the padding rows, several strips per read
-    ((2, -3, 5, 2), (230, 243), 50),
-    ((2, -3, 5, 2), (240, 244), 50),
+    # scoring, read lengths, strip rows: K 6 at the top of its range
+    # ((8 + 388 + 1 + 98) * 64 = 31680), K 5 from one base more, K 4 with beta from
+    # the mismatch, beta from the gap terms, a large gap extension (row offsets of
+    # up to 49 * 29) at the top of K 4, beta from the padding rows at the top of
+    # K 6, several strips per read
+    ((2, -3, 5, 2), (185, 194), 50),
+    ((2, -3, 5, 2), (190, 195), 50),
     ((2, -500, 5, 2), (240, 250), 50),
-    ((1, -1, 300, 100), (40, 80), 24),
-    ((3, -1, 1, 1), (100, 150), 34),
+    ((1, -1, 300, 2), (40, 80), 24),
+    ((3, -1, 10, 29), (150, 170), 50),
+    ((3, -1, 1, 1), (100, 146), 34),
     ((2, -3, 5, 2), (1, 60), 24),
 ]
+
+
+def test_int16_layout_rule():
+    """Tag width and bias from the rule, at its edges; no int16 layout for a gap
+    extension whose row offsets leave no room."""
+    assert _layout(2, -3, 7, 2, 2 * 194) == (6, 8)
+    assert _layout(2, -3, 7, 2, 2 * 195) == (5, 10)
+    assert _layout(2, -500, 7, 2, 500) == (4, 500)
+    assert _layout(1, -1, 302, 2, 80) == (6, 303)
+    assert _layout(3, -1, 39, 29, 510) == (4, 45)
+    assert _layout(3, -1, 2, 1, 3 * 146) == (6, 5)
+    assert _layout(3, -1, 2, 1, 3 * 147) == (5, 9)
+    assert _layout(1, -1, 400, 100, 80) is None
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-L{c[1][1]}-R{c[2]}" for c in CASES])
