@@ -48,7 +48,10 @@ typedef struct ihipStream_t *sw_stream_t; /* a hipStream_t */
 /* ------------------------------------------------------------------ codes */
 #define SW_OK 0
 #define SW_ERR_INVALID_ARG (-1)   /* null pointer, negative count, bad enum */
-#define SW_ERR_SCORING (-2)       /* scoring parameters outside the supported range */
+#define SW_ERR_SCORING (-2)       /* scoring parameters outside the supported range: match >= 1,
+                                     mismatch <= 0, gap_open >= 0, gap_extend >= 1,
+                                     match * max_read_len + 49 * gap_extend <= 2^19 - 2,
+                                     -mismatch <= 2^18, gap_open + 2 * gap_extend <= 2^18 */
 #define SW_ERR_READ_TOO_LONG (-3) /* max_read_len above SW_MAX_READ_LEN */
 #define SW_ERR_BOUND (-4)         /* int16 requested but the score bound does not hold */
 #define SW_ERR_WORKSPACE (-5)     /* workspace missing or smaller than sw_workspace_bytes() */

@@ -39,9 +39,12 @@ int validate_scoring(const sw_scoring_t *sc, ScoreMode *mode) {
   if (mrl < 1) return SW_ERR_INVALID_ARG;
   if (mrl > SW_MAX_READ_LEN) return SW_ERR_READ_TOO_LONG;
   const int64_t goe2 = (int64_t)sc->gap_open + 2 * (int64_t)sc->gap_extend;
-  // int32 path: values are V * 4096 + tag with |V| < 2^19
+  // int32 path: values are V * 4096 + tag with |V| < 2^19, plus the row offsets
+  // of the one-CAL-per-lane sweep (up to 49 * gap_extend)
   const int64_t top = (int64_t)sc->match * mrl;
-  if (top > (1 << 19) - 2 || -(int64_t)sc->mismatch > (1 << 18) || goe2 > (1 << 18)) return SW_ERR_SCORING;
+  if (top + 49 * (int64_t)sc->gap_extend > (1 << 19) - 2 || -(int64_t)sc->mismatch > (1 << 18) ||
+      goe2 > (1 << 18))
+    return SW_ERR_SCORING;
   // int16 path: biased values with K tag bits and per-row offsets (DpConst) in
   // int16; the bound needs V <= 510 everywhere and a tag width that holds them
   int32_t kb = 0, beta = 0;
@@ -91,10 +94,13 @@ DpConstHost make_consts(const sw_scoring_t *sc) {
   k.ge_f32 = ge * 4096;
   k.sm32 = sc->match * 4096 - 1;
   k.sx32 = sc->mismatch * 4096 - 1;
-  k.perm32 = sc->match <= 16 && sc->mismatch >= -15 ? 1 : 0;
+  // the one-CAL-per-lane int32 sweep adds the row step gap_extend * 4096 to every
+  // diagonal move: its byte tables hold (s + gap_extend) * 4096 - 1
+  k.perm32 = sc->match + ge <= 16 && sc->mismatch + ge >= -15 ? 1 : 0;
   if (k.perm32) {
-    const uint32_t m1 = ((uint32_t)k.sm32 >> 8) & 0xFFu, x1 = ((uint32_t)k.sx32 >> 8) & 0xFFu;
-    const uint32_t m2 = ((uint32_t)k.sm32 >> 16) & 0xFFu, x2 = ((uint32_t)k.sx32 >> 16) & 0xFFu;
+    const uint32_t smr = (uint32_t)(k.sm32 + k.ge_f32), sxr = (uint32_t)(k.sx32 + k.ge_f32);
+    const uint32_t m1 = (smr >> 8) & 0xFFu, x1 = (sxr >> 8) & 0xFFu;
+    const uint32_t m2 = (smr >> 16) & 0xFFu, x2 = (sxr >> 16) & 0xFFu;
     k.xlo32 = x1 * 0x01010101u;
     k.dlo32 = x1 ^ m1;
     k.xhi32 = x2 * 0x01010101u;

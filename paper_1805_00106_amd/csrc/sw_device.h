@@ -58,10 +58,12 @@ struct DpConst {
   int32_t match, mismatch, goe, ge;  // the scoring (goe = gap_open + gap_extend)
   // int32 (K = 12)
   int32_t goe_e32, ge_e32, goe_f32, ge_f32, sm32, sx32, e0_32;
-  // int32 substitution by byte permutation, usable when match <= 16 and
-  // mismatch >= -15: s * 4096 - 1 is then 0xFF in byte 0, a score-dependent
-  // byte 1 and the sign in bytes 2 and 3, so a table of byte 1 (low word) and of
-  // the sign byte (high word) per base yields it with one v_perm_b32
+  // int32 substitution by byte permutation in the one-CAL-per-lane sweep, whose
+  // diagonal moves also carry the row step gap_extend * 4096: usable when s' = s +
+  // gap_extend lies in [-15, 16] for both scores.  s' * 4096 - 1 is then 0xFF in
+  // byte 0, a score-dependent byte 1 and the sign in bytes 2 and 3, so a table of
+  // byte 1 (low word) and of the sign byte (high word) per base yields it with one
+  // v_perm_b32
   int32_t perm32;
   uint32_t xlo32, dlo32, xhi32, dhi32;
   // 1: only the last read row may hold the best cell (read-end-anchored scoring)

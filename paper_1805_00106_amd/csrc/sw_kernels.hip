@@ -586,6 +586,12 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
   stage(A, rt_off, rt_len, t, (Lmax + 15) >> 4, (Wmax + 15) >> 4, rdw, win, lane);
 
   uint64_t best = 0;
+  // Row r of a strip carries + r * GF, as in strip16: F moves down a row with no
+  // gap-extend step, a diagonal move carries + GF in its substitution (in the
+  // byte tables with P), and the rows above and below a strip are handed over at
+  // offset 0 (H as H - GF).
+  const int32_t GF = K.ge_f32, GO_F = K.goe_f32 - K.ge_f32;
+  const int32_t SMR = K.sm32 + GF, SXR = K.sx32 + GF;
   const int nstrips = (Lmax + R - 1) / R;
   for (int s = 0; s < nstrips; ++s) {
     const int r0 = s * R;
@@ -593,6 +599,8 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
     // (0xFF, table byte q, sign byte q, sign byte q); past the read end a code
     // that never equals a window code, or the selector of 0xFFFF00FF (about -16 per row)
     int32_t q[R], Hl[R], E[R], M[R];
+    // column -1 (H = 0, tag 4096) on row r, formed row by row (see strip16)
+    uint32_t h0 = 4096;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = r0 + r;
@@ -602,11 +610,12 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       } else {
         q[r] = P ? 0x0D0D0C0D : 4;
       }
-      Hl[r] = 4096;
-      E[r] = 4095;  // E is kept clamped at zero: column 0 starts at its zero
+      Hl[r] = (int32_t)h0;
+      E[r] = (int32_t)h0 - 1;  // E is kept clamped at zero: column 0 starts at its zero
       M[r] = 0;
+      h0 = opaque_s(h0 + (uint32_t)GF);
     }
-    int32_t hup_prev = 4096;
+    int32_t hup_prev = 4096 - GF;
     uint2 pf0 = make_uint2(0, 0), pf1 = make_uint2(0, 0);
     if (s > 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -620,7 +629,7 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       int32_t w = (int32_t)((wd >> (2 * (c & 15))) & 3u);
       // past the lane's window: a wall (no diagonal move enters these columns, so
       // no cell there can beat a real cell of its row, which the final-row mode needs)
-      int32_t sx = K.sx32;
+      int32_t sx = SXR;
       uint32_t tlo = 0, thi = 0;
       if (P) {
         const uint32_t sh8 = (uint32_t)w << 3;
@@ -636,7 +645,7 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       }
       int32_t hup, F;
       if (s == 0) {
-        hup = zt;
+        hup = zt - GF;
         F = zt - K.goe_f32;
       } else {
         const uint2 cur = pf0;
@@ -649,10 +658,11 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
       // and the clamp moves into E's own three-way maximum (with the next
       // column's zero, tag one lower)
       auto subst = [&](int32_t qr) {
-        return P ? (int32_t)__builtin_amdgcn_perm(thi, tlo, (uint32_t)qr) : (qr == w ? K.sm32 : sx);
+        return P ? (int32_t)__builtin_amdgcn_perm(thi, tlo, (uint32_t)qr) : (qr == w ? SMR : sx);
       };
       int32_t t = hup_prev + subst(q[0]);
       hup_prev = hup;
+      uint32_t zr = (uint32_t)(zt - 1);  // the zero of the next column on row r
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         // the diagonal of row r+1 is row r's previous H: consume it before row r's
@@ -662,18 +672,23 @@ __device__ __forceinline__ void tile32(const AlignArgs &A, const int64_t *rt_off
         const int32_t H = max(max(t, E[r]), F);
         t = tn;
         M[r] = max(M[r], H);
-        E[r] = max(max(E[r] - K.ge_e32, H - K.goe_e32), zt - 1);
-        F = max(F - K.ge_f32, H - K.goe_f32);
+        E[r] = max(max(E[r] - K.ge_e32, H - K.goe_e32), (int32_t)zr);
+        zr = opaque_s(zr + (uint32_t)GF);
+        F = max(F, H - GO_F);
         Hl[r] = H;
       }
-      if (s + 1 < nstrips) scr[c * 64 + lane] = make_uint2((uint32_t)Hl[R - 1], (uint32_t)F);
+      if (s + 1 < nstrips)
+        scr[c * 64 + lane] = make_uint2((uint32_t)(Hl[R - 1] - R * GF), (uint32_t)(F - R * GF));
     }
+    uint32_t off = 0;  // row r's offset
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = r0 + r;
-      int32_t v = M[r] >> 12;
+      const int32_t m = M[r] - (int32_t)off;
+      off = opaque_s(off + (uint32_t)GF);
+      int32_t v = m >> 12;
       if (i < L && v > 0 && (!K.final_row || i == L - 1)) {
-        uint64_t kk = cell_key(v, 4095 - (M[r] & 4095), i);
+        uint64_t kk = cell_key(v, 4095 - (m & 4095), i);
         best = kk > best ? kk : best;
       }
     }

@@ -72,6 +72,14 @@ def test_scoring_validation(sw, field, value, code):
     assert _call(sw, sc) == code
 
 
+def test_int32_range_includes_row_offsets(sw):
+    """match * max_read_len + 49 * gap_extend <= 2^19 - 2 (the int32 sweep's row offsets)."""
+    for (m, ge, mrl), code in (((511, 20, 1024), -5), ((511, 21, 1024), -2), ((1, 10699, 1), -5),
+                               ((1, 10700, 1), -2)):
+        sc = sw.Scoring.make(m, -1, 0, ge, 8, sw.PREC_INT32, max_read_len=mrl)
+        assert _call(sw, sc) == code, (m, ge, mrl)
+
+
 def test_null_scoring_is_invalid(sw):
     assert _call(sw, None) == -1
 

@@ -200,6 +200,39 @@ def test_int16_tag_width_and_bias_edges(edge, mode):
             assert int(exp["score"].max()) == m * int(b.read_len[has_cal].max())
 
 
+# The int32 one-CAL-per-lane sweep holds V * 4096 + tag plus r * gap_extend * 4096
+# on row r of a strip (match * max_read_len + 49 * gap_extend <= 2^19 - 2), and its
+# substitution is one byte permutation when s + gap_extend lies in [-15, 16] for
+# both scores, else a compare and select.
+INT32_EDGES = [
+    ((14, -3, 5, 2), 60, (1, 60)),          # match + ge = 16: byte permutation at its top
+    ((15, -3, 5, 2), 60, (1, 60)),          # 17: compare and select
+    ((2, -17, 5, 2), 60, (1, 60)),          # mismatch + ge = -15: byte permutation at its bottom
+    ((2, -18, 5, 2), 60, (1, 60)),          # -16: compare and select
+    ((511, -3, 5, 20), 1024, (900, 1024)),  # top of the range: 511 * 1024 + 49 * 20 = 524244
+]
+
+
+@pytest.mark.parametrize("mode", [sw.MODE_LOCAL, sw.MODE_FINAL_ROW])
+@pytest.mark.parametrize("edge", INT32_EDGES, ids=[f"{e[0]}-L{e[1]}" for e in INT32_EDGES])
+def test_int32_range_and_substitution_edges(edge, mode):
+    (m, x, go, ge), mrl, lens = edge
+    sc = wl.Scoring(m, x, go, ge, 12)
+    for seed, homo in ((25, True), (26, False)):
+        b = wl.random_small_batch(seed, n_reads=20, read_len=lens, ref_len=(1200, 3000), band=12,
+                                  homopolymer=homo)
+        b = dataclasses.replace(b, scoring=sc)
+        if homo:
+            b = dataclasses.replace(b, cal_pos=np.full_like(b.cal_pos, 12), strand=np.full_like(b.strand, 3))
+        exp, _ = oracle_align(b, mode=mode)
+        for kernel in (sw.KERNEL_INTER, sw.KERNEL_INTRA):
+            got = gpu_align(b, sw.PREC_INT32, kernel=kernel, max_read_len=mrl, mode=mode)
+            assert_same(got, exp, f"{edge} homopolymer={homo} mode={mode} kernel={kernel}")
+        if homo:
+            has_cal = np.diff(b.cal_ptr) > 0
+            assert int(exp["score"].max()) == m * int(b.read_len[has_cal].max())
+
+
 def test_empty_inputs():
     """No CALs at all, and reads without CALs: calls succeed and touch nothing."""
     b = wl.random_small_batch(19, n_reads=5, max_cals=0)
