@@ -664,7 +664,9 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
     # saturated throughput: the whole pool queued at once
     for b in pool[:8]:  # warm-up
         srv.wait(srv.submit_batch(b))
-    rounds = 3  # the pool three times over, so ramp-up and drain are a small part
+    # the pool eight times over (about 8.5 M reads, some 130 steps), so the pipeline's
+    # ramp-up and drain (two or three steps) are a small part of the window
+    rounds = 8
     preps = [srv.prepare_batch(b) for _ in range(rounds) for b in pool]
     n_clients = 4  # client threads submitting at once (the library calls release the GIL)
     hs = [None] * len(preps)

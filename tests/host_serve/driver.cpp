@@ -333,7 +333,7 @@ int main(int argc, char **argv) {
   if (argc > 1 && std::string(argv[1]) == "bench") {
     const uint64_t seed = argc > 2 ? strtoull(argv[2], nullptr, 10) : 1;
     const int pool_size = argc > 3 ? atoi(argv[3]) : 300;
-    const int rounds = argc > 4 ? atoi(argv[4]) : 3;
+    const int rounds = argc > 4 ? atoi(argv[4]) : 8;
     const int per_load = argc > 5 ? atoi(argv[5]) : 2000;
     return run_bench(seed, pool_size, rounds, per_load);
   }

@@ -16,7 +16,8 @@ waits, arena blocks reused, requests split over steps, both scoring paths), with
 read layouts that are tight, gapped and shuffled, or arbitrary; and the served
 benchmark's own configuration is replayed (4 GiB budget, 1024 chunks, 65536
 reads and 1 M CALs per step, 3.2 and 2.7 Gbp references, a 300-request pool
-submitted three times from four client threads, then three Poisson load phases
+submitted three times from four client threads (the benchmark submits it eight
+times; the number of rounds changes no code path), then three Poisson load phases
 with waits, timestamps and releases).  Every output must belong to its own
 request, read, CAL and strand.  Built with the host address and
 undefined-behaviour sanitizers (and the thread sanitizer where ROCm's clang
