@@ -217,7 +217,8 @@ int make_plan(int64_t n_cals, const sw_scoring_t *sc, int strip_override, PlainP
   const int64_t n_tiles = (p->n_tasks + 63) / 64;
   const int64_t resident = (int64_t)cus * blocks_per_cu(m.int16, p->strip_rows);
   p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, resident));
-  p->bytes = p->scratch_off + (size_t)p->grid * (size_t)m.wcap * 64 * sizeof(uint2);
+  p->queue_off = p->scratch_off + (size_t)p->grid * (size_t)m.wcap * 64 * sizeof(uint2);
+  p->bytes = p->queue_off + 256;
   return SW_OK;
 }
 
@@ -283,6 +284,14 @@ int run_plain(const PlainPlan &plan, const swk::RefTable &T, const uint32_t *rea
   A.band = sc->band;
   A.strip_rows = plan.strip_rows;
   A.k = make_consts(sc);
+  if (!plan.intra) {
+    // tiles are popped from a counter rather than dealt by block index, so that a
+    // block that finishes early takes the next tile (cleared by a kernel, not a
+    // memset, so that a caller may capture the call in a graph)
+    A.queue = (int32_t *)(ws + plan.queue_off);
+    e = swk::launch_fill_i32(A.queue, 1, 0, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   e = plan.intra ? swk::launch_intra(plan.mode.int16, A, T, plan.grid, st)
                  : swk::launch_inter(plan.mode.int16, A, T, plan.grid, st);
   if (e != hipSuccess) return hip_fail(e);

@@ -25,6 +25,7 @@ struct PlainPlan {
   int wwords, rwords;
   int grid;
   size_t cal_read_off, scratch_off, bytes;
+  size_t queue_off;  // one CAL per lane: the tile counter the blocks pop from (zeroed per call)
 };
 
 typedef swk::DpConst DpConstHost;

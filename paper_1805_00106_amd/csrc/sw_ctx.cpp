@@ -20,6 +20,7 @@ namespace {
 // One batched plan: how tasks are binned and ordered, which strip height each
 // bin takes, and how many persistent blocks pop the queue.
 struct TunedPlan {
+  int unbinned = 0;       // 1: no bins, tasks in input order, one strip height (the plain kernel)
   int bin_width = 4;
   int descending = 1;
   int strip_cap = 0;      // tallest strip height a bin may take (0: any)
@@ -79,16 +80,17 @@ void load_tune_cache(sw_ctx *c) {
   if (!f) return;
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
-    // one entry per line: "key": {"bin_width": N, "descending": N, "strip_cap": N,
-    // "strip_slack": N, "grid_quarters": N, "ms": X}
+    // one entry per line: "key": {"unbinned": N, "bin_width": N, "descending": N,
+    // "strip_cap": N, "strip_slack": N, "grid_quarters": N, "ms": X}
     char key[256];
     TunedPlan p;
     if (std::sscanf(line,
-                    " \"%255[^\"]\": {\"bin_width\": %d, \"descending\": %d, \"strip_cap\": %d, "
-                    "\"strip_slack\": %d, \"grid_quarters\": %d, \"ms\": %f",
-                    key, &p.bin_width, &p.descending, &p.strip_cap, &p.strip_slack, &p.grid_quarters, &p.ms) == 7 &&
-        p.bin_width >= 1 && p.bin_width <= SW_MAX_READ_LEN && p.grid_quarters >= 1 && p.grid_quarters <= 4 &&
-        p.strip_cap >= 0 && p.strip_slack >= 0)
+                    " \"%255[^\"]\": {\"unbinned\": %d, \"bin_width\": %d, \"descending\": %d, "
+                    "\"strip_cap\": %d, \"strip_slack\": %d, \"grid_quarters\": %d, \"ms\": %f",
+                    key, &p.unbinned, &p.bin_width, &p.descending, &p.strip_cap, &p.strip_slack, &p.grid_quarters,
+                    &p.ms) == 8 &&
+        (p.unbinned == 0 || p.unbinned == 1) && p.bin_width >= 1 && p.bin_width <= SW_MAX_READ_LEN &&
+        p.grid_quarters >= 1 && p.grid_quarters <= 4 && p.strip_cap >= 0 && p.strip_slack >= 0)
       c->tuned[key] = p;
   }
   std::fclose(f);
@@ -103,9 +105,10 @@ void save_tune_cache(const sw_ctx *c) {
   for (const auto &kv : c->tuned) {
     const TunedPlan &t = kv.second;
     std::fprintf(f,
-                 "  \"%s\": {\"bin_width\": %d, \"descending\": %d, \"strip_cap\": %d, \"strip_slack\": %d, "
-                 "\"grid_quarters\": %d, \"ms\": %.4f}%s\n",
-                 kv.first.c_str(), t.bin_width, t.descending, t.strip_cap, t.strip_slack, t.grid_quarters, t.ms,
+                 "  \"%s\": {\"unbinned\": %d, \"bin_width\": %d, \"descending\": %d, \"strip_cap\": %d, "
+                 "\"strip_slack\": %d, \"grid_quarters\": %d, \"ms\": %.4f}%s\n",
+                 kv.first.c_str(), t.unbinned, t.bin_width, t.descending, t.strip_cap, t.strip_slack,
+                 t.grid_quarters, t.ms,
                  ++i < c->tuned.size() ? "," : "");
   }
   std::fprintf(f, "}\n");
@@ -182,8 +185,12 @@ int enqueue(sw_ctx *c, const CallArgs &a, const swapi::ScoreMode &m, const swk::
   if (e != hipSuccess) return swapi::hip_fail(e);
   e = swk::launch_expand(a.cal_ptr, a.n_reads, a.n_cals, c->B.cal_read, st);
   if (e != hipSuccess) return swapi::hip_fail(e);
-  const swk::BinParams P = bin_params(m, t);
-  e = swk::launch_batch_plan(c->B, a.read_len, a.n_reads, n_tasks, P, st);
+  if (!t.unbinned) {
+    const swk::BinParams P = bin_params(m, t);
+    e = swk::launch_batch_plan(c->B, a.read_len, a.n_reads, n_tasks, P, st);
+  } else {
+    e = swk::launch_fill_i32(c->B.queue, 1, 0, st);  // the tile counter, in input order
+  }
   if (e != hipSuccess) return swapi::hip_fail(e);
   swk::AlignArgs A{};
   A.reads = a.reads2bit;
@@ -216,20 +223,31 @@ int enqueue(sw_ctx *c, const CallArgs &a, const swapi::ScoreMode &m, const swk::
   A.band = a.sc->band;
   A.strip_rows = 0;
   A.k = swapi::make_consts(a.sc);
-  e = swk::launch_inter_queue(m.int16, A, T, grid, st);
+  if (t.unbinned) {
+    // the plain kernel, its tiles 64 consecutive tasks popped from the counter
+    A.order = nullptr;
+    A.tiles = nullptr;
+    A.tile_len = nullptr;
+    A.tile_strips = nullptr;
+    A.n_tiles_dev = nullptr;
+    A.strip_rows = swapi::choose_strip_rows(m.int16, m.max_read_len);
+    e = swk::launch_inter(m.int16, A, T, grid, st);
+  } else {
+    e = swk::launch_inter_queue(m.int16, A, T, grid, st);
+  }
   if (e != hipSuccess) return swapi::hip_fail(e);
   return SW_OK;
 }
 
 std::string graph_key(const CallArgs &a, const swapi::ScoreMode &m, const TunedPlan &t, int grid) {
   char k[1024];
-  std::snprintf(k, sizeof k, "%p %p %p %d %p %d %p %p %p %p %p %lld %d %d %d %d %d %d %p %p %p %d %d %d %d %d %d %d",
+  std::snprintf(k, sizeof k, "%p %p %p %d %p %d %p %p %p %p %p %lld %d %d %d %d %d %d %p %p %p %d %d %d %d %d %d %d %d",
                 (const void *)a.reads2bit, (const void *)a.read_word_off, (const void *)a.read_len, a.n_reads,
                 (const void *)a.refs->words, a.refs->n_refs, (const void *)a.cal_ptr, (const void *)a.cal_pos,
                 (const void *)a.cal_ref, (const void *)a.strand, (const void *)a.score, (long long)a.n_cals,
                 a.sc->match, a.sc->mismatch, a.sc->gap_open, a.sc->gap_extend, a.sc->band, m.max_read_len,
                 (const void *)a.ref_end, (const void *)a.read_end, (const void *)nullptr, (int)m.int16, t.bin_width,
-                t.descending, grid, a.sc->mode, t.strip_cap, t.strip_slack);
+                t.descending, grid, a.sc->mode, t.strip_cap, t.strip_slack, t.unbinned);
   std::string s(k);
   for (int i = 0; i < a.refs->n_refs; ++i) {
     char r[64];
@@ -417,9 +435,16 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
           cand.descending = d;
           if ((rc = time_plan(cand))) return rc;
         }
+      {
+        // no bins: where the reads have one length, binning only reorders
+        TunedPlan cand;
+        cand.unbinned = 1;
+        if ((rc = time_plan(cand))) return rc;
+      }
       const TunedPlan base = best;
       const int strip_policies[][2] = {{0, 8}, {0, 16}, {0, 32}, {40, 0}, {44, 0}};
       for (const auto &sp : strip_policies) {
+        if (base.unbinned) break;  // the strip policies shape the bins
         TunedPlan cand = base;
         cand.strip_cap = sp[0];
         cand.strip_slack = sp[1];
@@ -486,15 +511,23 @@ int sw_align_batch_ctx(sw_ctx_t *c, const uint32_t *reads2bit, const int64_t *re
     if (rc) return rc;
   }
   char desc[320];
-  std::snprintf(desc, sizeof desc,
-                "%s tasks=%lld bins=%d(width %d, %s) strips(cap %d, slack %d) grid=%d(%d/4) graph=%s tuned=%s(%.3f ms",
-                m.int16 ? "int16-pairs" : "int32", (long long)n_tasks, (m.max_read_len + plan.bin_width - 1) / plan.bin_width,
-                plan.bin_width, plan.descending ? "longest first" : "shortest first", plan.strip_cap, plan.strip_slack,
-                grid, plan.grid_quarters, c->use_graph ? (graph_hit ? "replay" : "captured") : "off",
-                tuned_now ? "now" : "cached", plan.ms);
+  const int unbinned_rows = swapi::choose_strip_rows(m.int16, m.max_read_len);
+  if (plan.unbinned)
+    std::snprintf(desc, sizeof desc, "%s tasks=%lld unbinned(input order) grid=%d(%d/4) graph=%s tuned=%s(%.3f ms",
+                  m.int16 ? "int16-pairs" : "int32", (long long)n_tasks, grid, plan.grid_quarters,
+                  c->use_graph ? (graph_hit ? "replay" : "captured") : "off", tuned_now ? "now" : "cached", plan.ms);
+  else
+    std::snprintf(desc, sizeof desc,
+                  "%s tasks=%lld bins=%d(width %d, %s) strips(cap %d, slack %d) grid=%d(%d/4) graph=%s tuned=%s(%.3f ms",
+                  m.int16 ? "int16-pairs" : "int32", (long long)n_tasks,
+                  (m.max_read_len + plan.bin_width - 1) / plan.bin_width, plan.bin_width,
+                  plan.descending ? "longest first" : "shortest first", plan.strip_cap, plan.strip_slack, grid,
+                  plan.grid_quarters, c->use_graph ? (graph_hit ? "replay" : "captured") : "off",
+                  tuned_now ? "now" : "cached", plan.ms);
   c->last_plan = desc;
   if (tuned_now) c->last_plan += ", " + std::to_string(n_tried) + " plans";
-  c->last_plan += ") heights " + plan_heights(bin_params(m, plan));
+  c->last_plan += ") heights " + (plan.unbinned ? "1-" + std::to_string(m.max_read_len) + ":" + std::to_string(unbinned_rows)
+                                                : plan_heights(bin_params(m, plan)));
   return SW_OK;
 }
 

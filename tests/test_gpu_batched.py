@@ -57,7 +57,8 @@ def test_ctx_uneven_lengths_shape(band):
     res, plan = _ctx_run(b, sw.PREC_INT16, max_read_len=250, repeats=2)
     for r in res:
         assert_same(r, exp, f"uneven_lengths band {band} ({plan})", keys=SLOTS)
-    assert "longest first" in plan or "shortest first" in plan
+    # the tuner's pick: bins in either order, or input order without bins
+    assert "longest first" in plan or "shortest first" in plan or "unbinned" in plan, plan
 
 
 def test_ctx_equals_plain_on_chromosome_scale_shape():
@@ -116,7 +117,7 @@ def test_ctx_shapes_change_and_graph_cache(tmp_path):
     assert all("replay" in p for p in plans[3:]), plans
     with open(cache) as f:
         tuned = json.load(f)
-    fields = ("bin_width", "descending", "strip_cap", "strip_slack", "grid_quarters", "ms")
+    fields = ("unbinned", "bin_width", "descending", "strip_cap", "strip_slack", "grid_quarters", "ms")
     assert tuned and all(all(f in v for f in fields) for v in tuned.values())
     # the plan names the strip height each length range takes and how many plans were timed
     assert "heights 1-" in plans[0] and " plans)" in plans[0], plans[0]
@@ -149,3 +150,31 @@ def test_ctx_int16_tag_width_and_bias_edges(scoring, mrl):
         for r in res:
             assert_same(r, exp, f"{scoring} mrl {mrl} homopolymer={homo} ({plan})", keys=SLOTS)
         assert plan.startswith("int16-pairs")
+
+
+@pytest.mark.parametrize("precision,mode", [(sw.PREC_INT16, sw.MODE_LOCAL), (sw.PREC_INT16, sw.MODE_FINAL_ROW),
+                                            (sw.PREC_INT32, sw.MODE_LOCAL)])
+def test_ctx_unbinned_plan(tmp_path, precision, mode):
+    """The plan without bins (tasks in input order, the plain kernel popping tiles
+    from the context's counter), forced through a tune cache entry for the call's
+    shape class: same outputs as the oracle, on ragged reads and on one length."""
+    import math
+    for seed, lens in ((61, (1, 150)), (62, (100, 100))):
+        b = wl.random_small_batch(seed, n_reads=400, read_len=lens, band=16, ref_len=(500, 3000))
+        exp, _ = oracle_align(b, mode=mode)
+        n_tasks = b.n_cals if precision == sw.PREC_INT16 else 2 * b.n_cals
+        key = "gfx950/{}{}/L150/b16/t{}".format("int16" if precision == sw.PREC_INT16 else "int32",
+                                              "-final-row" if mode == sw.MODE_FINAL_ROW else "",
+                                              int(math.floor(math.log2(n_tasks))))
+        cache = tmp_path / f"tune{seed}.json"
+        cache.write_text('{\n  "%s": {"unbinned": 1, "bin_width": 4, "descending": 1, "strip_cap": 0, '
+                         '"strip_slack": 0, "grid_quarters": 4, "ms": 1.0}\n}\n' % key)
+        ctx = sw.Context(b.n_reads, b.n_cals, tune_cache=str(cache))
+        refs, db, out = _prepare(b)
+        for rnd in range(2):  # capture, then replay
+            out.score.fill_(-7)
+            ctx.align(db, refs, scoring_for(b, precision, max_read_len=150, mode=mode), out)
+            plan = ctx.last_plan()
+            assert "unbinned" in plan and "tuned=cached" in plan, plan
+            assert_same(_host(out), exp, f"seed {seed} round {rnd} {plan}", keys=SLOTS)
+        ctx.close()
