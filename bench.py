@@ -106,6 +106,13 @@ def load_issue(kernel: str, workload: str):
     return rec
 
 
+def profile_kernel(plan: str, int32: bool, final_row: bool) -> str:
+    """Name of the counter profiles of the kernel a batched plan runs: the plain
+    kernel where the tuner kept the plan without bins, else the queue kernel."""
+    kind = "plain" if "unbinned" in plan else "queue"
+    return f"inter{32 if int32 else 16}_{kind}" + ("_final_row" if final_row else "")
+
+
 def roofline(kernel: str, workload: str, cells: int, kern_ms: float, packed: bool) -> dict:
     """VALU-issue roofline of one scoring kernel.  `achieved` = VALU lane-instructions
     the kernel issues per second: its lane-instructions per cell, from the rocprofv3
@@ -404,11 +411,12 @@ class Leg:
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             gcups = self.cells / (ms * 1e-3) / 1e9
-            kern = "inter32_queue" if prec == sw.PREC_INT32 else "inter16_queue_final_row"
+            plan = self.ctx.last_plan()
+            kern = profile_kernel(plan, prec == sw.PREC_INT32, mode == sw.MODE_FINAL_ROW)
             res[name] = {"ms_per_step": round(ms, 3), "gcups": round(gcups, 1),
                          "roofline": roofline(kern, "chromosome_scale", self.cells, ms, prec != sw.PREC_INT32),
                          "peak_measured_tops": round(measured[name], 2),
-                         "plan": self.ctx.last_plan()}
+                         "plan": plan}
             if self.parity_reads:
                 res[name]["parity_sample_ok"] = parity_sample(self.batch, out,
                                                               final_row=mode == sw.MODE_FINAL_ROW)
@@ -863,8 +871,9 @@ def main():
     gcups = cells / (step_ms * 1e-3) / 1e9
     import paper_1805_00106_amd as sw
     measured = sw.alu_peak(16) / 1e12  # sustained packed-int16 add/max rate on this device
-    roof = roofline("inter16_queue", "chromosome_scale", cells, kern_ms, True)
-    roof["traffic"] = load_traffic("inter16_queue", "chromosome_scale")
+    kern_label = profile_kernel(r2["plan"], False, False)
+    roof = roofline(kern_label, "chromosome_scale", cells, kern_ms, True)
+    roof["traffic"] = load_traffic(kern_label, "chromosome_scale")
     roof["peak_measured_alu_tops"] = round(measured, 2)
     res = {
         "metric": METRIC, "value": round(gcups, 1), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
