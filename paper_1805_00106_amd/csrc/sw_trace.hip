@@ -820,13 +820,18 @@ __global__ __launch_bounds__(64) void k_trace_pair(const TraceInterArgs I, const
           hup = b.x;
           F = b.y;
         }
-        uint32_t Hd = hup_prev;
+        // the diagonal operand of row 0 (the row above, one column back)
+        uint32_t diag = padd(hup_prev, __builtin_amdgcn_perm(thi, tlo, sel[0]));
         hup_prev = hup;
         uint32_t word[G];
 #pragma unroll
         for (int x = 0; x < R; ++x) {
-          const uint32_t diag = padd(Hd, __builtin_amdgcn_perm(thi, tlo, sel[x]));
+          // the diagonal of row x+1 is row x's previous H: consume it before row x's
+          // new H takes its register (else every column ends rotating the H registers)
+          uint32_t dn = 0;
+          if (x + 1 < R) dn = padd(Hl[x], __builtin_amdgcn_perm(thi, tlo, sel[x + 1]));
           const uint32_t Ht = half_max3(diag, E[x], F);
+          diag = dn;
           const uint32_t nib = (Ht & 0x000C000Cu) | (E[x] & 0x00010001u) | (F & 0x00020002u);
           if ((x & 3) == 0)
             word[x >> 2] = nib;
@@ -835,7 +840,6 @@ __global__ __launch_bounds__(64) void k_trace_pair(const TraceInterArgs I, const
           const uint32_t Hc = Ht & 0xFFF0FFF0u;
           const uint32_t En = half_max3(padd(E[x] & 0xFFFEFFFEu, kee), padd(Hc, kue), Zn);
           F = half_max3(padd(F & 0xFFFDFFFDu, kfe), padd(Hc, kuf), Zj);
-          Hd = Hl[x];
           Hl[x] = Hc;
           E[x] = En;
         }
