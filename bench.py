@@ -882,7 +882,8 @@ def main():
         "config": {"workload": "chromosome scale: 100 Mbp reference (5% planted repeats), 1M x 100 bp reads, "
                                "Poisson(6)+1 CALs/read, band 32, both strands, int16",
                    "reads": n_reads, "cals": n_cals, "tasks": 2 * n_cals, "cells": cells,
-                   "path": "batched (length bins, persistent queue, HIP graph)", "plan": r2["plan"]},
+                   "path": "batched context (tuned plan: length bins or input order; tiles popped from a device queue; HIP graph)",
+                   "plan": r2["plan"]},
         "reads_per_s": round(n_reads / (step_ms * 1e-3), 1),
         "plain": {"gcups": r2["plain_gcups"], "ms_per_step": round(r2["plain_ms"], 3),
                   "reads_per_s": round(n_reads / (r2["plain_ms"] * 1e-3), 1),

@@ -1056,13 +1056,22 @@ __global__ void k_bin_count(const int32_t *__restrict__ cal_read, const int32_t 
     if (hist[i]) atomicAdd(&bin_count[i], hist[i]);
 }
 
-// One thread: bin order, bin offsets, tile offsets, strip height per bin, and
-// the queue reset.
+// Bin order, bin offsets, tile offsets, strip height per bin, and the queue
+// reset.  The block stages the bin counts in LDS and computes each bin's strip
+// height in parallel; one thread then runs the prefix sums over LDS (a serial
+// loop over global loads would pay a load latency per bin).
 __global__ void k_bin_plan(const int32_t *__restrict__ bin_count, int32_t *__restrict__ bin_off,
                            int32_t *__restrict__ bin_cursor, int32_t *__restrict__ tile_off,
                            int32_t *__restrict__ tile_bin, int32_t *__restrict__ strip_of_bin,
                            int32_t *__restrict__ n_tiles, int32_t *__restrict__ queue, const BinParams P) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  extern __shared__ int32_t cnt[];  // [nb + 1]
+  if (blockIdx.x != 0) return;
+  for (int b = threadIdx.x; b <= P.nb; b += blockDim.x) {
+    cnt[b] = bin_count[b];
+    strip_of_bin[b] = b < P.nb ? bin_strip_height(P, min((b + 1) * P.bin_width, P.max_read_len)) : P.strips[0];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   int32_t pos = 0, tiles = 0;
   for (int k = 0; k <= P.nb; ++k) {
     const int b = k == P.nb ? P.nb : (P.descending ? P.nb - 1 - k : k);
@@ -1070,10 +1079,9 @@ __global__ void k_bin_plan(const int32_t *__restrict__ bin_count, int32_t *__res
     bin_cursor[b] = pos;
     tile_off[k] = tiles;
     tile_bin[k] = b;
-    const int32_t cnt = bin_count[b];
-    pos += cnt;
-    tiles += (cnt + 63) / 64;
-    strip_of_bin[b] = b < P.nb ? bin_strip_height(P, min((b + 1) * P.bin_width, P.max_read_len)) : P.strips[0];
+    const int32_t c = cnt[b];
+    pos += c;
+    tiles += (c + 63) / 64;
   }
   tile_off[P.nb + 1] = tiles;
   *n_tiles = tiles;
@@ -1200,8 +1208,8 @@ hipError_t launch_batch_plan(const BatchBufs &B, const int32_t *read_len, int32_
   const int grid = (int)std::min<int64_t>(1024, blocks_for(n_tasks, 256));
   hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), nbins * sizeof(int32_t), st, B.cal_read, read_len,
                      n_reads, n_tasks, B.bin_count, P);
-  hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, st, B.bin_count, B.bin_off, B.bin_cursor, B.tile_off,
-                     B.tile_bin, B.strip_of_bin, B.n_tiles, B.queue, P);
+  hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(256), nbins * sizeof(int32_t), st, B.bin_count, B.bin_off,
+                     B.bin_cursor, B.tile_off, B.tile_bin, B.strip_of_bin, B.n_tiles, B.queue, P);
   hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 2 * nbins * sizeof(int32_t), st, B.cal_read, read_len,
                      n_reads, n_tasks, B.bin_cursor, B.order, P);
   const int64_t max_tiles = (n_tasks + 63) / 64 + nbins;
