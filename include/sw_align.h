@@ -163,14 +163,16 @@ int sw_align_batch(const uint32_t *reads2bit, const int64_t *read_word_off, cons
  * sw_align_batch without a workspace argument and without any allocation, for
  * callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  The same kernels and
- * outputs as sw_align_batch; its scratch (the owner-read array and the strip
- * scratch, sw_workspace_bytes(n_reads, n_cals, sc) bytes) lives in one static
+ * outputs as sw_align_batch; its scratch (the owner-read array, the strip
+ * scratch and a tile counter, sw_workspace_bytes(n_reads, n_cals, sc) bytes) lives in one static
  * device array of SW_NOALLOC_SCRATCH_BYTES per device, which the library holds
  * from load until the process ends.  A call whose scratch would exceed it
  * returns SW_ERR_WORKSPACE.  Every call on a device shares that device's array:
  * calls that overlap on one device (other streams, other host threads) race and
  * must be serialised by the caller.  The first call on a device looks up the
- * array's device address (no allocation); nothing in it needs clearing.
+ * array's device address (no allocation).  Each call clears the tile counter
+ * itself, with a fill kernel on `stream` (not a memset); nothing else in the
+ * array needs clearing.
  */
 #define SW_NOALLOC_SCRATCH_BYTES (128u << 20)
 int sw_align_batch_noalloc(const uint32_t *reads2bit, const int64_t *read_word_off, const int32_t *read_len,

@@ -412,7 +412,7 @@ int sw_align_batch_noalloc(const uint32_t *reads2bit, const int64_t *read_word_o
   PlainPlan plan;
   rc = make_plan(n_cals, sc, 0, &plan);
   if (rc) return rc;
-  // the plan's owner-read array and strip scratch must fit the static array
+  // the plan's owner-read array, strip scratch and tile counter must fit the static array
   if (plan.bytes > (size_t)SW_NOALLOC_SCRATCH_BYTES) return SW_ERR_WORKSPACE;
   void *ws = nullptr;
   rc = noalloc_scratch(&ws);
