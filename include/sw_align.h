@@ -370,9 +370,13 @@ int sw_classify(const int32_t *best_score, int32_t n_reads, int32_t n_refs, int3
 /*
  * A context holds device buffers sized once for a batch capacity, an autotuned
  * launch plan and captured HIP graphs.  sw_align_batch_ctx has the semantics of
- * sw_align_batch (bit-identical outputs) but bins tasks by read length and
- * window width, feeds a persistent kernel from a device work queue ordered
- * longest-first, and replays a captured graph when the shape repeats.
+ * sw_align_batch (bit-identical outputs).  Its plan either bins the tasks by
+ * read length (bin width, longest or shortest first, a strip height per bin)
+ * and feeds a persistent kernel from a device work queue of tiles, or keeps
+ * the tasks in input order, with one strip height, when that times faster (all
+ * reads of one length); the plan is timed on the caller's inputs on first use
+ * of a shape class (precision, mode, read-length bound, band, power of two of
+ * the task count), and a captured graph is replayed when the shape repeats.
  * A context is not thread-safe: use one per host thread.
  */
 typedef struct sw_ctx sw_ctx_t;
