@@ -737,21 +737,29 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
         th.start()
         th.join()
         lat = np.zeros(per_load)
+        admit = np.zeros(per_load)                     # submission to admission (arena space)
         done_last = 0.0
         for i, h in enumerate(handles):
             srv.wait(h)
-            _, _, _, t_done = srv.info(h)
+            _, t_sub, t_adm, t_done = srv.info(h)
             lat[i] = t_done - (start + arrivals[i])
+            admit[i] = t_adm - t_sub
             done_last = max(done_last, t_done)
             srv.release(h)
             same_in_every_mix &= all(np.array_equal(x, y) for x, y in zip(
                 (h.score, h.ref_end, h.read_end, h.best_score, h.best_slot, h.n_tied), first[int(picks[i])]))
         keep = lat[per_load // 10:]                    # 10% warm-up dropped
+        sizes = np.array([pool[int(k)].n_reads for k in picks])[per_load // 10:]
+        small, large = keep[sizes <= 100], keep[sizes >= 1000]
         span = done_last - start
         results.append({"load": load, "offered_requests_per_s": round(rate, 1), "requests": per_load,
                         "p50_ms": round(float(np.percentile(keep, 50)) * 1e3, 3),
                         "p99_ms": round(float(np.percentile(keep, 99)) * 1e3, 3),
                         "mean_ms": round(float(keep.mean()) * 1e3, 3),
+                        # by request size (reads): how much of the latency is queueing behind larger requests
+                        "p50_ms_upto_100_reads": round(float(np.percentile(small, 50)) * 1e3, 3) if len(small) else None,
+                        "p50_ms_from_1000_reads": round(float(np.percentile(large, 50)) * 1e3, 3) if len(large) else None,
+                        "mean_admission_wait_ms": round(float(admit[per_load // 10:].mean()) * 1e3, 3),
                         "achieved_reads_per_s": round(sum(pool[k].n_reads for k in picks) / span, 1),
                         "achieved_gcups": round(sum(pool_cells[k] for k in picks) / span / 1e9, 1)})
         progress(f"served: load {load}: p50 {results[-1]['p50_ms']} ms, p99 {results[-1]['p99_ms']} ms")
