@@ -643,7 +643,7 @@ def sat_reads_of(pool, rounds, dt):
 
 
 def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9), step_cals: int = 1 << 20,
-               parity_requests: int = 24):
+               parity_requests: int = 24, depth: int = 0):
     """Served requests: two resident references, Poisson arrivals of log-uniform request
     sizes, p50/p99 latency (scheduled arrival -> completion) at three loads
     relative to the measured saturated throughput."""
@@ -666,7 +666,8 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
     t_gen = time.perf_counter() - t_gen
     progress(f"served: references resident, pool of {pool_size} requests drawn ({t_gen:.0f} s)")
     sc = sw.Scoring.make(2, -3, 5, 2, 32, sw.PREC_AUTO, max_read_len=250)
-    srv = sw.Server(sc, memory_budget=4 << 30, max_step_reads=65536, max_step_cals=step_cals, max_step_chunks=1024)
+    srv = sw.Server(sc, memory_budget=4 << 30, max_step_reads=65536, max_step_cals=step_cals, max_step_chunks=1024,
+                    max_steps_in_flight=depth)
     srv.set_refs(rs)
 
     # saturated throughput: the whole pool queued at once
@@ -771,10 +772,10 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
                         "L U{75..250}, CALs U{1..32} per read, band 32, both strands",
             "saturated": {"reads_per_s": round(sat_reads, 1), "gcups": round(sat_gcups, 1),
                           "requests_per_s": round(rounds * pool_size / dt, 1)},
-            "mean_request_reads": round(mean_reads, 1), "loads": results, "steps": stats["steps"],
+            "mean_request_reads": round(mean_reads, 1), "loads": results, "steps": stats["steps"], "steps_launched_early": stats["steps_launched_early"],
             "parity_sample_ok": bool(parity_ok), "parity_requests": len(sample),
             "same_result_in_every_mix": bool(same_in_every_mix),
-            "max_step_cals": step_cals,
+            "max_step_cals": step_cals, "max_steps_in_flight": depth or "adaptive",
             "gen_s": round(t_gen, 1)}
 
 
@@ -798,6 +799,7 @@ def main():
                     help="reference size scale of the served leg (1.0 = 3.2 + 2.7 Gbp; 0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=300)
     ap.add_argument("--serve-step-cals", type=int, default=1 << 20, help="CALs per device step of the server")
+    ap.add_argument("--serve-depth", type=int, default=0, help="steps the server keeps queued on the device (0: adaptive, its default)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pipeline", type=int, default=1, help="1: also time seeds -> CALs -> filter -> score")
@@ -871,7 +873,7 @@ def main():
     c4 = classification_leg(args.two_ref_reads, parity=not args.no_parity) if args.two_ref_reads else None
     progress("two references done")
     served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests,
-                        step_cals=args.serve_step_cals) if args.serve_scale > 0 else None
+                        step_cals=args.serve_step_cals, depth=args.serve_depth) if args.serve_scale > 0 else None
     if served:
         progress("served done")
 

@@ -435,6 +435,14 @@ typedef struct {
   int64_t max_step_cals;    /* CALs per device step; also the most CALs of one read */
   int32_t max_step_chunks;  /* request chunks per step, 1..4096 */
   int32_t autotune;         /* 1: autotune the binning plan of each step shape class */
+  int32_t max_steps_in_flight; /* 1..3: at most that many steps queued on the device.
+                                  0 (adaptive): one, and the next is launched early,
+                                  once the running step is predicted to end within the
+                                  host time of a launch (a fit of step time against DP
+                                  cells over recent steps).  Under load a request waits
+                                  for every step queued ahead of its own, so one step
+                                  in flight gives the lowest latency; launching the next
+                                  early keeps the device busy while the host builds it */
 } sw_server_opts_t;
 
 typedef struct {
@@ -442,6 +450,7 @@ typedef struct {
   int64_t pending;                      /* submitted, not yet admitted */
   int64_t in_flight_requests;           /* admitted, not yet done */
   int64_t arena_used, arena_size;       /* bytes */
+  int64_t steps_launched_early;         /* adaptive rule: steps queued behind a running one */
 } sw_server_stats_t;
 
 int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out);

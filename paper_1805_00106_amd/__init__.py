@@ -69,13 +69,15 @@ class _FindOpts(ctypes.Structure):
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("scoring", Scoring), ("memory_budget", ctypes.c_size_t),
                 ("max_step_reads", ctypes.c_int32), ("max_step_cals", ctypes.c_int64),
-                ("max_step_chunks", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("max_step_chunks", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("max_steps_in_flight", ctypes.c_int32)]
 
 
 class _ServerStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("step_reads", ctypes.c_int64), ("step_cals", ctypes.c_int64),
                 ("pending", ctypes.c_int64), ("in_flight_requests", ctypes.c_int64),
-                ("arena_used", ctypes.c_int64), ("arena_size", ctypes.c_int64)]
+                ("arena_used", ctypes.c_int64), ("arena_size", ctypes.c_int64),
+                ("steps_launched_early", ctypes.c_int64)]
 
 
 class _CtxOpts(ctypes.Structure):
@@ -577,10 +579,11 @@ class Server:
     admitted requests, per-request timestamps."""
 
     def __init__(self, scoring: Scoring, memory_budget: int = 1 << 30, max_step_reads: int = 65536,
-                 max_step_cals: int = 1 << 20, max_step_chunks: int = 512, device: int = 0, autotune: bool = False):
+                 max_step_cals: int = 1 << 20, max_step_chunks: int = 512, device: int = 0, autotune: bool = False,
+                 max_steps_in_flight: int = 0):
         self._h = ctypes.c_void_p()
         opts = _ServerOpts(device, scoring, memory_budget, max_step_reads, max_step_cals, max_step_chunks,
-                           int(autotune))
+                           int(autotune), max_steps_in_flight)
         _check(lib().sw_server_create(ctypes.byref(opts), ctypes.byref(self._h)), "sw_server_create")
         self.n_refs = 0
         self.requests = {}

@@ -155,6 +155,9 @@ struct StepSlot {  // device buffers of one step (the slots are used in turn)
   void *small_ws = nullptr;  // workspace of the plain call that small steps use
   size_t small_ws_bytes = 0;
   bool busy = false;
+  bool small = false;     // took the plain call
+  double t_launch = 0;    // host time its launch began
+  double cells = 0;       // DP cells of its tasks (both strands), for the step-time model
   int error = 0;  // error of the step's library calls, passed to its requests
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> parts;  // request and reads placed
   std::vector<int64_t> part_r0;                                      // first read of each part
@@ -183,6 +186,42 @@ StepHeader header_layout(int64_t n_reads, int64_t n_chunks) {
 }
 
 constexpr int kSlots = 3;
+
+// Device time of a step against its DP cells, t = a + b * cells, fitted by least
+// squares over the steps seen so far with older steps weighted down by 0.9 per
+// step (the request mix drifts).  When the cells hardly vary (every step full)
+// the fit falls back to t = b * cells.
+class StepModel {
+ public:
+  void add(double x, double y) {
+    const double f = 0.9;
+    s0_ = f * s0_ + 1;
+    sx_ = f * sx_ + x;
+    sy_ = f * sy_ + y;
+    sxx_ = f * sxx_ + x * x;
+    sxy_ = f * sxy_ + x * y;
+    ++n_;
+  }
+  bool predict(double x, double *y) const {
+    if (n_ < 4 || sx_ <= 0) return false;
+    const double d = s0_ * sxx_ - sx_ * sx_;
+    double b = sy_ / sx_, a = 0;
+    if (d > 1e-6 * s0_ * sxx_) {
+      const double bl = (s0_ * sxy_ - sx_ * sy_) / d;
+      const double al = (sy_ - bl * sx_) / s0_;
+      if (bl > 0 && al >= 0) {
+        b = bl;
+        a = al;
+      }
+    }
+    *y = a + b * x;
+    return true;
+  }
+
+ private:
+  double s0_ = 0, sx_ = 0, sy_ = 0, sxx_ = 0, sxy_ = 0;
+  int64_t n_ = 0;
+};
 
 }  // namespace
 
@@ -215,7 +254,12 @@ struct sw_server {
   std::atomic<bool> stop{false};
   int64_t next_id = 1;
   int last_error = 0;
-  int64_t steps = 0, step_reads = 0, step_cals = 0;
+  int64_t steps = 0, step_reads = 0, step_cals = 0, steps_early = 0;
+  // adaptive launch (max_steps_in_flight 0): one step runs, and the next is
+  // launched once the running one is predicted to end within a launch's host time
+  StepModel model[2];     // batched and small (plain-call) steps
+  double t_gpu_free = 0;  // host time the last retired step was seen done
+  double lead_s = 3e-4;   // host time of a step launch (running mean) plus a margin
 };
 
 namespace {
@@ -256,17 +300,30 @@ T *hptr(sw_server *s, const Request &r, size_t field) {
 // to 2 bits per base (16 bases per word, first base least significant), each
 // read from its own code offset into the words from r.wptr[i] on: back to back,
 // whatever the caller's layout.
+// Eight base codes (one byte each, low 2 bits used) to 16 bits, base k at bits
+// 2k: adjacent fields are merged pairwise in three shift-or steps.
+inline uint32_t pack8(const uint8_t *q) {
+  uint64_t x;
+  std::memcpy(&x, q, 8);
+  x &= 0x0303030303030303ull;
+  x = (x | (x >> 6)) & 0x000F000F000F000Full;
+  x = (x | (x >> 12)) & 0x000000FF000000FFull;
+  return (uint32_t)((x | (x >> 24)) & 0xFFFFu);
+}
+
 void stage_inputs(sw_server *s, Request &r, const uint8_t *codes, const int64_t *code_off, const int64_t *cal_pos,
                   const int16_t *cal_ref, const uint8_t *strand) {
   uint32_t *words = hptr<uint32_t>(s, r, r.lay.words);
   for (int32_t i = 0; i < r.n_reads; ++i) {
     const uint8_t *q = codes + code_off[i];
     const int32_t L = r.len[i];
-    for (int64_t w = 0; w < r.wptr[i + 1] - r.wptr[i]; ++w) {
-      const int nb = (int)std::min<int64_t>(16, L - 16 * w);
+    uint32_t *out = words + r.wptr[i];
+    int32_t b = 0;
+    for (; b + 16 <= L; b += 16) *out++ = pack8(q + b) | pack8(q + b + 8) << 16;
+    if (b < L) {  // the last, partial word
       uint32_t v = 0;
-      for (int k = 0; k < nb; ++k) v |= (uint32_t)(q[16 * w + k] & 3u) << (2 * k);
-      words[r.wptr[i] + w] = v;
+      for (int k = 0; b + k < L; ++k) v |= (uint32_t)(q[b + k] & 3u) << (2 * k);
+      *out = v;
     }
   }
   if (r.n_cals > 0) {
@@ -299,10 +356,29 @@ bool admit(sw_server *s, std::shared_ptr<Request> &rq) {
   return true;
 }
 
+// Whether another step may be launched now.  A fixed depth allows that many
+// steps queued on the device.  The adaptive rule keeps one: a request that
+// arrives while a step runs joins the step launched next, so a queued step would
+// add its whole run to that request's wait.  But the next step's host work
+// (building its header, a dozen launches) would then leave the device idle
+// between steps, so it is launched early, once the running step's predicted end
+// is within that host time.
+bool may_launch(const sw_server *s, double now) {
+  const int n = (int)s->in_flight.size();
+  if (s->opts.max_steps_in_flight > 0) return n < s->opts.max_steps_in_flight;
+  if (n == 0) return true;
+  if (n > 1) return false;
+  const StepSlot &run = *s->in_flight.front();
+  double dur = 0;
+  if (!s->model[run.small].predict(run.cells, &dur)) return false;
+  return now >= std::max(run.t_launch, s->t_gpu_free) + dur - s->lead_s;
+}
+
 // Build and launch one step from the admitted requests (scheduler thread, lock held).
 bool launch_step(sw_server *s) {
   StepSlot &st = s->slots[s->next_slot];
-  if (st.busy || s->admitted.empty()) return false;
+  const double t_begin = now_s();
+  if (st.busy || s->admitted.empty() || !may_launch(s, t_begin)) return false;
   const int64_t max_reads = s->opts.max_step_reads, max_cals = s->opts.max_step_cals;
   const int64_t max_words = max_reads * ((s->mode.max_read_len + 15) / 16);
   // pass 1: which reads of which requests go into the step
@@ -341,6 +417,8 @@ bool launch_step(sw_server *s) {
   int64_t *h_cp = reinterpret_cast<int64_t *>(st.hdr_host + H.cal_ptr);
   swk::ServeChunk *h_ch = reinterpret_cast<swk::ServeChunk *>(st.hdr_host + H.chunks);
   int64_t sr = 0, sc = 0, sw = 0;
+  double cells = 0;
+  const double band2 = 2.0 * s->sc.band;
   for (int k = 0; k < nch; ++k) {
     Request &r = *st.parts[k].first;
     const int64_t r0 = st.part_r0[k], r1 = r0 + st.parts[k].second;
@@ -349,6 +427,7 @@ bool launch_step(sw_server *s) {
       h_len[sr + (i - r0)] = r.len[i];
       h_wo[sr + (i - r0)] = sw + (r.wptr[i] - w0);
       h_cp[sr + (i - r0)] = sc + (r.cal_ptr[i] - c0);
+      cells += 2.0 * (double)(r.cal_ptr[i + 1] - r.cal_ptr[i]) * r.len[i] * (r.len[i] + band2);
     }
     swk::ServeChunk &c = h_ch[k];
     c.words = dptr<uint32_t>(s, r, r.lay.words) + w0;
@@ -381,7 +460,10 @@ bool launch_step(sw_server *s) {
   hipError_t he = hipMemcpyAsync(st.hdr_dev, st.hdr_host, H.bytes, hipMemcpyHostToDevice, cs);
   if (he == hipSuccess) he = swk::launch_serve_gather(d_ch, nch, nw, nc, st.words, st.cal_pos, st.cal_ref, st.strand, cs);
   int rc = he == hipSuccess ? SW_OK : swapi::hip_fail(he);
-  if (rc == SW_OK && nc > 0 && nc <= s->small_step_cals) {
+  st.small = nc > 0 && nc <= s->small_step_cals;
+  st.cells = cells;
+  st.t_launch = t_begin;
+  if (rc == SW_OK && st.small) {
     // a small step: the plain call, whose AUTO kernel choice runs one wavefront
     // per task (a lane working through a whole long read alone would set the
     // latency); the outputs are the same
@@ -403,12 +485,14 @@ bool launch_step(sw_server *s) {
     swk::launch_serve_scatter(d_ch, nch, nr, nc, s->n_refs, st.score, st.ref_end, st.read_end, st.best_score,
                               st.best_slot, st.n_tied, cs);
   hipEventRecord(st.done, cs);
+  if (!s->in_flight.empty()) s->steps_early++;
   st.busy = true;
   s->in_flight.push_back(&st);
   s->next_slot = (s->next_slot + 1) % kSlots;
   s->steps++;
   s->step_reads += nr;
   s->step_cals += nc;
+  s->lead_s = 0.8 * s->lead_s + 0.2 * (now_s() - t_begin + 1e-4);  // 0.1 ms margin (polling, jitter)
   return true;
 }
 
@@ -417,9 +501,16 @@ bool launch_step(sw_server *s) {
 // goes to the finisher thread, so the scheduler keeps launching steps.
 void retire_steps(sw_server *s) {
   // steps retire in launch order (a request's chunks complete in order)
+  int n_retired = 0;
   while (!s->in_flight.empty() && hipEventQuery(s->in_flight.front()->done) == hipSuccess) {
     StepSlot &st = *s->in_flight.front();
     s->in_flight.pop_front();
+    // device time as seen from here: from its launch, or from the end of the step
+    // ahead of it, to now (a second step found done in the same pass has no
+    // separate end, and gives no sample)
+    const double t = now_s();
+    if (n_retired++ == 0 && st.cells > 0) s->model[st.small].add(st.cells, t - std::max(st.t_launch, s->t_gpu_free));
+    s->t_gpu_free = t;
     for (auto &p : st.parts) {
       Request &r = *p.first;
       r.reads_done += p.second;
@@ -512,7 +603,8 @@ int sw_server_create(const sw_server_opts_t *opts, sw_server_t **out) {
   int rc = swapi::validate_scoring(&opts->scoring, &m);
   if (rc) return rc;
   if (opts->memory_budget < (1 << 20) || opts->max_step_reads < 1 || opts->max_step_cals < 1 ||
-      opts->max_step_chunks < 1 || opts->max_step_chunks > 4096)
+      opts->max_step_chunks < 1 || opts->max_step_chunks > 4096 || opts->max_steps_in_flight < 0 ||
+      opts->max_steps_in_flight > kSlots)
     return SW_ERR_INVALID_ARG;
   hipError_t e = hipSetDevice(opts->device);
   if (e != hipSuccess) return swapi::hip_fail(e);
@@ -747,6 +839,7 @@ int sw_server_stats(sw_server_t *s, sw_server_stats_t *out) {
   out->in_flight_requests = (int64_t)s->admitted.size();
   out->arena_used = (int64_t)s->arena->used();
   out->arena_size = (int64_t)s->arena->size();
+  out->steps_launched_early = s->steps_early;
   return s->last_error ? s->last_error : SW_OK;
 }
 

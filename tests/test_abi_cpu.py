@@ -214,3 +214,16 @@ def test_binding_rejects_malformed_tensors(sw):
                         torch.zeros(3, dtype=torch.uint8))
     with pytest.raises(ValueError):
         sw._check_batch(db)
+
+
+@pytest.mark.parametrize("field,value", [("max_steps_in_flight", -1), ("max_steps_in_flight", 4),
+                                         ("max_step_chunks", 0), ("max_step_chunks", 4097),
+                                         ("max_step_reads", 0), ("memory_budget", 1 << 19)])
+def test_server_create_rejects_bad_options(sw, field, value):
+    """The server's options are checked before any device call."""
+    sc = sw.Scoring.make(2, -3, 5, 2, 8, sw.PREC_AUTO, max_read_len=128)
+    opts = sw._ServerOpts(0, sc, 1 << 24, 1024, 1 << 16, 64, 0, 0)
+    setattr(opts, field, value)
+    h = ctypes.c_void_p()
+    assert sw.lib().sw_server_create(ctypes.byref(opts), ctypes.byref(h)) == -1  # SW_ERR_INVALID_ARG
+    assert not h.value

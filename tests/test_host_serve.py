@@ -70,6 +70,13 @@ def test_served_routing_under_asan(asan_exe, seed, layout):
     assert "submit errors 0, failed 0" in out
 
 
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_served_routing_steps_in_flight(asan_exe, depth):
+    """Fixed numbers of steps in flight (the default, 0, is the adaptive rule)."""
+    out = _run(asan_exe, 3, 4, 60, 2, 0, depth)
+    assert "submit errors 0, failed 0" in out
+
+
 def test_served_routing_at_benchmark_scale(asan_exe):
     """The served benchmark's step sizes (1024 chunks, 65536 reads and 1 M CALs per
     step) and request sizes (1..10000 reads of up to 250 bases, up to 32 CALs)."""
