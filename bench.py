@@ -725,6 +725,7 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
         arrivals = np.cumsum(g.exponential(1.0 / rate, per_load))
         picks = g.integers(0, pool_size, per_load)
         handles = [srv.prepare_batch(pool[k]) for k in picks]   # outputs allocated before the clock starts
+        st0 = srv.stats()
         start = time.monotonic() + 0.05
 
         def feeder():
@@ -749,6 +750,8 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
             srv.release(h)
             same_in_every_mix &= all(np.array_equal(x, y) for x, y in zip(
                 (h.score, h.ref_end, h.read_end, h.best_score, h.best_slot, h.n_tied), first[int(picks[i])]))
+        st1 = srv.stats()
+        n_steps = st1["steps"] - st0["steps"]
         keep = lat[per_load // 10:]                    # 10% warm-up dropped
         sizes = np.array([pool[int(k)].n_reads for k in picks])[per_load // 10:]
         small, large = keep[sizes <= 100], keep[sizes >= 1000]
@@ -761,6 +764,10 @@ def served_leg(scale: float, pool_size: int, per_load: int, loads=(0.3, 0.6, 0.9
                         "p50_ms_upto_100_reads": round(float(np.percentile(small, 50)) * 1e3, 3) if len(small) else None,
                         "p50_ms_from_1000_reads": round(float(np.percentile(large, 50)) * 1e3, 3) if len(large) else None,
                         "mean_admission_wait_ms": round(float(admit[per_load // 10:].mean()) * 1e3, 3),
+                        # device steps of the phase and their mean size
+                        "steps": n_steps, "steps_launched_early": st1["steps_launched_early"] - st0["steps_launched_early"],
+                        "mean_step_reads": round((st1["step_reads"] - st0["step_reads"]) / max(n_steps, 1), 1),
+                        "phase_ms_per_step": round(span * 1e3 / max(n_steps, 1), 3),
                         "achieved_reads_per_s": round(sum(pool[k].n_reads for k in picks) / span, 1),
                         "achieved_gcups": round(sum(pool_cells[k] for k in picks) / span / 1e9, 1)})
         progress(f"served: load {load}: p50 {results[-1]['p50_ms']} ms, p99 {results[-1]['p99_ms']} ms")
