@@ -36,10 +36,11 @@ def requests(n, seed0, sizes=None):
     return [wl.served_request(refs, s, seed0 * 1000 + k, ref_pack=pack) for k, s in enumerate(sizes)]
 
 
-def make_server(budget=256 << 20, max_step_reads=4096, max_step_cals=60000):
+def make_server(budget=256 << 20, max_step_reads=4096, max_step_cals=60000, depth=0):
     refs, pack = refs_and_pack()
     sc = sw.Scoring.make(2, -3, 5, 2, 32, sw.PREC_AUTO, max_read_len=250)
-    srv = sw.Server(sc, memory_budget=budget, max_step_reads=max_step_reads, max_step_cals=max_step_cals)
+    srv = sw.Server(sc, memory_budget=budget, max_step_reads=max_step_reads, max_step_cals=max_step_cals,
+                    max_steps_in_flight=depth)
     rs = sw.RefSet.from_codes(torch.from_numpy(pack[0]).cuda(), pack[1], pack[2])
     torch.cuda.synchronize()
     srv.set_refs(rs)
@@ -100,6 +101,33 @@ def test_alone_equals_in_the_mix():
             np.testing.assert_array_equal(x, y, err_msg=f"request {k}")
     # requests shared steps: fewer steps than requests in the mixed phase
     assert stats["steps"] - steps_alone < len(reqs), (stats["steps"], steps_alone)
+    srv.close()
+
+
+@pytest.mark.parametrize("depth", [1, 3])
+def test_fixed_steps_in_flight_match_oracle(depth):
+    """Fixed step depths (the other tests run the adaptive default): requests
+    from two threads share steps, and each matches the oracle."""
+    reqs = requests(10, 7)
+    srv, rs = make_server(max_step_reads=1500, max_step_cals=20000, depth=depth)
+    prepared = [srv.prepare_batch(b) for b in reqs]
+
+    def feeder(idx):
+        for k in idx:
+            srv.submit_prepared(prepared[k])
+
+    th = [threading.Thread(target=feeder, args=(list(range(i, len(reqs), 2)),)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for h in prepared:
+        assert srv.wait(h, 60000)
+    for k, (b, h) in enumerate(zip(reqs, prepared)):
+        s, r, e, _ = orc.align_batch(b, n_threads=8)
+        bs, bl, nt = orc.reduce_best(b.cal_ptr, b.cal_ref, b.n_reads, b.n_refs, s)
+        for x, y in zip(outputs(h), (s, r, e, bs.reshape(-1), bl.reshape(-1), nt.reshape(-1))):
+            np.testing.assert_array_equal(x, y, err_msg=f"request {k}, depth {depth}")
     srv.close()
 
 
