@@ -16,7 +16,7 @@ waits, arena blocks reused, requests split over steps, both scoring paths), with
 read layouts that are tight, gapped and shuffled, or arbitrary; and the served
 benchmark's own configuration is replayed (4 GiB budget, 1024 chunks, 65536
 reads and 1 M CALs per step, 3.2 and 2.7 Gbp references, a 300-request pool
-submitted three times from four client threads (the benchmark submits it eight
+submitted twice from four client threads (the benchmark submits it eight
 times; the number of rounds changes no code path), then three Poisson load phases
 with waits, timestamps and releases).  Every output must belong to its own
 request, read, CAL and strand.  Built with the host address and
@@ -85,9 +85,9 @@ def test_served_routing_at_benchmark_scale(asan_exe):
 
 
 def test_served_benchmark_configuration(asan_exe):
-    """The served benchmark's configuration end to end (load phases shortened to
-    200 requests each)."""
-    out = _run(asan_exe, "bench", 7, 300, 3, 200)
+    """The served benchmark's configuration end to end (the pool submitted twice,
+    load phases shortened to 120 requests each)."""
+    out = _run(asan_exe, "bench", 7, 300, 2, 120)
     assert "submit errors 0, failed 0" in out
 
 
