@@ -791,6 +791,16 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def guarded(name, fn):
+    """Run one secondary leg; a Python-level failure is reported in its place in
+    the JSON line (and on stderr) instead of losing the whole line."""
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001 - reported, not hidden
+        progress(f"{name} failed: {e!r}")
+        return {"error": repr(e)[:500]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -834,13 +844,13 @@ def main():
     parity = None if args.no_parity else parity_sample(batch, leg.out)
     leg.parity_reads = not args.no_parity
     e2e = leg.end_to_end()
-    variants = leg.variants() if args.variants else None
+    variants = guarded("variants", leg.variants) if args.variants else None
     progress("variants done")
-    trace = leg.traceback(parity_reads=0 if args.no_parity else 200)
+    trace = guarded("traceback", lambda: leg.traceback(parity_reads=0 if args.no_parity else 200))
     progress("traceback done")
-    pipe = leg.pipeline() if args.pipeline else None
+    pipe = guarded("seed-to-score", leg.pipeline) if args.pipeline else None
     progress("seed-to-score done")
-    small = small_batch_latency(batch)
+    small = guarded("small batch", lambda: small_batch_latency(batch))
     n_reads, n_cals, cells = leg.db.n_reads, leg.db.n_cals, leg.cells
     leg.free()
     del leg
@@ -853,17 +863,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    c3 = None
-    if args.uneven_reads:
+    def uneven_leg():
         base3 = wl.uneven_lengths(n_reads=args.uneven_reads, band=32)  # reads and CALs do not depend on the band
-        c3 = {}
+        out3 = {}
         for band in [int(x) for x in args.uneven_bands.split(",")]:
             b3 = dataclasses.replace(base3, scoring=dataclasses.replace(base3.scoring, band=band),
                                      name=f"uneven_lengths_band{band}")
             leg3 = Leg(b3, 250, max(3, args.steps // 4), 1)
             r3 = leg3.run()
             p3 = None if args.no_parity else parity_sample(b3, leg3.out)
-            c3[f"band{band}"] = {
+            out3[f"band{band}"] = {
                 "workload": f"uneven lengths: same 100 Mbp reference, {b3.n_reads} reads with L uniform 75..250, geometric CALs "
                             f"(mean 8, cap 64), band {band}, both strands, int16",
                 "cals": b3.n_cals, "cells": leg3.cells,
@@ -876,12 +885,17 @@ def main():
             leg3.free()
             del leg3
             progress(f"uneven lengths band {band}: batched {r3['batched_gcups']} GCUPS")
+        return out3
 
-    c4 = classification_leg(args.two_ref_reads, parity=not args.no_parity) if args.two_ref_reads else None
+    c3 = guarded("uneven lengths", uneven_leg) if args.uneven_reads else None
+
+    c4 = guarded("two references", lambda: classification_leg(args.two_ref_reads, parity=not args.no_parity)) \
+        if args.two_ref_reads else None
     progress("two references done")
-    served = served_leg(args.serve_scale, args.serve_pool, args.serve_requests,
-                        step_cals=args.serve_step_cals, depth=args.serve_depth) if args.serve_scale > 0 else None
-    if served:
+    served = guarded("served", lambda: served_leg(args.serve_scale, args.serve_pool, args.serve_requests,
+                                                  step_cals=args.serve_step_cals, depth=args.serve_depth)) \
+        if args.serve_scale > 0 else None
+    if served and "error" not in served:
         progress("served done")
 
     step_ms, kern_ms = r2["batched_ms"], r2["batched_kern_ms"]
@@ -909,7 +923,7 @@ def main():
         "small_batch_latency": small,
         "end_to_end_with_pcie": e2e,
         "variants": variants,
-        "small_reference": small_reference_leg() if args.variants else None,
+        "small_reference": guarded("small reference", small_reference_leg) if args.variants else None,
         "traceback": trace,
         "seed_to_score": pipe,
         "aligned_fraction": round(r2["aligned_fraction"], 4), "aligned_threshold": ALIGNED_THRESHOLD,
@@ -922,10 +936,11 @@ def main():
         res["two_references"] = c4
     if served:
         res["served"] = served
-        res["p50_ms"] = served["loads"][-1]["p50_ms"]
-        res["p99_ms"] = served["loads"][-1]["p99_ms"]
+        if "loads" in served:
+            res["p50_ms"] = served["loads"][-1]["p50_ms"]
+            res["p99_ms"] = served["loads"][-1]["p99_ms"]
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(batch)
+        res["cpu_baseline"] = guarded("cpu baseline", lambda: cpu_baseline(batch))
     print(json.dumps(res))
 
 
